@@ -1,0 +1,279 @@
+"""Plain binary64 Gibbs sampler for Beta-Process Factor Analysis (BPFA).
+
+Test infrastructure, not product code (see ``oracle/__init__.py``).
+
+The paper (section "Beta-Process Factor Analysis") names BPFA, its
+per-iteration dictionary-learning and sparse-coding steps and blind
+inpainting from the observed pixels only, and defers the model to the works
+it cites (Paisley & Carin, ICML 2009; Zhou et al., NIPS 2009).  The model
+written out here is the finite-K beta-process approximation of those works,
+with the likelihood restricted to observed pixels Obs(i) of each patch:
+
+    x_ip ~ N( sum_k d_kp z_ik s_ik , 1/gamma_eps )   for p in Obs(i)
+    d_k  ~ N(0, I_P / P)         s_ik ~ N(0, 1/gamma_s)
+    z_ik ~ Bernoulli(pi_k)       pi_k ~ Beta(a/K, b(K-1)/K)
+    gamma_s ~ Ga(c, d)           gamma_eps ~ Ga(e, f)        (shape, rate)
+
+State: D (K x P), W = Z * S (N x K, inactive weights are not instantiated),
+ell_k = logit pi_k, gamma_s, gamma_eps and the iteration number t.
+
+One iteration, in this order:
+  1. z/s sweep: every patch independently, atoms k = 0 .. K-1 in order, draws
+     z_ik from its conditional with s_ik integrated out, then s_ik given z_ik;
+  2. dictionary: atoms k = 0 .. K-1 in order, d_k from its Gaussian
+     conditional (skipped in sparse-coding-only iterations);
+  3. pi_k from its Beta conditional, as ell_k = ln G_A - ln G_B;
+  4. gamma_s; 5. gamma_eps (residual after step 2); 6. t <- t + 1.
+
+Random numbers come from oracle.philox under the stream contract described
+there; a GPU implementation that follows the same contract draws the same
+uniforms, so the two can be compared draw by draw.
+"""
+import dataclasses
+import math
+
+import numpy as np
+
+from . import gamma as _gamma
+from . import philox
+
+
+@dataclasses.dataclass
+class Params:
+    K: int
+    a: float = 1.0
+    b: float = 1.0
+    c: float = 1e-6
+    d: float = 1e-6
+    e: float = 1e-6
+    f: float = 1e-6
+    gamma_s0: float = 1.0
+    gamma_eps0: float = 100.0
+    seed: int = 0
+    problem_id: int = 0
+
+
+@dataclasses.dataclass
+class State:
+    D: np.ndarray          # K x P
+    W: np.ndarray          # N x K, z * s
+    Z: np.ndarray          # N x K, bool
+    ell: np.ndarray        # K, logit pi
+    gamma_s: float
+    gamma_eps: float
+    t: int
+
+    def copy(self):
+        return State(self.D.copy(), self.W.copy(), self.Z.copy(), self.ell.copy(),
+                     float(self.gamma_s), float(self.gamma_eps), int(self.t))
+
+
+@dataclasses.dataclass
+class SweepReport:
+    near_ties: int = 0          # follow mode: mismatches adopted as certified near-ties
+    hard_mismatches: int = 0    # follow mode: mismatches away from the threshold
+    tie_sites: list = dataclasses.field(default_factory=list)   # (i, k) of adopted ties
+    hard_sites: list = dataclasses.field(default_factory=list)
+
+
+# ---------------------------------------------------------------- draws ----
+
+def zs_uniforms(params, i, k, t):
+    """Sweep draws for patches i at atom k: (u_z, n).
+
+    Block (i, k // 2, t, ZS): word (k mod 2) is the z uniform of atom k; words
+    2 and 3 make one Box-Muller pair, cosine branch for the even atom of the
+    pair and sine branch for the odd one.
+    """
+    w = philox.block(params.seed, params.problem_id, philox.TAG_ZS, i, k // 2, t)
+    u_z = philox.uniform(w[k % 2])
+    n_cos, n_sin = philox.box_muller(philox.uniform(w[2]), philox.uniform(w[3]))
+    return u_z, (n_cos if k % 2 == 0 else n_sin)
+
+
+def dict_normal(params, p, k, t):
+    """Dictionary draw for positions p of atom k: cosine branch of block (p, k, t, DICT)."""
+    w = philox.block(params.seed, params.problem_id, philox.TAG_DICT, p, k, t)
+    return philox.box_muller(philox.uniform(w[0]), philox.uniform(w[1]))[0]
+
+
+def init_normal(params, p, k):
+    w = philox.block(params.seed, params.problem_id, philox.TAG_INIT, p, k, 0)
+    return philox.box_muller(philox.uniform(w[0]), philox.uniform(w[1]))[0]
+
+
+# ------------------------------------------------------ conditionals ----
+
+def z_log_odds(ell_k, gamma_s, gamma_eps, delta, rho):
+    """ln p(z=1|.) - ln p(z=0|.) with s_ik integrated out.
+
+    delta = sum_{Obs} d_kp^2, rho = sum_{Obs} d_kp e_p where e is the patch
+    residual with atom k's own contribution added back.  Integrating
+    N(s; 0, 1/gamma_s) against exp(-gamma_eps/2 |e - d s|^2) gives the factor
+    sqrt(gamma_s / lam) exp((gamma_eps rho)^2 / (2 lam)), lam = gamma_s + gamma_eps delta.
+    Returns (L, lam, q) with q the exponent term.
+    """
+    lam = gamma_s + gamma_eps * delta
+    q = (gamma_eps * rho) ** 2 / (2.0 * lam)
+    return ell_k + 0.5 * np.log(gamma_s / lam) + q, lam, q
+
+
+def s_posterior(gamma_s, gamma_eps, delta, rho):
+    """s_ik | z_ik = 1: Gaussian with precision lam and mean gamma_eps rho / lam."""
+    lam = gamma_s + gamma_eps * delta
+    return gamma_eps * rho / lam, lam
+
+
+def dict_conditional(P, gamma_eps, A, b):
+    """d_kp | rest: precision P + gamma_eps A, mean gamma_eps b / precision.
+
+    A = sum_i m_ip w_ik^2 and b = sum_i m_ip w_ik (x_ip - sum_{j != k} d_jp w_ij).
+    """
+    lam = P + gamma_eps * A
+    return gamma_eps * b / lam, lam
+
+
+def logit_uniform(u):
+    return np.log(u) - np.log1p(-u)
+
+
+# ------------------------------------------------------------- steps ----
+
+def init_state(params, N, P):
+    """Prior draw of D (d_kp = n / sqrt(P)), no active atoms, pi_k at its prior mean."""
+    K = params.K
+    p = np.arange(P, dtype=np.uint64)
+    D = np.stack([init_normal(params, p, k) for k in range(K)]) / math.sqrt(P)
+    ell0 = math.log(params.a / K) - math.log(params.b * (K - 1) / K) if K > 1 else 0.0
+    return State(D=D, W=np.zeros((N, K)), Z=np.zeros((N, K), dtype=bool),
+                 ell=np.full(K, ell0), gamma_s=float(params.gamma_s0),
+                 gamma_eps=float(params.gamma_eps0), t=1)
+
+
+def residual(X, Mk, D, W):
+    """r_ip = m_ip (x_ip - sum_k d_kp w_ik): zero at unobserved entries."""
+    return Mk * (X - W @ D)
+
+
+def sweep(params, X, Mk, st, follow_z=None, tie_tol=1e-4):
+    """Step 1: z/s sweep.  Patches are independent; atoms go in ascending order.
+
+    Follow mode (follow_z given): where the drawn z differs from follow_z at a
+    point whose log-odds lie within tie_tol * (1 + |ell_k| + |ln(gs/lam)|/2 + q)
+    of the uniform's logit, the follow value is adopted and the site recorded
+    as a near-tie; any other difference is recorded as a hard mismatch (and the
+    oracle keeps its own draw).
+    Returns (W, Z, residual after the sweep, report).
+    """
+    N, K = st.W.shape
+    W = st.W.copy()
+    Z = st.Z.copy()
+    R = residual(X, Mk, st.D, W)
+    Mf = Mk.astype(np.float64)
+    gs, ge = st.gamma_s, st.gamma_eps
+    rep = SweepReport()
+    ii = np.arange(N, dtype=np.uint64)
+    for k in range(K):
+        dk = st.D[k]
+        w_old = W[:, k]
+        delta = Mf @ (dk * dk)
+        rho = R @ dk + delta * w_old
+        L, lam, q = z_log_odds(st.ell[k], gs, ge, delta, rho)
+        u_z, n = zs_uniforms(params, ii, k, st.t)
+        lu = logit_uniform(u_z)
+        z = lu < L
+        if follow_z is not None:
+            fz = follow_z[:, k].astype(bool)
+            diff = np.nonzero(z != fz)[0]
+            if diff.size:
+                scale = 1.0 + abs(st.ell[k]) + np.abs(0.5 * np.log(gs / lam[diff])) + q[diff]
+                tie = np.abs(lu[diff] - L[diff]) <= tie_tol * scale
+                for i in diff[tie]:
+                    rep.tie_sites.append((int(i), k))
+                for i in diff[~tie]:
+                    rep.hard_sites.append((int(i), k))
+                rep.near_ties += int(tie.sum())
+                rep.hard_mismatches += int((~tie).sum())
+                z[diff[tie]] = fz[diff[tie]]
+        mean, lam_s = s_posterior(gs, ge, delta, rho)
+        w_new = np.where(z, mean + n / np.sqrt(lam_s), 0.0)
+        dw = w_new - w_old
+        rows = np.nonzero(dw)[0]
+        if rows.size:
+            R[rows] -= Mf[rows] * (dw[rows, None] * dk[None, :])
+        W[:, k] = w_new
+        Z[:, k] = z
+    return W, Z, R, rep
+
+
+def dictionary_update(params, Mk, st, W, R):
+    """Step 2: atoms in order; every position p of d_k from its conditional.
+
+    R is the residual of the current dictionary and W; both the returned D and
+    the residual reflect the new atoms.
+    """
+    K, P = st.D.shape
+    D = st.D.copy()
+    R = R.copy()
+    Mf = Mk.astype(np.float64)
+    ge = st.gamma_eps
+    pp = np.arange(P, dtype=np.uint64)
+    for k in range(K):
+        w = W[:, k]
+        rows = np.nonzero(w)[0]
+        mw = Mf[rows] * w[rows, None]                       # m_ip w_ik
+        A = (mw * w[rows, None]).sum(axis=0)
+        b = (mw * (R[rows] + D[k][None, :] * w[rows, None])).sum(axis=0)
+        mean, lam = dict_conditional(P, ge, A, b)
+        d_new = mean + dict_normal(params, pp, k, st.t) / np.sqrt(lam)
+        R[rows] -= mw * (d_new - D[k])[None, :]
+        D[k] = d_new
+    return D, R
+
+
+def pi_update(params, Z, t):
+    """Step 3: pi_k | Z ~ Beta(a/K + n_k, b(K-1)/K + N - n_k), kept as its logit."""
+    N, K = Z.shape
+    nk = Z.sum(axis=0)
+    ell = np.empty(K)
+    for k in range(K):
+        la = _gamma.log_gamma_draw(params.a / K + nk[k], params.seed, params.problem_id,
+                                   philox.TAG_PI_A, k, t)
+        lb = _gamma.log_gamma_draw(params.b * (K - 1) / K + N - nk[k], params.seed,
+                                   params.problem_id, philox.TAG_PI_B, k, t)
+        ell[k] = la - lb
+    return ell
+
+
+def gamma_s_update(params, Z, W, t):
+    """Step 4: gamma_s ~ Ga(c + sum(z)/2, d + sum(w^2)/2) over active weights."""
+    shape = params.c + 0.5 * float(Z.sum())
+    rate = params.d + 0.5 * float((W * W).sum())
+    lg = _gamma.log_gamma_draw(shape, params.seed, params.problem_id, philox.TAG_GS, 0, t)
+    return math.exp(lg) / rate
+
+
+def gamma_eps_update(params, Mk, R, t):
+    """Step 5: gamma_eps ~ Ga(e + |Obs|/2, f + sum_{Obs} r^2 / 2)."""
+    shape = params.e + 0.5 * float(Mk.sum())
+    rate = params.f + 0.5 * float((R * R).sum())
+    lg = _gamma.log_gamma_draw(shape, params.seed, params.problem_id, philox.TAG_GE, 0, t)
+    return math.exp(lg) / rate
+
+
+def iterate(params, X, Mk, st, learn_dict=True, follow_z=None, tie_tol=1e-4):
+    """One Gibbs iteration (steps 1-6).  Returns (new state, sweep report)."""
+    W, Z, R, rep = sweep(params, X, Mk, st, follow_z=follow_z, tie_tol=tie_tol)
+    D = st.D
+    if learn_dict:
+        D, R = dictionary_update(params, Mk, st, W, R)
+    ell = pi_update(params, Z, st.t)
+    gs = gamma_s_update(params, Z, W, st.t)
+    ge = gamma_eps_update(params, Mk, R, st.t)
+    return State(D=D, W=W, Z=Z, ell=ell, gamma_s=gs, gamma_eps=ge, t=st.t + 1), rep
+
+
+def reconstruct(st, shape, patch, stride):
+    """Overlap average of the patch models D^T w_i (last Gibbs sample)."""
+    from . import patches
+    return patches.overlap_average(st.W @ st.D, shape, patch, stride)
