@@ -1,0 +1,773 @@
+// Host runtime of libbpfa: the C ABI declared in include/bpfa.h.
+//
+// A handle owns (or borrows) one device workspace carved into the buffers of
+// internal.hpp, a stream, and host copies of the few sizes the launches need.
+// Iterations are launched without host synchronisation; the device keeps the
+// gammas, the iteration counter and an error flag, read back by the
+// synchronising calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bpfa.h"
+#include "internal.hpp"
+
+using namespace bpfa;
+
+namespace {
+
+thread_local std::string g_err;
+
+bpfa_status fail(bpfa_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHK(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess) return fail(BPFA_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Layout {
+  int Npad = 0, Jcap = 0, KT = 0, KS = 0, sweep_blocks = 0;
+  size_t sweep_lds = 0;
+  DictPlan plan;
+  // byte offsets
+  size_t image, mask, poff, pcoord, obs_bits, obs_count, perm, inv_perm, obs_idx, obs_val, wave_J,
+      omega, omega_blk, D, list0, list1, nact0, nact1, Ck, ell, scal, nk, sw_cnt, sw_part, dpart,
+      dx2, Cfull, Bvec, sumr2_p, Y, recon, total;
+};
+
+bpfa_status make_geom(const bpfa_params* p, Geom* g) {
+  if (!p) return fail(BPFA_EINVAL, "params is NULL");
+  if (p->ndim < 1 || p->ndim > kMaxDim) return fail(BPFA_ESHAPE, "ndim must be 1..4, got %d", p->ndim);
+  if (p->K < 1 || p->K > 1024) return fail(BPFA_ESHAPE, "K must be 1..1024, got %d", p->K);
+  std::memset(g, 0, sizeof *g);
+  g->ndim = p->ndim;
+  g->K = p->K;
+  long long P = 1, N = 1, Mt = 1;
+  for (int d = 0; d < p->ndim; ++d) {
+    const long long m = p->shape[d], b = p->patch[d], s = p->stride[d];
+    if (m < 1 || b < 1 || b > m || s < 1)
+      return fail(BPFA_ESHAPE, "dimension %d: need 1 <= B <= M and S >= 1 (M=%lld B=%lld S=%lld)", d,
+                  m, b, s);
+    const long long G = (m - b) / s + 1;
+    if (s > b || (G - 1) * s + b != m)
+      return fail(BPFA_ESHAPE, "dimension %d: pixels not covered by any patch (M=%lld B=%lld S=%lld)",
+                  d, m, b, s);
+    P *= b;
+    N *= G;
+    Mt *= m;
+    if (Mt >= (1LL << 31) || N >= (1LL << 31) || P > 4096)
+      return fail(BPFA_ESHAPE, "problem too large for 32-bit indexing (M, N) or P > 4096");
+    g->M[d] = (int)m;
+    g->B[d] = (int)b;
+    g->S[d] = (int)s;
+    g->G[d] = (int)G;
+  }
+  g->P = (int)P;
+  g->PW = (int)((P + 31) / 32);
+  g->N = (int)N;
+  g->Mtot = (int)Mt;
+  int st = 1;
+  for (int d = p->ndim - 1; d >= 0; --d) {
+    g->mstride[d] = st;
+    st *= g->M[d];
+  }
+  if (!(p->a > 0 && p->b > 0 && p->c > 0 && p->d > 0 && p->e > 0 && p->f > 0 &&
+        p->gamma_s0 > 0 && p->gamma_eps0 > 0) ||
+      !std::isfinite(p->a + p->b + p->c + p->d + p->e + p->f + p->gamma_s0 + p->gamma_eps0))
+    return fail(BPFA_EINVAL, "hyper-parameters and initial precisions must be positive and finite");
+  if (p->problem_id >= (1u << 24)) return fail(BPFA_EINVAL, "problem_id must fit 24 bits");
+  return BPFA_OK;
+}
+
+DictPlan make_dict_plan(const Geom& g) {
+  DictPlan pl;
+  const int K = g.K;
+  int rg = 0;
+  pl.row0[0] = 0;
+  pl.ent0[0] = 0;
+  long long len = 0;
+  for (int k = 0; k < K; ++k) {
+    const long long add = (K - k) + 1;
+    if (len + add > kDictLdsEntries && len > 0) {
+      ++rg;
+      pl.row0[rg] = k;
+      pl.ent0[rg] = (long long)k * K - (long long)k * (k - 1) / 2;
+      len = 0;
+    }
+    len += add;
+  }
+  pl.RG = rg + 1;
+  pl.row0[pl.RG] = K;
+  pl.ent0[pl.RG] = (long long)K * (K + 1) / 2;
+  pl.tri_entries = pl.ent0[pl.RG];
+  pl.rec_len_total = pl.tri_entries + K;
+  const int target_blocks = 512;
+  pl.chunks = std::max(1, std::min(64, (target_blocks + g.P * pl.RG - 1) / (g.P * pl.RG)));
+  return pl;
+}
+
+Layout make_layout(const Geom& g) {
+  Layout L;
+  L.Npad = (int)align_up((size_t)g.N, kSlotAlign);
+  L.Jcap = (int)align_up((size_t)g.P, 4);
+  // dictionary tile of the sweep: pixel-major with an odd atom stride
+  const long long P1 = g.P + 1;
+  if (P1 * (g.K + 1) * 4 <= kLdsTileBytes) {
+    L.KT = g.K;
+  } else {
+    int ktmax = (int)(kLdsTileBytes / (P1 * 4)) - 1;
+    ktmax &= ~1;
+    if (ktmax < 2) ktmax = 2;
+    const int tiles = (g.K + ktmax - 1) / ktmax;
+    L.KT = (int)align_up((size_t)((g.K + tiles - 1) / tiles), 2);
+  }
+  L.KS = L.KT + 1;
+  if (L.KS % 2 == 0) L.KS += 1;
+  L.sweep_blocks = L.Npad / kSweepBlock;
+  L.sweep_lds = (size_t)P1 * L.KS * 4 + (size_t)g.K * 4;
+  L.plan = make_dict_plan(g);
+  long long rec_stride = 0;
+  for (int r = 0; r < L.plan.RG; ++r) {
+    const long long len =
+        (L.plan.ent0[r + 1] - L.plan.ent0[r]) + (L.plan.row0[r + 1] - L.plan.row0[r]);
+    rec_stride = std::max(rec_stride, len);
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 1), 256);
+    return o;
+  };
+  const size_t N = g.N, Np = L.Npad, K = g.K, P = g.P;
+  L.image = take(4 * (size_t)g.Mtot);
+  L.mask = take((size_t)g.Mtot);
+  L.poff = take(4 * P);
+  L.pcoord = take(4 * P * kMaxDim);
+  L.obs_bits = take(4 * N * g.PW);
+  L.obs_count = take(4 * N);
+  L.perm = take(4 * Np);
+  L.inv_perm = take(4 * N);
+  L.obs_idx = take(2 * (size_t)L.Jcap * Np);
+  L.obs_val = take(4 * (size_t)L.Jcap * Np);
+  L.wave_J = take(4 * (Np / kWave));
+  L.omega = take(4 * (size_t)g.Mtot);
+  L.omega_blk = take(4 * (((size_t)g.Mtot + 255) / 256 + 1));
+  L.D = take(4 * K * P);
+  L.list0 = take(8 * Np * K);
+  L.list1 = take(8 * Np * K);
+  L.nact0 = take(4 * Np);
+  L.nact1 = take(4 * Np);
+  L.Ck = take(4 * K);
+  L.ell = take(8 * K);
+  L.scal = take(sizeof(DevScalars));
+  L.nk = take(8 * K);
+  L.sw_cnt = take(4 * K);
+  L.sw_part = take(sizeof(SweepPart) * L.sweep_blocks);
+  L.dpart = take(8 * (size_t)P * L.plan.RG * L.plan.chunks * rec_stride);
+  L.dx2 = take(8 * P * L.plan.chunks);
+  L.Cfull = take(8 * P * K * K);
+  L.Bvec = take(8 * P * K);
+  L.sumr2_p = take(8 * P);
+  L.Y = take(4 * P * N);
+  L.recon = take(4 * (size_t)g.Mtot);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct bpfa_problem {
+  bpfa_params prm{};
+  Geom g{};
+  Layout L{};
+  Buffers b{};
+  char* ws = nullptr;
+  bool own_ws = false;
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  int cur = 0;
+  int max_obs = 0, n_omega = 0, jtmpl = 8;
+  uint32_t key0 = 0, key1 = 0;
+  int64_t t_host = 1;
+  // timing
+  bool timing = false;
+  std::vector<std::array<hipEvent_t, 4>> iter_events;
+  std::vector<std::array<hipEvent_t, 2>> index_events, recon_events;
+  double ms_index = 0, ms_sweep = 0, ms_dict = 0, ms_scalars = 0, ms_recon = 0;
+  int64_t n_sweeps = 0;
+};
+
+namespace {
+
+uint32_t stream_word(uint32_t tag, uint32_t pid) { return (tag & 0xFFu) | (pid << 8); }
+
+bpfa_status upload(bpfa_problem* h, void* dst, const void* src, size_t bytes, bpfa_mem mem) {
+  if (bytes == 0) return BPFA_OK;
+  if (!src) return fail(BPFA_EINVAL, "NULL input buffer");
+  HIPCHK(hipMemcpyAsync(dst, src, bytes,
+                        mem == BPFA_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->st));
+  if (mem == BPFA_HOST) HIPCHK(hipStreamSynchronize(h->st));  // the caller may free src
+  return BPFA_OK;
+}
+
+bpfa_status record(bpfa_problem* h, hipEvent_t* ev) {
+  HIPCHK(hipEventCreate(ev));
+  HIPCHK(hipEventRecord(*ev, h->st));
+  return BPFA_OK;
+}
+
+bpfa_status collect_timing(bpfa_problem* h) {
+  float ms = 0.f;
+  for (auto& e : h->iter_events) {
+    HIPCHK(hipEventElapsedTime(&ms, e[0], e[1]));
+    h->ms_sweep += ms;
+    HIPCHK(hipEventElapsedTime(&ms, e[1], e[2]));
+    h->ms_dict += ms;
+    HIPCHK(hipEventElapsedTime(&ms, e[2], e[3]));
+    h->ms_scalars += ms;
+    for (auto ev : e) (void)hipEventDestroy(ev);
+    ++h->n_sweeps;
+  }
+  h->iter_events.clear();
+  for (auto& e : h->index_events) {
+    HIPCHK(hipEventElapsedTime(&ms, e[0], e[1]));
+    h->ms_index += ms;
+    for (auto ev : e) (void)hipEventDestroy(ev);
+  }
+  h->index_events.clear();
+  for (auto& e : h->recon_events) {
+    HIPCHK(hipEventElapsedTime(&ms, e[0], e[1]));
+    h->ms_recon += ms;
+    for (auto ev : e) (void)hipEventDestroy(ev);
+  }
+  h->recon_events.clear();
+  return BPFA_OK;
+}
+
+bpfa_status check_status(bpfa_problem* h) {
+  DevScalars s;
+  HIPCHK(hipMemcpyAsync(&s, h->b.scal, sizeof s, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  bpfa_status r = collect_timing(h);
+  if (r != BPFA_OK) return r;
+  h->t_host = s.t;
+  if (s.status) {
+    const int zero = 0;
+    HIPCHK(hipMemcpyAsync(&h->b.scal->status, &zero, sizeof zero, hipMemcpyHostToDevice, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    return fail(BPFA_ENUMERIC, "numeric failure in an iteration (flags %d: %s%s)", s.status,
+                (s.status & 1) ? "non-finite value " : "",
+                (s.status & 2) ? "gamma draw without acceptance" : "");
+  }
+  return BPFA_OK;
+}
+
+bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask, bpfa_mem mem) {
+  const Geom& g = h->g;
+  bpfa_status r = upload(h, h->b.image, image, 4 * (size_t)g.Mtot, mem);
+  if (r != BPFA_OK) return r;
+  r = upload(h, h->b.mask, mask, (size_t)g.Mtot, mem);
+  if (r != BPFA_OK) return r;
+  std::array<hipEvent_t, 2> ev{};
+  if (h->timing && (r = record(h, &ev[0])) != BPFA_OK) return r;
+  HIPCHK(launch_index(g, h->b, h->L.Npad, h->st));
+  HIPCHK(launch_omega(g, h->b, h->st));
+  DevScalars s;
+  HIPCHK(hipMemcpyAsync(&s, h->b.scal, sizeof s, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  h->max_obs = s.max_obs;
+  h->n_omega = s.n_omega;
+  if (h->max_obs > 256)
+    return fail(BPFA_ESHAPE, "a patch has %d observed pixels; at most 256 are supported", h->max_obs);
+  const int J4 = (h->max_obs + 3) & ~3;
+  static const int tmpl[] = {8, 16, 24, 32, 48, 64, 96, 128, 256};
+  h->jtmpl = 256;
+  for (int v : tmpl)
+    if (J4 <= v) {
+      h->jtmpl = v;
+      break;
+    }
+  HIPCHK(launch_slots(g, h->b, h->L.Npad, std::max(J4, 4), h->st));
+  if (h->timing) {
+    if ((r = record(h, &ev[1])) != BPFA_OK) return r;
+    h->index_events.push_back(ev);
+  }
+  return BPFA_OK;
+}
+
+bpfa_status clear_codes(bpfa_problem* h) {
+  HIPCHK(hipMemsetAsync(h->b.nact[0], 0, 4 * (size_t)h->L.Npad, h->st));
+  HIPCHK(hipMemsetAsync(h->b.nact[1], 0, 4 * (size_t)h->L.Npad, h->st));
+  return BPFA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void bpfa_params_default(bpfa_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->ndim = 2;
+  for (int d = 0; d < 4; ++d) p->stride[d] = 1;
+  p->K = 64;
+  p->a = p->b = 1.0;
+  p->c = p->d = p->e = p->f = 1e-6;
+  p->gamma_s0 = 1.0;
+  p->gamma_eps0 = 100.0;
+}
+
+bpfa_status bpfa_workspace_size(const bpfa_params* params, size_t* bytes) {
+  Geom g;
+  bpfa_status r = make_geom(params, &g);
+  if (r != BPFA_OK) return r;
+  if (!bytes) return fail(BPFA_EINVAL, "bytes is NULL");
+  *bytes = make_layout(g).total;
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_bytes,
+                        const float* image, const uint8_t* mask, bpfa_mem mem, bpfa_t* out) {
+  if (!out) return fail(BPFA_EINVAL, "out is NULL");
+  *out = nullptr;
+  Geom g;
+  bpfa_status r = make_geom(params, &g);
+  if (r != BPFA_OK) return r;
+  if (!image || !mask) return fail(BPFA_EINVAL, "image and mask are required");
+  DeviceGuard dg(params->device);
+  if (!dg.ok) return fail(BPFA_EDEVICE, "cannot select device %d", params->device);
+  auto* h = new bpfa_problem();
+  h->prm = *params;
+  h->g = g;
+  h->L = make_layout(g);
+  h->key0 = (uint32_t)(params->seed & 0xFFFFFFFFu);
+  h->key1 = (uint32_t)(params->seed >> 32);
+  auto bail = [&](bpfa_status s) {
+    bpfa_destroy(h);
+    return s;
+  };
+  if (params->stream) {
+    h->st = (hipStream_t)params->stream;
+  } else {
+    if (hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(BPFA_EDEVICE, "hipStreamCreate failed"));
+    h->own_stream = true;
+  }
+  if (workspace) {
+    if (ws_bytes < h->L.total)
+      return bail(fail(BPFA_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, h->L.total));
+    h->ws = (char*)workspace;
+  } else {
+    if (hipMalloc((void**)&h->ws, h->L.total) != hipSuccess)
+      return bail(fail(BPFA_ENOMEM, "hipMalloc of %zu bytes failed", h->L.total));
+    h->own_ws = true;
+  }
+  const Layout& L = h->L;
+  char* w = h->ws;
+  Buffers& b = h->b;
+  b.image = (float*)(w + L.image);
+  b.mask = (uint8_t*)(w + L.mask);
+  b.poff = (int32_t*)(w + L.poff);
+  b.pcoord = (int32_t*)(w + L.pcoord);
+  b.obs_bits = (uint32_t*)(w + L.obs_bits);
+  b.obs_count = (int32_t*)(w + L.obs_count);
+  b.perm = (uint32_t*)(w + L.perm);
+  b.inv_perm = (int32_t*)(w + L.inv_perm);
+  b.obs_idx = (uint16_t*)(w + L.obs_idx);
+  b.obs_val = (float*)(w + L.obs_val);
+  b.wave_J = (int32_t*)(w + L.wave_J);
+  b.omega = (int32_t*)(w + L.omega);
+  b.omega_blk = (int32_t*)(w + L.omega_blk);
+  b.D = (float*)(w + L.D);
+  b.list[0] = (int2*)(w + L.list0);
+  b.list[1] = (int2*)(w + L.list1);
+  b.nact[0] = (int32_t*)(w + L.nact0);
+  b.nact[1] = (int32_t*)(w + L.nact1);
+  b.Ck = (float*)(w + L.Ck);
+  b.ell = (double*)(w + L.ell);
+  b.scal = (DevScalars*)(w + L.scal);
+  b.nk = (long long*)(w + L.nk);
+  b.sw_cnt = (int32_t*)(w + L.sw_cnt);
+  b.sw_part = (SweepPart*)(w + L.sw_part);
+  b.dpart = (long long*)(w + L.dpart);
+  b.dx2 = (double*)(w + L.dx2);
+  b.Cfull = (double*)(w + L.Cfull);
+  b.Bvec = (double*)(w + L.Bvec);
+  b.sumr2_p = (double*)(w + L.sumr2_p);
+  b.Y = (float*)(w + L.Y);
+
+  // in-patch pixel offsets and coordinates, C order over B
+  std::vector<int32_t> poff(g.P), pcoord((size_t)g.P * kMaxDim, 0);
+  for (int p = 0; p < g.P; ++p) {
+    int rem = p, off = 0;
+    for (int d = g.ndim - 1; d >= 0; --d) {
+      const int c = rem % g.B[d];
+      rem /= g.B[d];
+      pcoord[(size_t)p * kMaxDim + d] = c;
+      off += c * g.mstride[d];
+    }
+    poff[p] = off;
+  }
+  DevScalars s0;
+  std::memset(&s0, 0, sizeof s0);
+  s0.gamma_s = params->gamma_s0;
+  s0.gamma_eps = params->gamma_eps0;
+  s0.t = 1;
+  std::vector<double> ell(g.K, g.K > 1 ? std::log(params->a / g.K) -
+                                           std::log(params->b * (g.K - 1) / g.K)
+                                     : 0.0);
+  if (hipMemcpyAsync(b.poff, poff.data(), 4 * poff.size(), hipMemcpyHostToDevice, h->st) != hipSuccess ||
+      hipMemcpyAsync(b.pcoord, pcoord.data(), 4 * pcoord.size(), hipMemcpyHostToDevice, h->st) != hipSuccess ||
+      hipMemcpyAsync(b.scal, &s0, sizeof s0, hipMemcpyHostToDevice, h->st) != hipSuccess ||
+      hipMemcpyAsync(b.ell, ell.data(), 8 * ell.size(), hipMemcpyHostToDevice, h->st) != hipSuccess ||
+      hipMemsetAsync(b.sw_cnt, 0, 4 * (size_t)g.K, h->st) != hipSuccess ||
+      hipMemsetAsync(b.perm, 0, 4 * (size_t)L.Npad, h->st) != hipSuccess ||
+      hipStreamSynchronize(h->st) != hipSuccess)
+    return bail(fail(BPFA_EDEVICE, "initial uploads failed"));
+  if ((r = clear_codes(h)) != BPFA_OK) return bail(r);
+  if (launch_init_dict(g, b, h->key0, h->key1, stream_word(7, params->problem_id), h->st) !=
+          hipSuccess ||
+      launch_ck(g, b, h->st) != hipSuccess)
+    return bail(fail(BPFA_EDEVICE, "initial kernels failed to launch"));
+  if ((r = load_frame(h, image, mask, mem)) != BPFA_OK) return bail(r);
+  if (hipStreamSynchronize(h->st) != hipSuccess)
+    return bail(fail(BPFA_EDEVICE, "create: stream synchronisation failed"));
+  *out = h;
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_set_frame(bpfa_t h, const float* image, const uint8_t* mask, bpfa_mem mem,
+                           int reset_codes) {
+  if (!h) return fail(BPFA_EINVAL, "NULL handle");
+  DeviceGuard dg(h->prm.device);
+  bpfa_status r = load_frame(h, image, mask, mem);
+  if (r != BPFA_OK) return r;
+  if (reset_codes) return clear_codes(h);
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_iterate(bpfa_t h, int32_t n_iters, uint32_t flags) {
+  if (!h) return fail(BPFA_EINVAL, "NULL handle");
+  if (n_iters < 0) return fail(BPFA_EINVAL, "n_iters < 0");
+  if (flags & ~(uint32_t)(BPFA_LEARN_DICT | BPFA_SPARSE_CODE_ONLY | BPFA_PRECISION_BF16))
+    return fail(BPFA_EINVAL, "unknown flags 0x%x", flags);
+  if ((flags & BPFA_LEARN_DICT) && (flags & BPFA_SPARSE_CODE_ONLY))
+    return fail(BPFA_EINVAL, "LEARN_DICT and SPARSE_CODE_ONLY are exclusive");
+  if (flags & BPFA_PRECISION_BF16)
+    return fail(BPFA_EINVAL, "the BF16 precision form is not available in this build");
+  const int learn = (flags & BPFA_SPARSE_CODE_ONLY) ? 0 : 1;
+  DeviceGuard dg(h->prm.device);
+  const Geom& g = h->g;
+  const Layout& L = h->L;
+  Buffers& b = h->b;
+  const double hyper[6] = {h->prm.a, h->prm.b, h->prm.c, h->prm.d, h->prm.e, h->prm.f};
+  for (int it = 0; it < n_iters; ++it) {
+    SweepArgs a{};
+    a.N = g.N;
+    a.Npad = L.Npad;
+    a.P = g.P;
+    a.K = g.K;
+    a.KT = L.KT;
+    a.KS = L.KS;
+    a.key0 = h->key0;
+    a.key1 = h->key1;
+    a.stream = stream_word(1, h->prm.problem_id);
+    a.perm = b.perm;
+    a.wave_J = b.wave_J;
+    a.obs_idx = b.obs_idx;
+    a.obs_val = b.obs_val;
+    a.D = b.D;
+    a.Ck = b.Ck;
+    a.scal = b.scal;
+    a.list_in = b.list[h->cur];
+    a.nact_in = b.nact[h->cur];
+    a.list_out = b.list[1 - h->cur];
+    a.nact_out = b.nact[1 - h->cur];
+    a.cnt = b.sw_cnt;
+    a.part = b.sw_part;
+    std::array<hipEvent_t, 4> ev{};
+    bpfa_status r;
+    if (h->timing && (r = record(h, &ev[0])) != BPFA_OK) return r;
+    HIPCHK(launch_sweep(h->jtmpl, L.sweep_blocks, L.sweep_lds, a, h->st));
+    if (h->timing && (r = record(h, &ev[1])) != BPFA_OK) return r;
+    HIPCHK(launch_sweep_reduce(g, b, L.sweep_blocks, h->st));
+    h->cur = 1 - h->cur;
+    if (learn) {
+      HIPCHK(launch_dict_stats(g, b, L.plan, h->cur, L.Npad, h->st));
+      HIPCHK(launch_dict_chain(g, b, L.plan, h->key0, h->key1, stream_word(2, h->prm.problem_id),
+                               h->st));
+    }
+    if (h->timing && (r = record(h, &ev[2])) != BPFA_OK) return r;
+    HIPCHK(launch_scalars(g, b, hyper, learn, h->key0, h->key1, h->prm.problem_id, h->st));
+    if (h->timing) {
+      if ((r = record(h, &ev[3])) != BPFA_OK) return r;
+      h->iter_events.push_back(ev);
+    }
+    ++h->t_host;
+  }
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_reconstruct(bpfa_t h, float* out, bpfa_mem mem) {
+  if (!h || !out) return fail(BPFA_EINVAL, "NULL handle or output");
+  DeviceGuard dg(h->prm.device);
+  float* dst = mem == BPFA_DEVICE ? out : (float*)(h->ws + h->L.recon);
+  std::array<hipEvent_t, 2> ev{};
+  bpfa_status r;
+  if (h->timing && (r = record(h, &ev[0])) != BPFA_OK) return r;
+  HIPCHK(launch_recon(h->g, h->b, h->cur, h->L.Npad, dst, h->st));
+  if (h->timing) {
+    if ((r = record(h, &ev[1])) != BPFA_OK) return r;
+    h->recon_events.push_back(ev);
+  }
+  if (mem == BPFA_HOST) {
+    HIPCHK(hipMemcpyAsync(out, dst, 4 * (size_t)h->g.Mtot, hipMemcpyDeviceToHost, h->st));
+    return check_status(h);
+  }
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_transfer_dictionary(bpfa_t dst, bpfa_t src, uint32_t what) {
+  if (!dst || !src) return fail(BPFA_EINVAL, "NULL handle");
+  if (what & ~(uint32_t)(BPFA_XFER_D | BPFA_XFER_PI | BPFA_XFER_GAMMAS))
+    return fail(BPFA_EINVAL, "unknown transfer selector 0x%x", what);
+  if (dst->g.P != src->g.P || dst->g.K != src->g.K)
+    return fail(BPFA_ESHAPE, "transfer needs equal P and K (dst %d/%d, src %d/%d)", dst->g.P,
+                dst->g.K, src->g.P, src->g.K);
+  DeviceGuard dg(dst->prm.device);
+  if (dst == src) return BPFA_OK;
+  hipEvent_t ev;
+  HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(ev, src->st));
+  HIPCHK(hipStreamWaitEvent(dst->st, ev, 0));
+  HIPCHK(hipEventDestroy(ev));
+  const Geom& g = dst->g;
+  if (what & BPFA_XFER_D)
+    HIPCHK(hipMemcpyAsync(dst->b.D, src->b.D, 4 * (size_t)g.K * g.P, hipMemcpyDeviceToDevice, dst->st));
+  if (what & BPFA_XFER_PI)
+    HIPCHK(hipMemcpyAsync(dst->b.ell, src->b.ell, 8 * (size_t)g.K, hipMemcpyDeviceToDevice, dst->st));
+  if (what & BPFA_XFER_GAMMAS)
+    HIPCHK(hipMemcpyAsync(&dst->b.scal->gamma_s, &src->b.scal->gamma_s, 2 * sizeof(double),
+                          hipMemcpyDeviceToDevice, dst->st));
+  HIPCHK(launch_ck(g, dst->b, dst->st));
+  // src must not be modified before the copies have read it
+  HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(ev, dst->st));
+  HIPCHK(hipStreamWaitEvent(src->st, ev, 0));
+  HIPCHK(hipEventDestroy(ev));
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_get_state(bpfa_t h, bpfa_state_view* v) {
+  if (!h || !v) return fail(BPFA_EINVAL, "NULL handle or view");
+  DeviceGuard dg(h->prm.device);
+  const Geom& g = h->g;
+  const hipMemcpyKind kind = v->mem == BPFA_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (v->D) HIPCHK(hipMemcpyAsync(v->D, h->b.D, 4 * (size_t)g.K * g.P, kind, h->st));
+  if (v->logit_pi) HIPCHK(hipMemcpyAsync(v->logit_pi, h->b.ell, 8 * (size_t)g.K, kind, h->st));
+  if (v->W || v->Z) {
+    float* W = v->W;
+    uint8_t* Z = v->Z;
+    void* tmp = nullptr;
+    const size_t nk = (size_t)g.N * g.K;
+    if (v->mem == BPFA_HOST) {
+      HIPCHK(hipMallocAsync(&tmp, 5 * nk, h->st));
+      W = v->W ? (float*)tmp : nullptr;
+      Z = v->Z ? (uint8_t*)tmp + 4 * nk : nullptr;
+    }
+    HIPCHK(launch_lists_to_dense(g, h->b, h->cur, W, Z, h->st));
+    if (v->mem == BPFA_HOST) {
+      if (v->W) HIPCHK(hipMemcpyAsync(v->W, W, 4 * nk, hipMemcpyDeviceToHost, h->st));
+      if (v->Z) HIPCHK(hipMemcpyAsync(v->Z, Z, nk, hipMemcpyDeviceToHost, h->st));
+      HIPCHK(hipFreeAsync(tmp, h->st));
+    }
+  }
+  DevScalars s;
+  HIPCHK(hipMemcpyAsync(&s, h->b.scal, sizeof s, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  v->gamma_s = s.gamma_s;
+  v->gamma_eps = s.gamma_eps;
+  v->t = s.t;
+  return check_status(h);
+}
+
+bpfa_status bpfa_set_state(bpfa_t h, const bpfa_state_view* v) {
+  if (!h || !v) return fail(BPFA_EINVAL, "NULL handle or view");
+  if (!(v->gamma_s > 0) || !(v->gamma_eps > 0) || !std::isfinite(v->gamma_s) ||
+      !std::isfinite(v->gamma_eps) || v->t < 1 || v->t >= (1LL << 32))
+    return fail(BPFA_ESTATE, "state gammas must be positive and finite, 1 <= t < 2^32");
+  DeviceGuard dg(h->prm.device);
+  const Geom& g = h->g;
+  const hipMemcpyKind kind = v->mem == BPFA_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (v->D) HIPCHK(hipMemcpyAsync(h->b.D, v->D, 4 * (size_t)g.K * g.P, kind, h->st));
+  if (v->logit_pi) HIPCHK(hipMemcpyAsync(h->b.ell, v->logit_pi, 8 * (size_t)g.K, kind, h->st));
+  int bad = 0;
+  if (v->W) {
+    const size_t nk = (size_t)g.N * g.K;
+    void* tmp = nullptr;
+    HIPCHK(hipMallocAsync(&tmp, 5 * nk + 4, h->st));
+    const float* W = v->W;
+    const uint8_t* Z = v->Z;
+    int* dbad = (int*)((char*)tmp + 5 * nk);
+    if (v->mem == BPFA_HOST) {
+      HIPCHK(hipMemcpyAsync(tmp, v->W, 4 * nk, hipMemcpyHostToDevice, h->st));
+      W = (const float*)tmp;
+      if (v->Z) {
+        HIPCHK(hipMemcpyAsync((char*)tmp + 4 * nk, v->Z, nk, hipMemcpyHostToDevice, h->st));
+        Z = (const uint8_t*)tmp + 4 * nk;
+      }
+    }
+    HIPCHK(hipMemsetAsync(dbad, 0, 4, h->st));
+    HIPCHK(launch_dense_to_lists(g, h->b, h->cur, h->L.Npad, W, Z, dbad, h->st));
+    HIPCHK(hipMemcpyAsync(&bad, dbad, 4, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipFreeAsync(tmp, h->st));
+  } else if (v->Z) {
+    return fail(BPFA_ESTATE, "Z without W cannot define the weights");
+  }
+  DevScalars s;
+  HIPCHK(hipMemcpyAsync(&s, h->b.scal, sizeof s, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  s.gamma_s = v->gamma_s;
+  s.gamma_eps = v->gamma_eps;
+  s.t = v->t;
+  HIPCHK(hipMemcpyAsync(h->b.scal, &s, sizeof s, hipMemcpyHostToDevice, h->st));
+  HIPCHK(launch_ck(g, h->b, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  h->t_host = v->t;
+  if (bad) return fail(BPFA_ESTATE, "W is non-zero where Z is 0");
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_get_stats(bpfa_t h, bpfa_stats* out) {
+  if (!h || !out) return fail(BPFA_EINVAL, "NULL handle or stats");
+  DeviceGuard dg(h->prm.device);
+  DevScalars s;
+  HIPCHK(hipMemcpyAsync(&s, h->b.scal, sizeof s, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  bpfa_status r = collect_timing(h);
+  if (r != BPFA_OK) return r;
+  std::memset(out, 0, sizeof *out);
+  out->t = s.t;
+  out->N = h->g.N;
+  out->P = h->g.P;
+  out->K = h->g.K;
+  out->n_obs = s.n_obs;
+  out->sum_z = s.sum_z;
+  out->mean_active = (double)s.sum_z / h->g.N;
+  out->gamma_s = s.gamma_s;
+  out->gamma_eps = s.gamma_eps;
+  out->pi_min = s.pi_min;
+  out->pi_mean = s.pi_mean;
+  out->pi_max = s.pi_max;
+  out->sum_w2 = s.sum_w2;
+  out->sum_r2 = s.sum_r2_used;
+  out->max_obs = h->max_obs;
+  out->timing = h->timing ? 1 : 0;
+  out->ms_index = h->ms_index;
+  out->ms_sweep = h->ms_sweep;
+  out->ms_dict = h->ms_dict;
+  out->ms_scalars = h->ms_scalars;
+  out->ms_recon = h->ms_recon;
+  out->n_sweeps = h->n_sweeps;
+  return check_status(h);
+}
+
+bpfa_status bpfa_set_timing(bpfa_t h, int on) {
+  if (!h) return fail(BPFA_EINVAL, "NULL handle");
+  DeviceGuard dg(h->prm.device);
+  HIPCHK(hipStreamSynchronize(h->st));
+  bpfa_status r = collect_timing(h);
+  if (r != BPFA_OK) return r;
+  h->timing = on != 0;
+  h->ms_index = h->ms_sweep = h->ms_dict = h->ms_scalars = h->ms_recon = 0.0;
+  h->n_sweeps = 0;
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_sync(bpfa_t h) {
+  if (!h) return fail(BPFA_EINVAL, "NULL handle");
+  DeviceGuard dg(h->prm.device);
+  return check_status(h);
+}
+
+bpfa_status bpfa_get_patch_index(bpfa_t h, uint32_t* obs_bits, int32_t* obs_count, bpfa_mem mem) {
+  if (!h) return fail(BPFA_EINVAL, "NULL handle");
+  DeviceGuard dg(h->prm.device);
+  const hipMemcpyKind kind = mem == BPFA_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (obs_bits)
+    HIPCHK(hipMemcpyAsync(obs_bits, h->b.obs_bits, 4 * (size_t)h->g.N * h->g.PW, kind, h->st));
+  if (obs_count)
+    HIPCHK(hipMemcpyAsync(obs_count, h->b.obs_count, 4 * (size_t)h->g.N, kind, h->st));
+  if (mem == BPFA_HOST) HIPCHK(hipStreamSynchronize(h->st));
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_debug_philox(int32_t device, uint64_t seed, uint32_t problem_id, uint32_t tag,
+                              const uint32_t* c0, uint32_t c1, uint32_t t, int64_t n,
+                              uint32_t* out, bpfa_mem mem) {
+  if (n < 0 || (n > 0 && (!c0 || !out))) return fail(BPFA_EINVAL, "bad arguments");
+  if (problem_id >= (1u << 24)) return fail(BPFA_EINVAL, "problem_id must fit 24 bits");
+  DeviceGuard dg(device);
+  if (!dg.ok) return fail(BPFA_EDEVICE, "cannot select device %d", device);
+  if (n == 0) return BPFA_OK;
+  const uint32_t* dc0 = c0;
+  uint32_t* dout = out;
+  void* tmp = nullptr;
+  if (mem == BPFA_HOST) {
+    HIPCHK(hipMalloc(&tmp, 20 * (size_t)n));
+    HIPCHK(hipMemcpy(tmp, c0, 4 * (size_t)n, hipMemcpyHostToDevice));
+    dc0 = (const uint32_t*)tmp;
+    dout = (uint32_t*)((char*)tmp + 4 * (size_t)n);
+  }
+  hipError_t e = launch_debug_philox((uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), c1, t,
+                                     stream_word(tag, problem_id), dc0, n, dout, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess && mem == BPFA_HOST) e = hipMemcpy(out, dout, 16 * (size_t)n, hipMemcpyDeviceToHost);
+  if (tmp) (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(BPFA_EDEVICE, "debug_philox: %s", hipGetErrorString(e));
+  return BPFA_OK;
+}
+
+void bpfa_destroy(bpfa_t h) {
+  if (!h) return;
+  DeviceGuard dg(h->prm.device);
+  if (h->st) (void)hipStreamSynchronize(h->st);
+  (void)collect_timing(h);
+  if (h->own_ws && h->ws) (void)hipFree(h->ws);
+  if (h->own_stream && h->st) (void)hipStreamDestroy(h->st);
+  delete h;
+}
+
+const char* bpfa_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+// Internal layout shared by the host runtime and the kernels of libbpfa.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace bpfa {
+
+constexpr int kWave = 64;
+constexpr int kMaxDim = 4;
+constexpr int kSweepBlock = 512;      // 8 waves share one LDS copy of the dictionary tile
+constexpr int kSlotAlign = kSweepBlock;
+constexpr int kLdsTileBytes = 64 * 1024;
+constexpr int kDictBlock = 256;
+constexpr int kDictLdsEntries = 16384; // int64 accumulators per statistics block (128 KiB)
+
+// Patch geometry (all sizes fit 32 bits; checked at create).
+struct Geom {
+  int32_t ndim, P, PW, K;
+  int32_t N, Mtot;
+  int32_t M[kMaxDim], B[kMaxDim], S[kMaxDim], G[kMaxDim];
+  int32_t mstride[kMaxDim];   // image element strides
+};
+
+// Device-resident scalars: read by kernels, written by kernels, so an
+// iteration needs no host round trip.
+struct DevScalars {
+  double gamma_s, gamma_eps;
+  double sum_w2;          // after the last sweep
+  double sum_r2_sweep;    // residual sum of squares after the last sweep
+  double sum_r2_dict;     // after the last dictionary update (statistics form)
+  double sum_r2_used;     // the one the last gamma_eps draw used
+  double scale_c, scale_b;// fixed-point scales of the dictionary statistics
+  double pi_min, pi_mean, pi_max;
+  long long t;            // next iteration number
+  long long sum_z;
+  long long n_obs;        // sum_i |Obs(i)|
+  int max_obs;
+  int status;             // bit 0: non-finite value, bit 1: gamma draw without acceptance
+  float wmax;             // max |w| after the last sweep
+  float ymax;             // max |y| over observed pixels
+  int n_omega;            // number of observed pixels
+  int pad_;
+};
+
+struct SweepPart {
+  double sum_w2, sum_r2;
+  long long sum_z;
+  float wmax;
+  int pad_;
+};
+
+// Arguments of the z/s sweep.
+struct SweepArgs {
+  int N, Npad, P, K, KT, KS;     // KT atoms per LDS tile, KS = KT + 1 (odd column stride)
+  uint32_t key0, key1, stream;   // Philox key and stream word (tag | problem_id << 8)
+  const uint32_t* perm;          // slot -> patch
+  const int32_t* wave_J;         // per 64-slot wave: max |Obs|, rounded up to 4
+  const uint16_t* obs_idx;       // [J][Npad] pixel offset p in the patch (P = padding)
+  const float* obs_val;          // [J][Npad] observed value (0 = padding)
+  const float* D;                // K x P
+  const float* Ck;               // K: logit pi_k + ln(gamma_s) / 2
+  const DevScalars* scal;
+  const int2* list_in;           // [Npad][K] active (atom, weight bits), ascending atom
+  const int32_t* nact_in;        // [Npad]
+  int2* list_out;
+  int32_t* nact_out;
+  int32_t* cnt;                  // [gridDim][K] z counts per block
+  SweepPart* part;               // [gridDim]
+};
+
+struct Buffers {
+  float* image = nullptr;
+  uint8_t* mask = nullptr;
+  int32_t* poff = nullptr;       // P: linear image offset of in-patch pixel p
+  int32_t* pcoord = nullptr;     // P x 4: its coordinates
+  uint32_t* obs_bits = nullptr;  // N x PW
+  int32_t* obs_count = nullptr;  // N
+  uint32_t* perm = nullptr;      // Npad slot -> patch
+  int32_t* inv_perm = nullptr;   // N patch -> slot
+  uint16_t* obs_idx = nullptr;   // [Jcap][Npad]
+  float* obs_val = nullptr;      // [Jcap][Npad]
+  int32_t* wave_J = nullptr;     // Npad / 64
+  int32_t* omega = nullptr;      // observed pixel indices, ascending (Mtot capacity)
+  int32_t* omega_blk = nullptr;  // per-block counts / offsets of the compaction
+  float* D = nullptr;            // K x P
+  int2* list[2] = {nullptr, nullptr};
+  int32_t* nact[2] = {nullptr, nullptr};
+  float* Ck = nullptr;           // K
+  double* ell = nullptr;         // K
+  DevScalars* scal = nullptr;
+  long long* nk = nullptr;       // K
+  int32_t* sw_cnt = nullptr;     // sweep blocks x K
+  SweepPart* sw_part = nullptr;  // sweep blocks
+  long long* dpart = nullptr;    // dictionary statistics partials
+  double* dx2 = nullptr;         // P x chunks: sum of y^2 over visits
+  double* Cfull = nullptr;       // P x K x K
+  double* Bvec = nullptr;        // P x K
+  double* sumr2_p = nullptr;     // P
+  float* Y = nullptr;            // P x Npad patch models D^T w_i (reconstruction)
+};
+
+// Plan of the dictionary-statistics pass: row groups of the K x K triangle
+// that fit the LDS accumulator, and patch-visit chunks per (p, row group).
+struct DictPlan {
+  int RG = 1;                  // row groups
+  int row0[65];                // row group r covers atoms [row0[r], row0[r+1])
+  long long ent0[65];          // triangle entry offset of row0[r]
+  int chunks = 1;
+  long long rec_len_total = 0; // sum over row groups of (entries + rows)
+  long long tri_entries = 0;   // K (K + 1) / 2
+};
+
+// ---- launchers (each checks its own launch and returns the HIP status) ----
+hipError_t launch_index(const Geom& g, const Buffers& b, int Npad, hipStream_t st);
+hipError_t launch_slots(const Geom& g, const Buffers& b, int Npad, int Jcap4, hipStream_t st);
+hipError_t launch_omega(const Geom& g, const Buffers& b, hipStream_t st);
+hipError_t launch_init_dict(const Geom& g, const Buffers& b, uint32_t key0, uint32_t key1,
+                            uint32_t stream, hipStream_t st);
+hipError_t launch_sweep(int JMAX, int blocks, size_t lds, const SweepArgs& a, hipStream_t st);
+hipError_t launch_sweep_reduce(const Geom& g, const Buffers& b, int blocks, hipStream_t st);
+hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& plan, int cur,
+                             int Npad, hipStream_t st);
+hipError_t launch_dict_chain(const Geom& g, const Buffers& b, const DictPlan& plan,
+                             uint32_t key0, uint32_t key1, uint32_t stream, hipStream_t st);
+hipError_t launch_scalars(const Geom& g, const Buffers& b, const double* hyper, int learn_dict,
+                          uint32_t key0, uint32_t key1, uint32_t problem_id, hipStream_t st);
+hipError_t launch_recon(const Geom& g, const Buffers& b, int cur, int Npad, float* out,
+                        hipStream_t st);
+hipError_t launch_lists_to_dense(const Geom& g, const Buffers& b, int cur, float* W, uint8_t* Z,
+                                 hipStream_t st);
+hipError_t launch_dense_to_lists(const Geom& g, const Buffers& b, int cur, int Npad,
+                                 const float* W, const uint8_t* Z, int* bad, hipStream_t st);
+hipError_t launch_ck(const Geom& g, const Buffers& b, hipStream_t st);
+hipError_t launch_debug_philox(uint32_t key0, uint32_t key1, uint32_t c1, uint32_t t,
+                               uint32_t stream, const uint32_t* c0, long long n, uint32_t* out,
+                               hipStream_t st);
+
+}  // namespace bpfa
