@@ -139,6 +139,11 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
 bpfa_status bpfa_set_frame(bpfa_t h, const float* image, const uint8_t* mask, bpfa_mem mem,
                            int reset_codes);
 
+/* Restart the sampler on the current frame from the initial state that
+ * bpfa_create sets (prior draw of D, no active atoms, initial pi and gammas,
+ * t = 1).  Stream-ordered, no host synchronisation. */
+bpfa_status bpfa_reset_state(bpfa_t h);
+
 /* Run n_iters Gibbs iterations (BPFA section: each iteration a sparse-coding
  * step and, unless BPFA_SPARSE_CODE_ONLY, a dictionary-learning step).  One
  * iteration: z/s sweep over all patches (atoms in ascending order), the

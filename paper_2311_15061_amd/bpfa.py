@@ -21,7 +21,7 @@ _NAMES = {EINVAL: "EINVAL", ESHAPE: "ESHAPE", ENOMEM: "ENOMEM", EDEVICE: "EDEVIC
           ESTATE: "ESTATE", ENUMERIC: "ENUMERIC", EBUSY: "EBUSY"}
 
 EXPORTED = ["bpfa_params_default", "bpfa_workspace_size", "bpfa_create", "bpfa_set_frame",
-            "bpfa_iterate", "bpfa_reconstruct", "bpfa_transfer_dictionary", "bpfa_get_state",
+            "bpfa_reset_state", "bpfa_iterate", "bpfa_reconstruct", "bpfa_transfer_dictionary", "bpfa_get_state",
             "bpfa_set_state", "bpfa_get_stats", "bpfa_set_timing", "bpfa_sync",
             "bpfa_get_patch_index", "bpfa_debug_philox", "bpfa_destroy", "bpfa_last_error"]
 
@@ -79,6 +79,7 @@ def _load():
         "bpfa_workspace_size": (ctypes.c_int, [P(Params), P(ctypes.c_size_t)]),
         "bpfa_create": (ctypes.c_int, [P(Params), vp, ctypes.c_size_t, vp, vp, ctypes.c_int, P(vp)]),
         "bpfa_set_frame": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, ctypes.c_int]),
+        "bpfa_reset_state": (ctypes.c_int, [vp]),
         "bpfa_iterate": (ctypes.c_int, [vp, i32, u32]),
         "bpfa_reconstruct": (ctypes.c_int, [vp, vp, ctypes.c_int]),
         "bpfa_transfer_dictionary": (ctypes.c_int, [vp, vp, u32]),
@@ -226,6 +227,9 @@ class Problem:
         if kind != kind_m:
             raise TypeError("image and mask must both be host or both be device memory")
         _check(lib.bpfa_set_frame(self._h, ip, mp, kind, int(bool(reset_codes))))
+
+    def reset_state(self):
+        _check(lib.bpfa_reset_state(self._h))
 
     def iterate(self, n=1, flags=LEARN_DICT):
         _check(lib.bpfa_iterate(self._h, int(n), int(flags)))

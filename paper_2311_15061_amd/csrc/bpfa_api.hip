@@ -476,6 +476,19 @@ bpfa_status bpfa_set_frame(bpfa_t h, const float* image, const uint8_t* mask, bp
   return BPFA_OK;
 }
 
+bpfa_status bpfa_reset_state(bpfa_t h) {
+  if (!h) return fail(BPFA_EINVAL, "NULL handle");
+  DeviceGuard dg(h->prm.device);
+  const Geom& g = h->g;
+  const double ell0 =
+      g.K > 1 ? std::log(h->prm.a / g.K) - std::log(h->prm.b * (g.K - 1) / g.K) : 0.0;
+  HIPCHK(launch_reset_scalars(g, h->b, ell0, h->prm.gamma_s0, h->prm.gamma_eps0, h->st));
+  HIPCHK(launch_init_dict(g, h->b, h->key0, h->key1, stream_word(7, h->prm.problem_id), h->st));
+  HIPCHK(launch_ck(g, h->b, h->st));
+  h->t_host = 1;
+  return clear_codes(h);
+}
+
 bpfa_status bpfa_iterate(bpfa_t h, int32_t n_iters, uint32_t flags) {
   if (!h) return fail(BPFA_EINVAL, "NULL handle");
   if (n_iters < 0) return fail(BPFA_EINVAL, "n_iters < 0");

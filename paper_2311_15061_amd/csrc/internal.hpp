@@ -132,6 +132,8 @@ hipError_t launch_lists_to_dense(const Geom& g, const Buffers& b, int cur, float
 hipError_t launch_dense_to_lists(const Geom& g, const Buffers& b, int cur, int Npad,
                                  const float* W, const uint8_t* Z, int* bad, hipStream_t st);
 hipError_t launch_ck(const Geom& g, const Buffers& b, hipStream_t st);
+hipError_t launch_reset_scalars(const Geom& g, const Buffers& b, double ell0, double gamma_s0,
+                                double gamma_eps0, hipStream_t st);
 hipError_t launch_debug_philox(uint32_t key0, uint32_t key1, uint32_t c1, uint32_t t,
                                uint32_t stream, const uint32_t* c0, long long n, uint32_t* out,
                                hipStream_t st);

@@ -146,6 +146,27 @@ hipError_t launch_ck(const Geom& g, const Buffers& b, hipStream_t st) {
   return hipGetLastError();
 }
 
+__global__ void reset_scalars_kernel(int K, double ell0, double gs0, double ge0,
+                                     double* __restrict__ ell, int32_t* __restrict__ nk,
+                                     DevScalars* scal) {
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    ell[k] = ell0;
+    nk[k] = 0;
+  }
+  if (threadIdx.x == 0) {
+    scal->gamma_s = gs0;
+    scal->gamma_eps = ge0;
+    scal->t = 1;
+  }
+}
+
+hipError_t launch_reset_scalars(const Geom& g, const Buffers& b, double ell0, double gamma_s0,
+                                double gamma_eps0, hipStream_t st) {
+  reset_scalars_kernel<<<1, 256, 0, st>>>(g.K, ell0, gamma_s0, gamma_eps0, b.ell, b.sw_cnt,
+                                          b.scal);
+  return hipGetLastError();
+}
+
 __global__ void debug_philox_kernel(uint32_t key0, uint32_t key1, uint32_t c1, uint32_t t,
                                     uint32_t stream, const uint32_t* __restrict__ c0,
                                     long long n, uint32_t* __restrict__ out) {
