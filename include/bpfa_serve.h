@@ -1,0 +1,109 @@
+/*
+ * bpfa_serve.h -- live-feed serving on top of libbpfa.
+ *
+ * The paper's abstract and introduction describe frame-by-frame
+ * reconstruction of a time-variable feed, and its feature summary lists
+ * multiple simultaneous problems and dictionary transfer between sources.
+ * A server holds one dictionary state (D, logit pi, gamma_s, gamma_eps and the
+ * Philox iteration counter) per feed stream, resident on the device, and
+ * reconstructs submitted frames of any 1..4-D shape: each frame starts with
+ * zero codes and the stream's state, runs `sc_iters` sparse-coding iterations
+ * (plus one dictionary-learning iteration on every `dict_every`-th frame of the
+ * stream), writes the overlap-averaged reconstruction and carries the updated
+ * state back to its stream.  Frames of one stream run in submission order;
+ * frames of different streams overlap on the device (continuous batching):
+ * a frame is admitted as soon as a slot for its shape is free and the
+ * workspaces fit the HBM budget, and slots of other shapes are freed when idle.
+ * Results of a stream do not depend on what else is in flight: every kernel
+ * is deterministic and a stream's random numbers depend only on its own
+ * counter (problem id = stream index, t continuing across its frames).
+ *
+ * Threading: submit / poll / stats may be called from any thread; the server
+ * runs one dispatcher thread and one worker thread per slot.
+ */
+#ifndef BPFA_SERVE_H
+#define BPFA_SERVE_H
+
+#include "bpfa.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bpfa_server* bpfa_server_t;
+
+typedef struct {
+  int32_t ndim;
+  int64_t patch[4], stride[4];     /* patch shape B and stride S of every frame */
+  int32_t K;
+  double a, b, c, d, e, f;         /* priors, as in bpfa_params */
+  double gamma_s0, gamma_eps0;
+  uint64_t seed;
+  int32_t n_streams;               /* feed streams, 1..4096 */
+  int32_t sc_iters;                /* sparse-coding iterations per frame (>= 1) */
+  int32_t dict_every;              /* dictionary iteration on every n-th frame of a stream; 0 = never */
+  int32_t max_slots;               /* frames in flight at most (>= 1) */
+  uint64_t hbm_budget;             /* bytes of slot workspaces the server may hold */
+  int32_t device;
+} bpfa_server_params;
+
+/* Defaults: 2-D 10 x 10 patches stride 1, K = 128, priors as bpfa_params_default,
+ * 4 streams, 5 sparse-coding iterations, dictionary every 10 frames, 4 slots,
+ * 16 GiB budget, device 0. */
+void bpfa_server_params_default(bpfa_server_params* p);
+
+/* Start a server.  EINVAL / ESHAPE for bad parameters, EDEVICE on HIP errors. */
+bpfa_status bpfa_server_create(const bpfa_server_params* p, bpfa_server_t* out);
+
+/* Dictionary transfer (feature summary) into stream `stream`: copies D,
+ * logit pi and the gammas from a problem (same P and K) and resets the
+ * stream's frame count; ESHAPE on a size mismatch.  Waits for the stream to
+ * be idle. */
+bpfa_status bpfa_server_set_dictionary(bpfa_server_t s, int32_t stream, bpfa_t src);
+
+/* Queue one frame of `stream`.  image / mask: host memory, prod(shape)
+ * floats / bytes, copied before return.  out: host memory of prod(shape)
+ * floats that the caller keeps valid until the ticket is reported by
+ * bpfa_server_poll (the reconstruction is written there).  *ticket gets a
+ * number increasing with submission.  ESHAPE if the shape is invalid for the
+ * server's patch geometry. */
+bpfa_status bpfa_server_submit(bpfa_server_t s, int32_t stream, const int64_t* shape,
+                               const float* image, const uint8_t* mask, float* out,
+                               uint64_t* ticket);
+
+typedef struct {
+  uint64_t ticket;
+  int32_t stream;
+  int32_t status;        /* bpfa_status of the frame (ENOMEM: larger than the whole budget) */
+  int64_t frame_index;   /* index of the frame within its stream */
+  int64_t pixels;
+  double latency_ms;     /* submission to reconstruction in host memory */
+  double queue_ms;       /* submission to admission */
+  int32_t learned;       /* 1 if the frame ran a dictionary iteration */
+} bpfa_serve_result;
+
+/* Completed frames since the last poll, oldest first; at most `max`.  */
+bpfa_status bpfa_server_poll(bpfa_server_t s, bpfa_serve_result* results, int32_t max,
+                             int32_t* n);
+
+/* Block until every submitted frame has completed. */
+bpfa_status bpfa_server_drain(bpfa_server_t s);
+
+typedef struct {
+  int64_t submitted, completed, failed;
+  int64_t in_flight, queued;
+  int64_t slots, slot_bytes;       /* live slots and their workspace bytes */
+  int64_t peak_slot_bytes;
+  int64_t slot_creations, slot_evictions;
+} bpfa_serve_stats;
+
+bpfa_status bpfa_server_stats(bpfa_server_t s, bpfa_serve_stats* st);
+
+/* Stop the threads (after draining) and free every device resource. */
+void bpfa_server_destroy(bpfa_server_t s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BPFA_SERVE_H */

@@ -60,9 +60,9 @@ struct Layout {
   size_t sweep_lds = 0;
   DictPlan plan;
   // byte offsets
-  size_t image, mask, poff, pcoord, obs_bits, obs_count, perm, inv_perm, obs_idx, obs_val, wave_J,
-      omega, omega_blk, D, list0, list1, nact0, nact1, Ck, ell, scal, nk, sw_cnt, sw_part, dpart,
-      dx2, Cfull, Bvec, sumr2_p, Y, recon, total;
+  size_t image, mask, poff, pcoord, obs_bits, obs_count, perm, inv_perm, inv_prev, obs_idx, obs_val, block_J, sort_hist, sort_bin,
+      omega, omega_c, omega_blk, D, list0, list1, nact0, nact1, Ck, ell, scal, nk, sw_cnt, sw_part, dpart,
+      dx2, Cfull, Bvec, diag, x2p, sumr2_p, Y, recon, total;
 };
 
 bpfa_status make_geom(const bpfa_params* p, Geom* g) {
@@ -154,7 +154,8 @@ Layout make_layout(const Geom& g) {
   L.KS = L.KT + 1;
   if (L.KS % 2 == 0) L.KS += 1;
   L.sweep_blocks = L.Npad / kSweepBlock;
-  L.sweep_lds = (size_t)P1 * L.KS * 4 + (size_t)g.K * 4;
+  // tile, then per-wave z counts (bytes)
+  L.sweep_lds = (size_t)P1 * L.KS * 4 + align_up((size_t)g.K * (kSweepBlock / kWave), 4);
   L.plan = make_dict_plan(g);
   long long rec_stride = 0;
   for (int r = 0; r < L.plan.RG; ++r) {
@@ -177,10 +178,14 @@ Layout make_layout(const Geom& g) {
   L.obs_count = take(4 * N);
   L.perm = take(4 * Np);
   L.inv_perm = take(4 * N);
+  L.inv_prev = take(4 * N);
   L.obs_idx = take(2 * (size_t)L.Jcap * Np);
   L.obs_val = take(4 * (size_t)L.Jcap * Np);
-  L.wave_J = take(4 * (Np / kWave));
+  L.block_J = take(4 * (Np / kSweepBlock));
+  L.sort_hist = take(4 * (P + 1) * ((N + kSortBlock - 1) / kSortBlock));
+  L.sort_bin = take(4 * (P + 1));
   L.omega = take(4 * (size_t)g.Mtot);
+  L.omega_c = take(16 * (size_t)g.Mtot);
   L.omega_blk = take(4 * (((size_t)g.Mtot + 255) / 256 + 1));
   L.D = take(4 * K * P);
   L.list0 = take(8 * Np * K);
@@ -197,6 +202,8 @@ Layout make_layout(const Geom& g) {
   L.dx2 = take(8 * P * L.plan.chunks);
   L.Cfull = take(8 * P * K * K);
   L.Bvec = take(8 * P * K);
+  L.diag = take(8 * P * K);
+  L.x2p = take(8 * P);
   L.sumr2_p = take(8 * P);
   L.Y = take(4 * P * N);
   L.recon = take(4 * (size_t)g.Mtot);
@@ -215,8 +222,11 @@ struct bpfa_problem {
   bool own_ws = false;
   hipStream_t st = nullptr;
   bool own_stream = false;
+  hipStream_t aux[kSweepRanges] = {};   // concurrent sweep ranges
+  hipEvent_t ev_fork = nullptr, ev_join[kSweepRanges] = {};
   int cur = 0;
-  int max_obs = 0, n_omega = 0, jtmpl = 8;
+  int max_obs = 0, n_omega = 0;
+  SweepLaunch sweep_ranges{};
   uint32_t key0 = 0, key1 = 0;
   int64_t t_host = 1;
   // timing
@@ -292,7 +302,10 @@ bpfa_status check_status(bpfa_problem* h) {
   return BPFA_OK;
 }
 
-bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask, bpfa_mem mem) {
+// Upload a frame and rebuild the patch index.  keep_codes: the active lists
+// follow their patches into the new slot order (otherwise they are cleared).
+bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask, bpfa_mem mem,
+                       bool keep_codes) {
   const Geom& g = h->g;
   bpfa_status r = upload(h, h->b.image, image, 4 * (size_t)g.Mtot, mem);
   if (r != BPFA_OK) return r;
@@ -300,7 +313,18 @@ bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask,
   if (r != BPFA_OK) return r;
   std::array<hipEvent_t, 2> ev{};
   if (h->timing && (r = record(h, &ev[0])) != BPFA_OK) return r;
+  if (keep_codes)
+    HIPCHK(hipMemcpyAsync(h->b.inv_prev, h->b.inv_perm, 4 * (size_t)g.N, hipMemcpyDeviceToDevice,
+                          h->st));
   HIPCHK(launch_index(g, h->b, h->L.Npad, h->st));
+  HIPCHK(launch_sort(g, h->b, h->L.Npad, h->st));
+  if (keep_codes) {
+    HIPCHK(launch_remap_lists(g, h->b, h->cur, h->st));
+    h->cur = 1 - h->cur;
+  } else {
+    HIPCHK(hipMemsetAsync(h->b.nact[0], 0, 4 * (size_t)h->L.Npad, h->st));
+    HIPCHK(hipMemsetAsync(h->b.nact[1], 0, 4 * (size_t)h->L.Npad, h->st));
+  }
   HIPCHK(launch_omega(g, h->b, h->st));
   DevScalars s;
   HIPCHK(hipMemcpyAsync(&s, h->b.scal, sizeof s, hipMemcpyDeviceToHost, h->st));
@@ -309,15 +333,27 @@ bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask,
   h->n_omega = s.n_omega;
   if (h->max_obs > 256)
     return fail(BPFA_ESHAPE, "a patch has %d observed pixels; at most 256 are supported", h->max_obs);
-  const int J4 = (h->max_obs + 3) & ~3;
-  static const int tmpl[] = {8, 16, 24, 32, 48, 64, 96, 128, 256};
-  h->jtmpl = 256;
-  for (int v : tmpl)
-    if (J4 <= v) {
-      h->jtmpl = v;
-      break;
-    }
-  HIPCHK(launch_slots(g, h->b, h->L.Npad, std::max(J4, 4), h->st));
+  const int J4 = std::max(4, (h->max_obs + 3) & ~3);
+  HIPCHK(launch_slots(g, h->b, h->L.Npad, J4, h->st));
+  // launch ranges of the sweep: blocks ascend in J
+  const int nblk = h->L.sweep_blocks;
+  std::vector<int32_t> bj(nblk);
+  HIPCHK(hipMemcpyAsync(bj.data(), h->b.block_J, 4 * (size_t)nblk, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  static const int bound[kSweepRanges] = {16, 32, 64, 128, 256};
+  int blk = 0;
+  for (int rr = 0; rr < kSweepRanges; ++rr) {
+    h->sweep_ranges.block0[rr] = blk;
+    while (blk < nblk && bj[blk] <= bound[rr]) ++blk;
+  }
+  h->sweep_ranges.block0[kSweepRanges] = blk;
+  if (blk != nblk) return fail(BPFA_EDEVICE, "slot blocks are not in ascending |Obs| order");
+  int best = 0;
+  for (int rr = 1; rr < kSweepRanges; ++rr)
+    if (h->sweep_ranges.block0[rr + 1] - h->sweep_ranges.block0[rr] >
+        h->sweep_ranges.block0[best + 1] - h->sweep_ranges.block0[best])
+      best = rr;
+  h->sweep_ranges.main_range = best;
   if (h->timing) {
     if ((r = record(h, &ev[1])) != BPFA_OK) return r;
     h->index_events.push_back(ev);
@@ -383,6 +419,12 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
       return bail(fail(BPFA_EDEVICE, "hipStreamCreate failed"));
     h->own_stream = true;
   }
+  for (int r = 0; r < kSweepRanges; ++r)
+    if (hipStreamCreateWithFlags(&h->aux[r], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_join[r], hipEventDisableTiming) != hipSuccess)
+      return bail(fail(BPFA_EDEVICE, "auxiliary stream creation failed"));
+  if (hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess)
+    return bail(fail(BPFA_EDEVICE, "event creation failed"));
   if (workspace) {
     if (ws_bytes < h->L.total)
       return bail(fail(BPFA_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, h->L.total));
@@ -403,10 +445,14 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
   b.obs_count = (int32_t*)(w + L.obs_count);
   b.perm = (uint32_t*)(w + L.perm);
   b.inv_perm = (int32_t*)(w + L.inv_perm);
+  b.inv_prev = (int32_t*)(w + L.inv_prev);
   b.obs_idx = (uint16_t*)(w + L.obs_idx);
   b.obs_val = (float*)(w + L.obs_val);
-  b.wave_J = (int32_t*)(w + L.wave_J);
+  b.block_J = (int32_t*)(w + L.block_J);
+  b.sort_hist = (int32_t*)(w + L.sort_hist);
+  b.sort_bin = (int32_t*)(w + L.sort_bin);
   b.omega = (int32_t*)(w + L.omega);
+  b.omega_c = (int4*)(w + L.omega_c);
   b.omega_blk = (int32_t*)(w + L.omega_blk);
   b.D = (float*)(w + L.D);
   b.list[0] = (int2*)(w + L.list0);
@@ -423,6 +469,8 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
   b.dx2 = (double*)(w + L.dx2);
   b.Cfull = (double*)(w + L.Cfull);
   b.Bvec = (double*)(w + L.Bvec);
+  b.diag = (double*)(w + L.diag);
+  b.x2p = (double*)(w + L.x2p);
   b.sumr2_p = (double*)(w + L.sumr2_p);
   b.Y = (float*)(w + L.Y);
 
@@ -459,7 +507,7 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
           hipSuccess ||
       launch_ck(g, b, h->st) != hipSuccess)
     return bail(fail(BPFA_EDEVICE, "initial kernels failed to launch"));
-  if ((r = load_frame(h, image, mask, mem)) != BPFA_OK) return bail(r);
+  if ((r = load_frame(h, image, mask, mem, false)) != BPFA_OK) return bail(r);
   if (hipStreamSynchronize(h->st) != hipSuccess)
     return bail(fail(BPFA_EDEVICE, "create: stream synchronisation failed"));
   *out = h;
@@ -470,10 +518,7 @@ bpfa_status bpfa_set_frame(bpfa_t h, const float* image, const uint8_t* mask, bp
                            int reset_codes) {
   if (!h) return fail(BPFA_EINVAL, "NULL handle");
   DeviceGuard dg(h->prm.device);
-  bpfa_status r = load_frame(h, image, mask, mem);
-  if (r != BPFA_OK) return r;
-  if (reset_codes) return clear_codes(h);
-  return BPFA_OK;
+  return load_frame(h, image, mask, mem, reset_codes == 0);
 }
 
 bpfa_status bpfa_reset_state(bpfa_t h) {
@@ -516,7 +561,7 @@ bpfa_status bpfa_iterate(bpfa_t h, int32_t n_iters, uint32_t flags) {
     a.key1 = h->key1;
     a.stream = stream_word(1, h->prm.problem_id);
     a.perm = b.perm;
-    a.wave_J = b.wave_J;
+    a.block_J = b.block_J;
     a.obs_idx = b.obs_idx;
     a.obs_val = b.obs_val;
     a.D = b.D;
@@ -531,12 +576,34 @@ bpfa_status bpfa_iterate(bpfa_t h, int32_t n_iters, uint32_t flags) {
     std::array<hipEvent_t, 4> ev{};
     bpfa_status r;
     if (h->timing && (r = record(h, &ev[0])) != BPFA_OK) return r;
-    HIPCHK(launch_sweep(h->jtmpl, L.sweep_blocks, L.sweep_lds, a, h->st));
+    {
+      const SweepLaunch& sl = h->sweep_ranges;
+      hipStream_t streams[kSweepRanges];
+      bool side = false;
+      for (int rr = 0; rr < kSweepRanges; ++rr) {
+        streams[rr] = rr == sl.main_range ? h->st : h->aux[rr];
+        side = side || (rr != sl.main_range && sl.block0[rr + 1] > sl.block0[rr]);
+      }
+      if (side) {
+        HIPCHK(hipEventRecord(h->ev_fork, h->st));
+        for (int rr = 0; rr < kSweepRanges; ++rr)
+          if (rr != sl.main_range && sl.block0[rr + 1] > sl.block0[rr])
+            HIPCHK(hipStreamWaitEvent(h->aux[rr], h->ev_fork, 0));
+      }
+      HIPCHK(launch_sweep(sl, L.sweep_lds, a, streams));
+      if (side)
+        for (int rr = 0; rr < kSweepRanges; ++rr)
+          if (rr != sl.main_range && sl.block0[rr + 1] > sl.block0[rr]) {
+            HIPCHK(hipEventRecord(h->ev_join[rr], h->aux[rr]));
+            HIPCHK(hipStreamWaitEvent(h->st, h->ev_join[rr], 0));
+          }
+    }
     if (h->timing && (r = record(h, &ev[1])) != BPFA_OK) return r;
     HIPCHK(launch_sweep_reduce(g, b, L.sweep_blocks, h->st));
     h->cur = 1 - h->cur;
     if (learn) {
       HIPCHK(launch_dict_stats(g, b, L.plan, h->cur, L.Npad, h->st));
+      HIPCHK(launch_dict_reduce(g, b, L.plan, h->st));
       HIPCHK(launch_dict_chain(g, b, L.plan, h->key0, h->key1, stream_word(2, h->prm.problem_id),
                                h->st));
     }
@@ -778,9 +845,59 @@ void bpfa_destroy(bpfa_t h) {
   (void)collect_timing(h);
   if (h->own_ws && h->ws) (void)hipFree(h->ws);
   if (h->own_stream && h->st) (void)hipStreamDestroy(h->st);
+  for (int r = 0; r < kSweepRanges; ++r) {
+    if (h->aux[r]) {
+      (void)hipStreamSynchronize(h->aux[r]);
+      (void)hipStreamDestroy(h->aux[r]);
+    }
+    if (h->ev_join[r]) (void)hipEventDestroy(h->ev_join[r]);
+  }
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   delete h;
 }
 
 const char* bpfa_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
+
+namespace bpfa {
+
+size_t dict_blob_bytes(int K, int P) { return (size_t)4 * K * P + (size_t)8 * K + 16; }
+
+int problem_dims(bpfa_problem* h, int* K, int* P) {
+  *K = h->g.K;
+  *P = h->g.P;
+  return BPFA_OK;
+}
+
+void problem_set_id(bpfa_problem* h, uint32_t problem_id) { h->prm.problem_id = problem_id; }
+
+int problem_export_dict(bpfa_problem* h, void* blob) {
+  DeviceGuard dg(h->prm.device);
+  const Geom& g = h->g;
+  char* b = (char*)blob;
+  HIPCHK(hipMemcpyAsync(b, h->b.D, 4 * (size_t)g.K * g.P, hipMemcpyDeviceToDevice, h->st));
+  b += 4 * (size_t)g.K * g.P;
+  HIPCHK(hipMemcpyAsync(b, h->b.ell, 8 * (size_t)g.K, hipMemcpyDeviceToDevice, h->st));
+  b += 8 * (size_t)g.K;
+  HIPCHK(hipMemcpyAsync(b, &h->b.scal->gamma_s, 16, hipMemcpyDeviceToDevice, h->st));
+  return BPFA_OK;
+}
+
+int problem_import_dict(bpfa_problem* h, const void* blob, long long t, uint32_t problem_id) {
+  DeviceGuard dg(h->prm.device);
+  const Geom& g = h->g;
+  const char* b = (const char*)blob;
+  HIPCHK(hipMemcpyAsync(h->b.D, b, 4 * (size_t)g.K * g.P, hipMemcpyDeviceToDevice, h->st));
+  b += 4 * (size_t)g.K * g.P;
+  HIPCHK(hipMemcpyAsync(h->b.ell, b, 8 * (size_t)g.K, hipMemcpyDeviceToDevice, h->st));
+  b += 8 * (size_t)g.K;
+  HIPCHK(hipMemcpyAsync(&h->b.scal->gamma_s, b, 16, hipMemcpyDeviceToDevice, h->st));
+  HIPCHK(launch_set_t(h->b.scal, t, h->st));
+  HIPCHK(launch_ck(g, h->b, h->st));
+  h->prm.problem_id = problem_id;
+  h->t_host = t;
+  return BPFA_OK;
+}
+
+}  // namespace bpfa

@@ -1,0 +1,473 @@
+// Serving engine of libbpfa: the C ABI declared in include/bpfa_serve.h.
+//
+// Frames wait in per-stream FIFOs.  A dispatcher thread admits the oldest
+// frame whose stream is idle as soon as a slot of its shape is free; slots
+// (a problem handle with its own HIP stream and workspace) are created while
+// the HBM budget allows and idle slots of other shapes are evicted to make
+// room.  One worker thread per slot runs a frame: upload and index the frame,
+// load the stream's dictionary state, sparse-coding iterations (plus one
+// dictionary iteration every dict_every-th frame), save the state back,
+// reconstruct into the caller's buffer.  Slots work on separate streams, so
+// frames of different feed streams overlap on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/bpfa_serve.h"
+#include "internal.hpp"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_between(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+struct Frame {
+  uint64_t ticket = 0;
+  int stream = 0;
+  std::vector<int64_t> shape;
+  int64_t pixels = 0;
+  float* img = nullptr;       // pinned copies of the caller's inputs
+  uint8_t* mask = nullptr;
+  float* out = nullptr;       // caller's host buffer
+  Clock::time_point submit_t, admit_t;
+  int64_t frame_index = 0;
+  long long t0 = 1;           // first Philox iteration number of this frame
+  bool learn = false;
+};
+
+struct Slot {
+  std::vector<int64_t> shape;
+  bpfa_t h = nullptr;
+  size_t bytes = 0;
+  bool busy = false;
+  bool stop = false;
+  Frame* job = nullptr;
+  std::thread worker;
+  std::condition_variable cv;
+};
+
+struct StreamState {
+  void* blob = nullptr;       // device: D, logit pi, gammas
+  long long t = 1;
+  int64_t frames = 0;
+  bool busy = false;
+  std::deque<Frame*> fifo;
+};
+
+}  // namespace
+
+struct bpfa_server {
+  bpfa_server_params prm{};
+  int K = 0, P = 0;
+  std::mutex mu;
+  std::condition_variable cv_disp, cv_done;
+  std::vector<StreamState> streams;
+  std::vector<Slot*> slots;
+  std::vector<bpfa_serve_result> results;
+  uint64_t next_ticket = 1;
+  int64_t submitted = 0, completed = 0, failed = 0, in_flight = 0, queued = 0;
+  int64_t slot_bytes = 0, peak_slot_bytes = 0, creations = 0, evictions = 0;
+  bool stopping = false;
+  std::thread dispatcher;
+};
+
+namespace {
+
+bpfa_params frame_params(const bpfa_server_params& s, const std::vector<int64_t>& shape) {
+  bpfa_params p;
+  bpfa_params_default(&p);
+  p.ndim = s.ndim;
+  for (int d = 0; d < 4; ++d) {
+    p.shape[d] = d < s.ndim ? shape[d] : 0;
+    p.patch[d] = s.patch[d];
+    p.stride[d] = s.stride[d];
+  }
+  p.K = s.K;
+  p.a = s.a;
+  p.b = s.b;
+  p.c = s.c;
+  p.d = s.d;
+  p.e = s.e;
+  p.f = s.f;
+  p.gamma_s0 = s.gamma_s0;
+  p.gamma_eps0 = s.gamma_eps0;
+  p.seed = s.seed;
+  p.device = s.device;
+  p.stream = nullptr;   // each slot owns a stream
+  return p;
+}
+
+void finish(bpfa_server* s, Frame* f, int status, bool learned) {
+  bpfa_serve_result r{};
+  r.ticket = f->ticket;
+  r.stream = f->stream;
+  r.status = status;
+  r.frame_index = f->frame_index;
+  r.pixels = f->pixels;
+  const Clock::time_point now = Clock::now();
+  r.latency_ms = ms_between(f->submit_t, now);
+  r.queue_ms = ms_between(f->submit_t, status == BPFA_OK ? f->admit_t : now);
+  r.learned = learned ? 1 : 0;
+  s->results.push_back(r);
+  if (status == BPFA_OK) ++s->completed;
+  else ++s->failed;
+  (void)hipHostFree(f->img);
+  (void)hipHostFree(f->mask);
+  delete f;
+}
+
+// one frame on a slot (called by the slot's worker without the server lock)
+int run_frame(bpfa_server* s, Slot* sl, Frame* f, StreamState* ss) {
+  const bpfa_server_params& p = s->prm;
+  bpfa_t h = sl->h;
+  int st = bpfa_set_frame(h, f->img, f->mask, BPFA_HOST, 1);
+  if (st != BPFA_OK) return st;
+  st = bpfa::problem_import_dict(h, ss->blob, f->t0, (uint32_t)f->stream);
+  if (st != BPFA_OK) return st;
+  st = bpfa_iterate(h, p.sc_iters, BPFA_SPARSE_CODE_ONLY);
+  if (st == BPFA_OK && f->learn) st = bpfa_iterate(h, 1, BPFA_LEARN_DICT);
+  if (st != BPFA_OK) return st;
+  st = bpfa::problem_export_dict(h, ss->blob);
+  if (st != BPFA_OK) return st;
+  return bpfa_reconstruct(h, f->out, BPFA_HOST);   // synchronises the slot's stream
+}
+
+void worker_loop(bpfa_server* s, Slot* sl) {
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    sl->cv.wait(lk, [&] { return sl->stop || sl->job != nullptr; });
+    if (sl->job == nullptr && sl->stop) return;
+    Frame* f = sl->job;
+    StreamState* ss = &s->streams[f->stream];
+    lk.unlock();
+    const int st = run_frame(s, sl, f, ss);
+    lk.lock();
+    const bool learned = f->learn;
+    if (st == BPFA_OK) {
+      ss->t = f->t0 + s->prm.sc_iters + (learned ? 1 : 0);
+    }
+    ss->busy = false;
+    sl->busy = false;
+    sl->job = nullptr;
+    --s->in_flight;
+    finish(s, f, st, learned);
+    s->cv_disp.notify_all();
+    s->cv_done.notify_all();
+  }
+}
+
+void destroy_slot(Slot* sl) {
+  if (sl->worker.joinable()) sl->worker.join();
+  if (sl->h) bpfa_destroy(sl->h);
+  delete sl;
+}
+
+// called with the lock held; may release it while creating a slot
+// *fail_status != OK: the frame cannot run (larger than the whole budget, or
+// the slot could not be built); nullptr with OK: wait for a slot to free up
+Slot* acquire_slot(bpfa_server* s, const std::vector<int64_t>& shape, size_t need,
+                   std::unique_lock<std::mutex>& lk, int* fail_status) {
+  *fail_status = need > s->prm.hbm_budget ? BPFA_ENOMEM : BPFA_OK;
+  if (*fail_status != BPFA_OK) return nullptr;
+  for (Slot* sl : s->slots)
+    if (!sl->busy && sl->shape == shape) return sl;
+  // make room: evict idle slots of other shapes until the new one fits
+  while ((uint64_t)s->slot_bytes + need > s->prm.hbm_budget ||
+         (int)s->slots.size() >= s->prm.max_slots) {
+    auto it = std::find_if(s->slots.begin(), s->slots.end(),
+                           [&](Slot* x) { return !x->busy && x->shape != shape; });
+    if (it == s->slots.end()) return nullptr;   // wait for a slot to free up
+    Slot* ev = *it;
+    s->slots.erase(it);
+    s->slot_bytes -= (int64_t)ev->bytes;
+    ++s->evictions;
+    ev->stop = true;
+    ev->cv.notify_all();
+    lk.unlock();
+    destroy_slot(ev);
+    lk.lock();
+  }
+  Slot* sl = new Slot();
+  sl->shape = shape;
+  sl->bytes = need;
+  sl->busy = true;   // reserved while it is being built
+  s->slots.push_back(sl);
+  s->slot_bytes += (int64_t)need;
+  s->peak_slot_bytes = std::max(s->peak_slot_bytes, s->slot_bytes);
+  ++s->creations;
+  lk.unlock();
+  // a slot starts on an all-zero frame; every job uploads its own
+  bpfa_params fp = frame_params(s->prm, shape);
+  int64_t px = 1;
+  for (int d = 0; d < s->prm.ndim; ++d) px *= shape[d];
+  std::vector<float> zimg((size_t)px, 0.f);
+  std::vector<uint8_t> zmask((size_t)px, 0);
+  bpfa_t h = nullptr;
+  const int st = bpfa_create(&fp, nullptr, 0, zimg.data(), zmask.data(), BPFA_HOST, &h);
+  lk.lock();
+  if (st != BPFA_OK) {
+    s->slots.erase(std::find(s->slots.begin(), s->slots.end(), sl));
+    s->slot_bytes -= (int64_t)need;
+    delete sl;
+    *fail_status = st;
+    return nullptr;
+  }
+  sl->h = h;
+  sl->busy = false;
+  sl->worker = std::thread(worker_loop, s, sl);
+  return sl;
+}
+
+void dispatcher_loop(bpfa_server* s) {
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    bool progress = true;
+    while (progress) {
+      progress = false;
+      // oldest head-of-stream frame first
+      Frame* best = nullptr;
+      for (auto& ss : s->streams)
+        if (!ss.busy && !ss.fifo.empty() && (!best || ss.fifo.front()->ticket < best->ticket))
+          best = ss.fifo.front();
+      if (!best) break;
+      StreamState& ss = s->streams[best->stream];
+      bpfa_params fp = frame_params(s->prm, best->shape);
+      size_t need = 0;
+      if (bpfa_workspace_size(&fp, &need) != BPFA_OK) need = (size_t)-1;
+      int fail_status = BPFA_OK;
+      Slot* sl = acquire_slot(s, best->shape, need, lk, &fail_status);
+      if (fail_status != BPFA_OK) {
+        ss.fifo.pop_front();
+        --s->queued;
+        finish(s, best, fail_status, false);
+        s->cv_done.notify_all();
+        progress = true;
+        continue;
+      }
+      if (!sl) break;   // wait for a slot
+      ss.fifo.pop_front();
+      --s->queued;
+      ss.busy = true;
+      best->frame_index = ss.frames++;
+      best->t0 = ss.t;
+      best->learn = s->prm.dict_every > 0 && (best->frame_index + 1) % s->prm.dict_every == 0;
+      best->admit_t = Clock::now();
+      sl->busy = true;
+      sl->job = best;
+      ++s->in_flight;
+      sl->cv.notify_all();
+      progress = true;
+    }
+    if (s->stopping && s->in_flight == 0 && s->queued == 0) return;
+    s->cv_disp.wait(lk);
+  }
+}
+
+int64_t frame_pixels(int ndim, const int64_t* shape) {
+  int64_t px = 1;
+  for (int d = 0; d < ndim; ++d) px *= shape[d];
+  return px;
+}
+
+}  // namespace
+
+extern "C" {
+
+void bpfa_server_params_default(bpfa_server_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->ndim = 2;
+  for (int d = 0; d < 4; ++d) {
+    p->patch[d] = d < 2 ? 10 : 1;
+    p->stride[d] = 1;
+  }
+  p->K = 128;
+  p->a = p->b = 1.0;
+  p->c = p->d = p->e = p->f = 1e-6;
+  p->gamma_s0 = 1.0;
+  p->gamma_eps0 = 100.0;
+  p->n_streams = 4;
+  p->sc_iters = 5;
+  p->dict_every = 10;
+  p->max_slots = 4;
+  p->hbm_budget = 16ull << 30;
+}
+
+bpfa_status bpfa_server_create(const bpfa_server_params* p, bpfa_server_t* out) {
+  if (!p || !out) return BPFA_EINVAL;
+  *out = nullptr;
+  if (p->n_streams < 1 || p->n_streams > 4096 || p->sc_iters < 1 || p->dict_every < 0 ||
+      p->max_slots < 1 || p->hbm_budget == 0)
+    return BPFA_EINVAL;
+  // validate the patch geometry and priors on the smallest frame that holds one patch
+  std::vector<int64_t> probe(4, 1);
+  for (int d = 0; d < p->ndim && d < 4; ++d) probe[d] = p->patch[d];
+  bpfa_params fp = frame_params(*p, probe);
+  size_t bytes = 0;
+  bpfa_status st = bpfa_workspace_size(&fp, &bytes);
+  if (st != BPFA_OK) return st;
+  auto* s = new bpfa_server();
+  s->prm = *p;
+  s->K = p->K;
+  s->P = 1;
+  for (int d = 0; d < p->ndim; ++d) s->P *= (int)p->patch[d];
+  s->streams.resize(p->n_streams);
+  // every stream starts from the prior: build it once on a probe problem
+  std::vector<float> zimg(frame_pixels(p->ndim, probe.data()), 0.f);
+  std::vector<uint8_t> zmask(zimg.size(), 0);
+  bpfa_t h0 = nullptr;
+  st = bpfa_create(&fp, nullptr, 0, zimg.data(), zmask.data(), BPFA_HOST, &h0);
+  if (st != BPFA_OK) {
+    delete s;
+    return st;
+  }
+  // stream n starts from its own prior draw (Philox stream id n), as a problem created with id n
+  const size_t blob = bpfa::dict_blob_bytes(s->K, s->P);
+  for (int n = 0; n < p->n_streams; ++n) {
+    StreamState& ss = s->streams[n];
+    bpfa::problem_set_id(h0, (uint32_t)n);
+    if (hipMalloc(&ss.blob, blob) != hipSuccess || bpfa_reset_state(h0) != BPFA_OK ||
+        bpfa::problem_export_dict(h0, ss.blob) != BPFA_OK) {
+      bpfa_destroy(h0);
+      bpfa_server_destroy(s);
+      return BPFA_ENOMEM;
+    }
+  }
+  st = bpfa_sync(h0);
+  bpfa_destroy(h0);
+  if (st != BPFA_OK) {
+    bpfa_server_destroy(s);
+    return st;
+  }
+  s->dispatcher = std::thread(dispatcher_loop, s);
+  *out = s;
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_server_set_dictionary(bpfa_server_t s, int32_t stream, bpfa_t src) {
+  if (!s || !src || stream < 0 || stream >= s->prm.n_streams) return BPFA_EINVAL;
+  int K = 0, P = 0;
+  bpfa::problem_dims(src, &K, &P);
+  if (K != s->K || P != s->P) return BPFA_ESHAPE;
+  std::unique_lock<std::mutex> lk(s->mu);
+  StreamState& ss = s->streams[stream];
+  s->cv_done.wait(lk, [&] { return !ss.busy && ss.fifo.empty(); });
+  ss.busy = true;   // keep the dispatcher away while the blob changes
+  lk.unlock();
+  int st = bpfa::problem_export_dict(src, ss.blob);
+  if (st == BPFA_OK) st = bpfa_sync(src);
+  lk.lock();
+  ss.frames = 0;
+  ss.busy = false;
+  s->cv_disp.notify_all();
+  return (bpfa_status)st;
+}
+
+bpfa_status bpfa_server_submit(bpfa_server_t s, int32_t stream, const int64_t* shape,
+                               const float* image, const uint8_t* mask, float* out,
+                               uint64_t* ticket) {
+  if (!s || !shape || !image || !mask || !out || stream < 0 || stream >= s->prm.n_streams)
+    return BPFA_EINVAL;
+  std::vector<int64_t> shp(shape, shape + s->prm.ndim);
+  bpfa_params fp = frame_params(s->prm, shp);
+  size_t need = 0;
+  bpfa_status st = bpfa_workspace_size(&fp, &need);
+  if (st != BPFA_OK) return st;
+  auto* f = new Frame();
+  f->stream = stream;
+  f->shape = shp;
+  f->pixels = frame_pixels(s->prm.ndim, shape);
+  f->out = out;
+  if (hipHostMalloc((void**)&f->img, 4 * (size_t)f->pixels, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&f->mask, (size_t)f->pixels, hipHostMallocDefault) != hipSuccess) {
+    (void)hipHostFree(f->img);
+    delete f;
+    return BPFA_ENOMEM;
+  }
+  std::memcpy(f->img, image, 4 * (size_t)f->pixels);
+  std::memcpy(f->mask, mask, (size_t)f->pixels);
+  std::lock_guard<std::mutex> lk(s->mu);
+  f->submit_t = Clock::now();
+  f->ticket = s->next_ticket++;
+  if (ticket) *ticket = f->ticket;
+  s->streams[stream].fifo.push_back(f);
+  ++s->submitted;
+  ++s->queued;
+  s->cv_disp.notify_all();
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_server_poll(bpfa_server_t s, bpfa_serve_result* results, int32_t max, int32_t* n) {
+  if (!s || !n || (max > 0 && !results)) return BPFA_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  const int32_t k = std::min<int32_t>(max, (int32_t)s->results.size());
+  for (int32_t i = 0; i < k; ++i) results[i] = s->results[i];
+  s->results.erase(s->results.begin(), s->results.begin() + k);
+  *n = k;
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_server_drain(bpfa_server_t s) {
+  if (!s) return BPFA_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] { return s->in_flight == 0 && s->queued == 0; });
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_server_stats(bpfa_server_t s, bpfa_serve_stats* st) {
+  if (!s || !st) return BPFA_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  st->submitted = s->submitted;
+  st->completed = s->completed;
+  st->failed = s->failed;
+  st->in_flight = s->in_flight;
+  st->queued = s->queued;
+  st->slots = (int64_t)s->slots.size();
+  st->slot_bytes = s->slot_bytes;
+  st->peak_slot_bytes = s->peak_slot_bytes;
+  st->slot_creations = s->creations;
+  st->slot_evictions = s->evictions;
+  return BPFA_OK;
+}
+
+void bpfa_server_destroy(bpfa_server_t s) {
+  if (!s) return;
+  {
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->stopping = true;
+    s->cv_disp.notify_all();
+  }
+  if (s->dispatcher.joinable()) s->dispatcher.join();
+  std::vector<Slot*> slots;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    slots.swap(s->slots);
+    for (Slot* sl : slots) {
+      sl->stop = true;
+      sl->cv.notify_all();
+    }
+  }
+  for (Slot* sl : slots) destroy_slot(sl);
+  for (auto& ss : s->streams) {
+    for (Frame* f : ss.fifo) {
+      (void)hipHostFree(f->img);
+      (void)hipHostFree(f->mask);
+      delete f;
+    }
+    if (ss.blob) (void)hipFree(ss.blob);
+  }
+  delete s;
+}
+
+}  // extern "C"

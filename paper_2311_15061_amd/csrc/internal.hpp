@@ -8,11 +8,13 @@ namespace bpfa {
 
 constexpr int kWave = 64;
 constexpr int kMaxDim = 4;
-constexpr int kSweepBlock = 512;      // 8 waves share one LDS copy of the dictionary tile
+constexpr int kSweepBlock = 256;      // 4 waves share one LDS copy of the dictionary tile
 constexpr int kSlotAlign = kSweepBlock;
 constexpr int kLdsTileBytes = 64 * 1024;
-constexpr int kDictBlock = 256;
+constexpr int kDictBlock = 512;
 constexpr int kDictLdsEntries = 16384; // int64 accumulators per statistics block (128 KiB)
+constexpr int kSortBlock = 256;        // patches per block of the slot sort
+constexpr int kSweepRanges = 5;        // J <= 16, <= 32, <= 64 (exact bodies), <= 128, <= 256
 
 // Patch geometry (all sizes fit 32 bits; checked at create).
 struct Geom {
@@ -55,7 +57,7 @@ struct SweepArgs {
   int N, Npad, P, K, KT, KS;     // KT atoms per LDS tile, KS = KT + 1 (odd column stride)
   uint32_t key0, key1, stream;   // Philox key and stream word (tag | problem_id << 8)
   const uint32_t* perm;          // slot -> patch
-  const int32_t* wave_J;         // per 64-slot wave: max |Obs|, rounded up to 4
+  const int32_t* block_J;        // per block of slots: largest |Obs|, rounded up to 4 (>= 4)
   const uint16_t* obs_idx;       // [J][Npad] pixel offset p in the patch (P = padding)
   const float* obs_val;          // [J][Npad] observed value (0 = padding)
   const float* D;                // K x P
@@ -78,10 +80,14 @@ struct Buffers {
   int32_t* obs_count = nullptr;  // N
   uint32_t* perm = nullptr;      // Npad slot -> patch
   int32_t* inv_perm = nullptr;   // N patch -> slot
+  int32_t* inv_prev = nullptr;   // N: patch -> slot of the previous frame
   uint16_t* obs_idx = nullptr;   // [Jcap][Npad]
   float* obs_val = nullptr;      // [Jcap][Npad]
-  int32_t* wave_J = nullptr;     // Npad / 64
+  int32_t* block_J = nullptr;    // Npad / kSweepBlock
+  int32_t* sort_hist = nullptr;  // (P + 1) x sort blocks, bin-major
+  int32_t* sort_bin = nullptr;   // P + 1: bin totals, then bin offsets
   int32_t* omega = nullptr;      // observed pixel indices, ascending (Mtot capacity)
+  int4* omega_c = nullptr;       // their coordinates (unused dimensions 0)
   int32_t* omega_blk = nullptr;  // per-block counts / offsets of the compaction
   float* D = nullptr;            // K x P
   int2* list[2] = {nullptr, nullptr};
@@ -96,6 +102,8 @@ struct Buffers {
   double* dx2 = nullptr;         // P x chunks: sum of y^2 over visits
   double* Cfull = nullptr;       // P x K x K
   double* Bvec = nullptr;        // P x K
+  double* diag = nullptr;        // P x K: C_p[k][k]
+  double* x2p = nullptr;         // P: sum of x^2 over the visits of position p
   double* sumr2_p = nullptr;     // P
   float* Y = nullptr;            // P x Npad patch models D^T w_i (reconstruction)
 };
@@ -111,16 +119,26 @@ struct DictPlan {
   long long tri_entries = 0;   // K (K + 1) / 2
 };
 
+// First block of each sweep launch range (ranges of ascending J).
+struct SweepLaunch {
+  int block0[kSweepRanges + 1];
+  int main_range;   // the range with the most blocks: it runs on the handle's stream
+};
+
 // ---- launchers (each checks its own launch and returns the HIP status) ----
 hipError_t launch_index(const Geom& g, const Buffers& b, int Npad, hipStream_t st);
 hipError_t launch_slots(const Geom& g, const Buffers& b, int Npad, int Jcap4, hipStream_t st);
 hipError_t launch_omega(const Geom& g, const Buffers& b, hipStream_t st);
 hipError_t launch_init_dict(const Geom& g, const Buffers& b, uint32_t key0, uint32_t key1,
                             uint32_t stream, hipStream_t st);
-hipError_t launch_sweep(int JMAX, int blocks, size_t lds, const SweepArgs& a, hipStream_t st);
+hipError_t launch_sweep(const SweepLaunch& sl, size_t lds, const SweepArgs& a,
+                        const hipStream_t* streams);
+hipError_t launch_sort(const Geom& g, const Buffers& b, int Npad, hipStream_t st);
 hipError_t launch_sweep_reduce(const Geom& g, const Buffers& b, int blocks, hipStream_t st);
 hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& plan, int cur,
                              int Npad, hipStream_t st);
+hipError_t launch_dict_reduce(const Geom& g, const Buffers& b, const DictPlan& plan,
+                              hipStream_t st);
 hipError_t launch_dict_chain(const Geom& g, const Buffers& b, const DictPlan& plan,
                              uint32_t key0, uint32_t key1, uint32_t stream, hipStream_t st);
 hipError_t launch_scalars(const Geom& g, const Buffers& b, const double* hyper, int learn_dict,
@@ -132,10 +150,25 @@ hipError_t launch_lists_to_dense(const Geom& g, const Buffers& b, int cur, float
 hipError_t launch_dense_to_lists(const Geom& g, const Buffers& b, int cur, int Npad,
                                  const float* W, const uint8_t* Z, int* bad, hipStream_t st);
 hipError_t launch_ck(const Geom& g, const Buffers& b, hipStream_t st);
+hipError_t launch_remap_lists(const Geom& g, const Buffers& b, int cur, hipStream_t st);
+hipError_t launch_set_t(DevScalars* scal, long long t, hipStream_t st);
 hipError_t launch_reset_scalars(const Geom& g, const Buffers& b, double ell0, double gamma_s0,
                                 double gamma_eps0, hipStream_t st);
 hipError_t launch_debug_philox(uint32_t key0, uint32_t key1, uint32_t c1, uint32_t t,
                                uint32_t stream, const uint32_t* c0, long long n, uint32_t* out,
                                hipStream_t st);
 
+}  // namespace bpfa
+
+// ---- runtime helpers shared with the serving engine (not part of the C ABI) ----
+struct bpfa_problem;
+namespace bpfa {
+// bytes of a dictionary-state blob: D (K x P f32), logit pi (K f64), gamma_s, gamma_eps (f64)
+size_t dict_blob_bytes(int K, int P);
+// copy the problem's dictionary state into / out of a device blob, on the problem's stream
+int problem_export_dict(bpfa_problem* h, void* blob);
+// load a blob, set the Philox stream id and the next iteration number
+int problem_import_dict(bpfa_problem* h, const void* blob, long long t, uint32_t problem_id);
+int problem_dims(bpfa_problem* h, int* K, int* P);
+void problem_set_id(bpfa_problem* h, uint32_t problem_id);
 }  // namespace bpfa

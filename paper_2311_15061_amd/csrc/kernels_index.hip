@@ -3,11 +3,16 @@
 // inpainting uses only the observed pixels of each patch).
 //
 // index_kernel   one thread per patch: observed-pixel bitmask and |Obs(i)|.
+// sort_*         stable counting sort of the patches by |Obs(i)| into slots
+//                (per-block histograms, per-count scans over blocks, ranks
+//                inside a block): deterministic, so results do not depend on
+//                scheduling; the sweep's blocks then hold patches of nearly
+//                equal |Obs|.
 // slots_kernel   one thread per slot: the observed offsets p (ascending) and
 //                values of the slot's patch, stored [j][slot] so that a wave
 //                reads them coalesced; padding entries point at offset P,
-//                which the sweep keeps at zero.  Per 64-slot wave the largest
-//                |Obs| (rounded up to 4) bounds the sweep's inner loops.
+//                which the sweep keeps at zero.  Per block of slots the
+//                largest |Obs| (rounded up to 4) is the sweep's register count.
 // omega_*        ordered compaction of the observed pixels (the dictionary
 //                statistics visit patches through them).
 #include "internal.hpp"
@@ -36,8 +41,7 @@ __global__ __launch_bounds__(256) void index_kernel(Geom g, const uint8_t* __res
                                                     const int32_t* __restrict__ poff,
                                                     uint32_t* __restrict__ bits,
                                                     int32_t* __restrict__ count,
-                                                    uint32_t* __restrict__ perm,
-                                                    int32_t* __restrict__ inv_perm, int Npad,
+                                                    uint32_t* __restrict__ perm, int Npad,
                                                     DevScalars* scal) {
   __shared__ int s_max[4];
   __shared__ long long s_sum[4];
@@ -57,9 +61,8 @@ __global__ __launch_bounds__(256) void index_kernel(Geom g, const uint8_t* __res
       bits[(size_t)i * g.PW + w] = word;
     }
     count[i] = cnt;
-    inv_perm[i] = i;
   }
-  if (i < Npad) perm[i] = (i < g.N) ? (uint32_t)i : 0u;
+  if (i >= g.N && i < Npad) perm[i] = 0u;   // padding slots
   // block max / sum of |Obs| (integers: order-free)
   int m = cnt;
   long long s = cnt;
@@ -92,7 +95,7 @@ __global__ __launch_bounds__(256) void slots_kernel(Geom g, const float* __restr
                                                     const uint32_t* __restrict__ perm,
                                                     uint16_t* __restrict__ obs_idx,
                                                     float* __restrict__ obs_val,
-                                                    int32_t* __restrict__ wave_J, int Npad,
+                                                    int32_t* __restrict__ block_J, int Npad,
                                                     int Jcap4) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;   // grid covers Npad exactly
   const bool valid = s < g.N;
@@ -118,9 +121,91 @@ __global__ __launch_bounds__(256) void slots_kernel(Geom g, const float* __restr
     obs_idx[(size_t)j * Npad + s] = (uint16_t)g.P;
     obs_val[(size_t)j * Npad + s] = 0.f;
   }
-  int m = cnt;
-  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
-  if ((threadIdx.x & 63) == 0) wave_J[s >> 6] = (m + 3) & ~3;
+  // slots ascend in |Obs|: the block's last valid slot has its largest count
+  const int blk = s / kSweepBlock;
+  const int last = min(g.N, (blk + 1) * kSweepBlock) - 1;
+  if (s == last || (s % kSweepBlock == 0 && last < s)) block_J[blk] = max(4, (cnt + 3) & ~3);
+}
+
+// exclusive scan in place of data[0 .. n) by one block of 1024 threads; returns the total
+__device__ int block_scan_1024(int* __restrict__ data, int n, int* s_tot) {
+  const int tid = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int b0 = min(n, tid * per), b1 = min(n, b0 + per);
+  int sum = 0;
+  for (int b = b0; b < b1; ++b) sum += data[b];
+  s_tot[tid] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int v = tid >= o ? s_tot[tid - o] : 0;
+    __syncthreads();
+    s_tot[tid] += v;
+    __syncthreads();
+  }
+  int run = s_tot[tid] - sum;
+  for (int b = b0; b < b1; ++b) {
+    const int c = data[b];
+    data[b] = run;
+    run += c;
+  }
+  const int total = s_tot[1023];
+  __syncthreads();
+  return total;
+}
+
+// ---- stable counting sort of patches by |Obs(i)| ---------------------------
+
+__global__ __launch_bounds__(kSortBlock) void sort_hist_kernel(Geom g, const int32_t* __restrict__ count,
+                                                               int32_t* __restrict__ hist, int nb) {
+  extern __shared__ int s_h[];
+  for (int v = threadIdx.x; v <= g.P; v += kSortBlock) s_h[v] = 0;
+  __syncthreads();
+  const int i = blockIdx.x * kSortBlock + threadIdx.x;
+  if (i < g.N) atomicAdd(&s_h[count[i]], 1);
+  __syncthreads();
+  for (int v = threadIdx.x; v <= g.P; v += kSortBlock) hist[(size_t)v * nb + blockIdx.x] = s_h[v];
+}
+
+// one block per count value: exclusive scan over the blocks, total into bins[v]
+__global__ __launch_bounds__(1024) void sort_scan_kernel(int32_t* __restrict__ hist, int nb,
+                                                         int32_t* __restrict__ bins) {
+  __shared__ int s_tot[1024];
+  const int t = block_scan_1024(hist + (size_t)blockIdx.x * nb, nb, s_tot);
+  if (threadIdx.x == 0) bins[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(1024) void sort_bins_kernel(int nbins, int32_t* __restrict__ bins) {
+  __shared__ int s_tot[1024];
+  block_scan_1024(bins, nbins, s_tot);
+}
+
+__global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(Geom g, const int32_t* __restrict__ count,
+                                                                  const int32_t* __restrict__ hist,
+                                                                  const int32_t* __restrict__ bins,
+                                                                  int nb, uint32_t* __restrict__ perm,
+                                                                  int32_t* __restrict__ inv_perm) {
+  __shared__ int s_c[kSortBlock];
+  const int i = blockIdx.x * kSortBlock + threadIdx.x;
+  const int c = i < g.N ? count[i] : -1;
+  s_c[threadIdx.x] = c;
+  __syncthreads();
+  if (i >= g.N) return;
+  int rank = 0;
+  for (int t = 0; t < (int)threadIdx.x; ++t) rank += s_c[t] == c;
+  const int slot = bins[c] + hist[(size_t)c * nb + blockIdx.x] + rank;
+  perm[slot] = (uint32_t)i;
+  inv_perm[i] = slot;
+}
+
+hipError_t launch_sort(const Geom& g, const Buffers& b, int Npad, hipStream_t st) {
+  (void)Npad;
+  const int nb = (g.N + kSortBlock - 1) / kSortBlock;
+  sort_hist_kernel<<<nb, kSortBlock, (g.P + 1) * sizeof(int), st>>>(g, b.obs_count, b.sort_hist, nb);
+  sort_scan_kernel<<<g.P + 1, 1024, 0, st>>>(b.sort_hist, nb, b.sort_bin);
+  sort_bins_kernel<<<1, 1024, 0, st>>>(g.P + 1, b.sort_bin);
+  sort_scatter_kernel<<<nb, kSortBlock, 0, st>>>(g, b.obs_count, b.sort_hist, b.sort_bin, nb, b.perm,
+                                                 b.inv_perm);
+  return hipGetLastError();
 }
 
 // ---- ordered compaction of observed pixels ---------------------------------
@@ -159,31 +244,15 @@ __global__ __launch_bounds__(256) void omega_count_kernel(int Mtot, const uint8_
 __global__ __launch_bounds__(1024) void omega_scan_kernel(int nb, int32_t* __restrict__ blk,
                                                           DevScalars* scal) {
   __shared__ int s_tot[1024];
-  const int tid = threadIdx.x;
-  const int per = (nb + 1023) / 1024;
-  const int b0 = min(nb, tid * per), b1 = min(nb, b0 + per);
-  int sum = 0;
-  for (int b = b0; b < b1; ++b) sum += blk[b];
-  s_tot[tid] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const int v = tid >= o ? s_tot[tid - o] : 0;
-    __syncthreads();
-    s_tot[tid] += v;
-    __syncthreads();
-  }
-  int run = s_tot[tid] - sum;
-  for (int b = b0; b < b1; ++b) {
-    const int c = blk[b];
-    blk[b] = run;
-    run += c;
-  }
-  if (tid == 1023) scal->n_omega = s_tot[1023];
+  const int total = block_scan_1024(blk, nb, s_tot);
+  if (threadIdx.x == 0) scal->n_omega = total;
 }
 
-__global__ __launch_bounds__(256) void omega_write_kernel(int Mtot, const uint8_t* __restrict__ mask,
+__global__ __launch_bounds__(256) void omega_write_kernel(Geom g, const uint8_t* __restrict__ mask,
                                                           const int32_t* __restrict__ blk,
-                                                          int32_t* __restrict__ omega) {
+                                                          int32_t* __restrict__ omega,
+                                                          int4* __restrict__ omega_c) {
+  const int Mtot = g.Mtot;
   __shared__ int s_c[4];
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const bool on = q < Mtot && mask[q] != 0;
@@ -194,7 +263,17 @@ __global__ __launch_bounds__(256) void omega_write_kernel(int Mtot, const uint8_
   int base = blk[blockIdx.x];
   for (int w = 0; w < wid; ++w) base += s_c[w];
   const unsigned long long below = (lane == 0) ? 0ull : (bal & ((~0ull) >> (64 - lane)));
-  if (on) omega[base + __popcll(below)] = q;
+  if (on) {
+    const int v = base + __popcll(below);
+    omega[v] = q;
+    int c[kMaxDim] = {0, 0, 0, 0};
+    int rem = q;
+    for (int d = g.ndim - 1; d >= 0; --d) {
+      c[d] = rem % g.M[d];
+      rem /= g.M[d];
+    }
+    omega_c[v] = make_int4(c[0], c[1], c[2], c[3]);
+  }
 }
 
 // ---- prior draw of the dictionary: d_kp = n / sqrt(P), binary64 ----------
@@ -215,7 +294,7 @@ hipError_t launch_index(const Geom& g, const Buffers& b, int Npad, hipStream_t s
   frame_reset_kernel<<<1, 1, 0, st>>>(b.scal);
   const int n = max(g.N, Npad);
   index_kernel<<<(n + 255) / 256, 256, 0, st>>>(g, b.mask, b.poff, b.obs_bits, b.obs_count,
-                                                b.perm, b.inv_perm, Npad, b.scal);
+                                                b.perm, Npad, b.scal);
   return hipGetLastError();
 }
 
@@ -223,13 +302,13 @@ hipError_t launch_omega(const Geom& g, const Buffers& b, hipStream_t st) {
   const int nb = (g.Mtot + 255) / 256;
   omega_count_kernel<<<nb, 256, 0, st>>>(g.Mtot, b.mask, b.image, b.omega_blk, b.scal);
   omega_scan_kernel<<<1, 1024, 0, st>>>(nb, b.omega_blk, b.scal);
-  omega_write_kernel<<<nb, 256, 0, st>>>(g.Mtot, b.mask, b.omega_blk, b.omega);
+  omega_write_kernel<<<nb, 256, 0, st>>>(g, b.mask, b.omega_blk, b.omega, b.omega_c);
   return hipGetLastError();
 }
 
 hipError_t launch_slots(const Geom& g, const Buffers& b, int Npad, int Jcap4, hipStream_t st) {
   slots_kernel<<<Npad / 256, 256, 0, st>>>(g, b.image, b.poff, b.obs_bits, b.obs_count, b.perm,
-                                           b.obs_idx, b.obs_val, b.wave_J, Npad, Jcap4);
+                                           b.obs_idx, b.obs_val, b.block_J, Npad, Jcap4);
   return hipGetLastError();
 }
 

@@ -1,8 +1,9 @@
 // Overlap-averaged reconstruction and conversions of the sampler state.
 //
-// recon_patch_kernel: one lane per slot computes the patch model
-//   y_i = D^T w_i (P values) from its active list and stores it pixel-major,
-//   Y[p][i], so that neighbouring output pixels read neighbouring patches.
+// recon_patch_kernel: the patch models y_i = D^T w_i, one thread per (patch,
+//   run of 16 in-patch offsets) reading the patch's active list once; stored
+//   pixel-major, Y[p][i], so that neighbouring output pixels read
+//   neighbouring patches.
 // recon_pixel_kernel: one thread per image pixel q sums Y[p][i] over every
 //   patch i and in-patch offset p with o_i + b(p) = q, in ascending p, and
 //   divides by the number of such pairs (the coverage of q).
@@ -10,24 +11,37 @@
 
 namespace bpfa {
 
+constexpr int kReconChunk = 16;   // in-patch offsets per thread
+
+// thread (chunk c, slot s): y_i[p] for p in [16 c, 16 c + 16), one pass over the entries
 __global__ __launch_bounds__(256) void recon_patch_kernel(Geom g, const float* __restrict__ D,
-                                                          const uint32_t* __restrict__ perm,
+                                                          const int32_t* __restrict__ inv_perm,
                                                           const int2* __restrict__ list,
                                                           const int32_t* __restrict__ nact,
                                                           float* __restrict__ Y) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.N) return;
-  const int i = (int)perm[s];
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(t % g.N);
+  const int c = (int)(t / g.N);
+  const int p0 = c * kReconChunk;
+  if (p0 >= g.P) return;
+  const int s = inv_perm[i];
   const int na = nact[s];
   const int2* L = list + (size_t)s * g.K;
-  for (int p = 0; p < g.P; ++p) {
-    float acc = 0.f;
-    for (int a = 0; a < na; ++a) {
-      const int2 e = L[a];
-      acc = fmaf(D[(size_t)e.x * g.P + p], __int_as_float(e.y), acc);
-    }
-    Y[(size_t)p * g.N + i] = acc;
+  float acc[kReconChunk];
+#pragma unroll
+  for (int u = 0; u < kReconChunk; ++u) acc[u] = 0.f;
+  const bool full = p0 + kReconChunk <= g.P;
+  for (int a = 0; a < na; ++a) {
+    const int2 e = L[a];
+    const float w = __int_as_float(e.y);
+    const float* row = D + (size_t)e.x * g.P + p0;
+#pragma unroll
+    for (int u = 0; u < kReconChunk; ++u)
+      if (full || p0 + u < g.P) acc[u] = fmaf(row[u], w, acc[u]);
   }
+#pragma unroll
+  for (int u = 0; u < kReconChunk; ++u)
+    if (full || p0 + u < g.P) Y[(size_t)(p0 + u) * g.N + i] = acc[u];
 }
 
 __global__ __launch_bounds__(256) void recon_pixel_kernel(Geom g, const int32_t* __restrict__ pcoord,
@@ -63,8 +77,9 @@ __global__ __launch_bounds__(256) void recon_pixel_kernel(Geom g, const int32_t*
 hipError_t launch_recon(const Geom& g, const Buffers& b, int cur, int Npad, float* out,
                         hipStream_t st) {
   (void)Npad;
-  recon_patch_kernel<<<(g.N + 255) / 256, 256, 0, st>>>(g, b.D, b.perm, b.list[cur], b.nact[cur],
-                                                        b.Y);
+  const long long n = (long long)g.N * ((g.P + kReconChunk - 1) / kReconChunk);
+  recon_patch_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(g, b.D, b.inv_perm, b.list[cur],
+                                                                  b.nact[cur], b.Y);
   recon_pixel_kernel<<<(g.Mtot + 255) / 256, 256, 0, st>>>(g, b.pcoord, b.Y, out);
   return hipGetLastError();
 }
@@ -127,6 +142,30 @@ hipError_t launch_dense_to_lists(const Geom& g, const Buffers& b, int cur, int N
   (void)Npad;
   dense_to_lists_kernel<<<(g.N + 255) / 256, 256, 0, st>>>(g, b.inv_perm, W, Z, b.list[cur],
                                                            b.nact[cur], bad);
+  return hipGetLastError();
+}
+
+// codes kept across a new frame: slot rows move from the previous slot order to the new one
+__global__ __launch_bounds__(256) void remap_lists_kernel(Geom g, const int32_t* __restrict__ prev_inv,
+                                                          const int32_t* __restrict__ inv_perm,
+                                                          const int2* __restrict__ list_in,
+                                                          const int32_t* __restrict__ nact_in,
+                                                          int2* __restrict__ list_out,
+                                                          int32_t* __restrict__ nact_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  const int so = prev_inv[i], sn = inv_perm[i];
+  const int na = nact_in[so];
+  const int2* src = list_in + (size_t)so * g.K;
+  int2* dst = list_out + (size_t)sn * g.K;
+  for (int a = 0; a < na; ++a) dst[a] = src[a];
+  nact_out[sn] = na;
+}
+
+hipError_t launch_remap_lists(const Geom& g, const Buffers& b, int cur, hipStream_t st) {
+  remap_lists_kernel<<<(g.N + 255) / 256, 256, 0, st>>>(g, b.inv_prev, b.inv_perm, b.list[cur],
+                                                        b.nact[cur], b.list[1 - cur],
+                                                        b.nact[1 - cur]);
   return hipGetLastError();
 }
 

@@ -51,16 +51,30 @@ __global__ __launch_bounds__(256) void scalars_kernel(Geom g, double a, double b
   __shared__ long long s_z;
   __shared__ int s_bad;
   __shared__ double s_min[256], s_max[256], s_sum[256];
+  __shared__ long long s_zp[256];
   const int K = g.K, tid = threadIdx.x;
   const uint32_t t = (uint32_t)scal->t;
+  // sum(z) and the residual sum of squares: strided partials, fixed-order tree
+  long long zp = 0;
+  double rp = 0.0;
+  for (int k = tid; k < K; k += 256) zp += nk[k];
+  if (learn_dict)
+    for (int p = tid; p < g.P; p += 256) rp += sumr2_p[p];
+  s_zp[tid] = zp;
+  s_sum[tid] = rp;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) {
+      s_zp[tid] += s_zp[tid + o];
+      s_sum[tid] += s_sum[tid + o];
+    }
+    __syncthreads();
+  }
   if (tid == 0) {
-    long long z = 0;
-    for (int k = 0; k < K; ++k) z += nk[k];
-    s_z = z;
+    s_z = s_zp[0];
     double sr2 = scal->sum_r2_sweep;
     if (learn_dict) {
-      sr2 = 0.0;
-      for (int p = 0; p < g.P; ++p) sr2 += sumr2_p[p];
+      sr2 = s_sum[0];
       scal->sum_r2_dict = sr2;
     }
     s_sr2 = sr2;
@@ -108,12 +122,18 @@ __global__ __launch_bounds__(256) void scalars_kernel(Geom g, double a, double b
   s_max[tid] = mx;
   s_sum[tid] = sm;
   __syncthreads();
-  if (tid == 0) {
-    for (int i = 1; i < 256; ++i) {
-      mn = fmin(mn, s_min[i]);
-      mx = fmax(mx, s_max[i]);
-      sm += s_sum[i];
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) {
+      s_min[tid] = fmin(s_min[tid], s_min[tid + o]);
+      s_max[tid] = fmax(s_max[tid], s_max[tid + o]);
+      s_sum[tid] += s_sum[tid + o];
     }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    mn = s_min[0];
+    mx = s_max[0];
+    sm = s_sum[0];
     int st = s_bad;
     if (!isfinite(gs) || !(gs > 0.0) || !isfinite(ge) || !(ge > 0.0) || !isfinite(s_sr2)) st |= 1;
     scal->status |= st;
@@ -164,6 +184,13 @@ hipError_t launch_reset_scalars(const Geom& g, const Buffers& b, double ell0, do
                                 double gamma_eps0, hipStream_t st) {
   reset_scalars_kernel<<<1, 256, 0, st>>>(g.K, ell0, gamma_s0, gamma_eps0, b.ell, b.sw_cnt,
                                           b.scal);
+  return hipGetLastError();
+}
+
+__global__ void set_t_kernel(DevScalars* scal, long long t) { scal->t = t; }
+
+hipError_t launch_set_t(DevScalars* scal, long long t, hipStream_t st) {
+  set_t_kernel<<<1, 1, 0, st>>>(scal, t);
   return hipGetLastError();
 }
 

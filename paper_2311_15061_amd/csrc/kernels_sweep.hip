@@ -10,20 +10,34 @@
 // evaluated in the equivalent form u sqrt(lam) < (1 - u) exp(C_k + q) with
 // C_k = ell_k + ln(gamma_s) / 2 and q = (gamma_eps rho)^2 / (2 lam).
 //
-// Mapping onto gfx950: one lane per patch, 64 patches per wavefront, 8
-// wavefronts per block.  A lane keeps its patch's residual on the observed
-// pixels in VGPRs for the whole atom loop; the dictionary tile sits in LDS
-// pixel-major with an odd atom stride (column p of atom k at p * KS + k), so
-// the per-lane gathers d_{k, p_j} hit different banks.  Padding slots of the
-// observed list point at a zero row.  Inner loops run to the wavefront's
-// largest |Obs| (uniform), in steps of four.  One Philox block serves two
-// atoms: two z uniforms and one Box-Muller pair.  Active atoms are carried
-// between iterations as per-patch lists (atom, weight) in ascending atom
-// order, so the sweep streams only what is non-zero.
+// Mapping onto gfx950:
+//  * one lane per patch, 64 patches per wavefront, 4 wavefronts per block
+//    sharing one LDS copy of the dictionary tile (three blocks fit a CU's
+//    LDS for 10 x 10 patches and 128 atoms);
+//  * slots are sorted by |Obs(i)| once per frame, so every block has one
+//    register count J (|Obs| of its last slot, rounded up to 4) and runs a
+//    body compiled for exactly that J: the residual on the observed pixels
+//    lives in J VGPRs for the whole atom loop, with no per-element guards;
+//  * the tile is pixel-major with an odd atom stride (d_kp at p * KS + k):
+//    a lane's gathers for its observed pixels hit different banks, and the
+//    values of atoms k and k+1 at one pixel are adjacent, so one ds_read2
+//    serves a pair of atoms;
+//  * atoms go in pairs: one pass gives delta and rho of both atoms and the
+//    cross term g = sum d_k d_{k+1}; after atom k's draw the pair's second rho
+//    is corrected by -(w_new - w_old) g, exactly the effect of the residual
+//    update on it; the residual takes both updates in one second pass;
+//  * one Philox block per pair: two z uniforms and one Box-Muller pair;
+//  * active atoms travel between iterations as per-patch lists
+//    (atom, weight) in ascending atom order.
 #include "internal.hpp"
 #include "philox.hpp"
 
 namespace bpfa {
+
+typedef __attribute__((address_space(3))) float lds_f;
+
+constexpr float kLn2 = 0.69314718055994531f;
+constexpr float kLog2e = 1.44269504088896341f;
 
 __device__ __forceinline__ void load_tile(const SweepArgs& a, float* lds, int k0, int k1) {
   const int kt = k1 - k0;
@@ -32,88 +46,58 @@ __device__ __forceinline__ void load_tile(const SweepArgs& a, float* lds, int k0
     const int kk = idx / a.P, p = idx - kk * a.P;
     lds[p * a.KS + kk] = a.D[(size_t)(k0 + kk) * a.P + p];
   }
+  // zero columns kt .. KS-1 of every row and the whole padding row p = P
+  const int padc = a.KS - kt;
+  for (int idx = threadIdx.x; idx < a.P * padc; idx += kSweepBlock) {
+    const int p = idx / padc, kk = kt + (idx - p * padc);
+    lds[p * a.KS + kk] = 0.f;
+  }
   for (int kk = threadIdx.x; kk < a.KS; kk += kSweepBlock) lds[a.P * a.KS + kk] = 0.f;
 }
 
-template <int JMAX>
-struct LaneState {
-  int addr[JMAX];   // LDS float index of column p_j (p_j * KS)
-  float r[JMAX];    // residual on observed pixel j
-};
-
-template <int JMAX>
-__device__ __forceinline__ void dot_delta_rho(const LaneState<JMAX>& ls, const float* __restrict__ col,
-                                              int Jw, float& delta, float& rho) {
-  float d0 = 0.f, d1 = 0.f, r0 = 0.f, r1 = 0.f;
-#pragma unroll
-  for (int j0 = 0; j0 < JMAX; j0 += 4) {
-    if (j0 < Jw) {
-      const float a0 = col[ls.addr[j0 + 0]], a1 = col[ls.addr[j0 + 1]];
-      const float a2 = col[ls.addr[j0 + 2]], a3 = col[ls.addr[j0 + 3]];
-      d0 = fmaf(a0, a0, d0);
-      r0 = fmaf(a0, ls.r[j0 + 0], r0);
-      d1 = fmaf(a1, a1, d1);
-      r1 = fmaf(a1, ls.r[j0 + 1], r1);
-      d0 = fmaf(a2, a2, d0);
-      r0 = fmaf(a2, ls.r[j0 + 2], r0);
-      d1 = fmaf(a3, a3, d1);
-      r1 = fmaf(a3, ls.r[j0 + 3], r1);
-    }
-  }
-  delta = d0 + d1;
-  rho = r0 + r1;
-}
-
-template <int JMAX>
-__device__ __forceinline__ void residual_axpy(LaneState<JMAX>& ls, const float* __restrict__ col,
-                                              int Jw, float c) {
-#pragma unroll
-  for (int j0 = 0; j0 < JMAX; j0 += 4) {
-    if (j0 < Jw) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) ls.r[j0 + u] = fmaf(-col[ls.addr[j0 + u]], c, ls.r[j0 + u]);
-    }
-  }
-}
-
-template <int JMAX>
-__global__ __launch_bounds__(kSweepBlock) void sweep_kernel(SweepArgs a) {
+// J registers of residual; GUARD: J is an upper bound and Jrt the real count
+template <int J, bool GUARD>
+__device__ __forceinline__ void sweep_block(const SweepArgs& a, int blk, int Jrt) {
   extern __shared__ float lds[];
-  int* cnt_lds = reinterpret_cast<int*>(lds + (a.P + 1) * a.KS);
+  uint8_t* cnt_lds = reinterpret_cast<uint8_t*>(lds + (a.P + 1) * a.KS);  // [wave][K] z counts
   __shared__ double s_w2[kSweepBlock / kWave], s_r2[kSweepBlock / kWave];
   __shared__ long long s_z[kSweepBlock / kWave];
   __shared__ float s_wm[kSweepBlock / kWave];
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-  const int s = blockIdx.x * kSweepBlock + tid;
+  const int s = blk * kSweepBlock + tid;
   const bool valid = s < a.N;
   const float gs = (float)a.scal->gamma_s;
   const float ge = (float)a.scal->gamma_eps;
   const uint32_t t = (uint32_t)a.scal->t;
-  const int Jw = __builtin_amdgcn_readfirstlane(a.wave_J[s / kWave]);
   const uint32_t ip = a.perm[s];
+  const int K = a.K;
 
-  LaneState<JMAX> ls;
+  lds_f* const L = (lds_f*)lds;
+  lds_f* col[J];     // column p_j of the tile (p_j = P: the zero row)
+  float r[J];        // residual on observed pixel j
 #pragma unroll
-  for (int j = 0; j < JMAX; ++j) {
-    if (j < Jw) {
-      ls.addr[j] = (int)a.obs_idx[(size_t)j * a.Npad + s] * a.KS;
-      ls.r[j] = a.obs_val[(size_t)j * a.Npad + s];
-    } else {
-      ls.addr[j] = a.P * a.KS;
-      ls.r[j] = 0.f;
+  for (int j = 0; j < J; ++j) {
+    int p = a.P;
+    float x = 0.f;
+    if (!GUARD || j < Jrt) {
+      p = a.obs_idx[(size_t)j * a.Npad + s];
+      x = a.obs_val[(size_t)j * a.Npad + s];
     }
+    col[j] = L + p * a.KS;
+    r[j] = x;
   }
-  for (int k = tid; k < a.K; k += kSweepBlock) cnt_lds[k] = 0;
+  uint8_t* const cnt_w = cnt_lds + wid * K;
+  const float* __restrict__ Ck = a.Ck;
 
-  const int ntiles = (a.K + a.KT - 1) / a.KT;
+  const int ntiles = (K + a.KT - 1) / a.KT;
   const int na = valid ? a.nact_in[s] : 0;
-  const int2* __restrict__ lin = a.list_in + (size_t)s * a.K;
+  const int2* __restrict__ lin = a.list_in + (size_t)s * K;
 
   // pass 1: residual of the previous sample, r = x - sum_k d_k w_k on Obs(i)
   int ia = 0;
   for (int tile = 0; tile < ntiles; ++tile) {
-    const int k0 = tile * a.KT, k1 = min(a.K, k0 + a.KT);
+    const int k0 = tile * a.KT, k1 = min(K, k0 + a.KT);
     __syncthreads();
     load_tile(a, lds, k0, k1);
     __syncthreads();
@@ -124,75 +108,103 @@ __global__ __launch_bounds__(kSweepBlock) void sweep_kernel(SweepArgs a) {
       more = more && e.x < k1;
       if (!__any(more)) break;
       if (more) {
-        residual_axpy<JMAX>(ls, lds + (e.x - k0), Jw, __int_as_float(e.y));
+        const float w = __int_as_float(e.y);
+        const int ko = e.x - k0;
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+          if (!GUARD || (j & ~3) < Jrt) r[j] = fmaf(-col[j][ko], w, r[j]);
         ++ia;
       }
     }
   }
 
   // pass 2: the sweep
-  const int2 sent = make_int2(a.K, 0);
   int cur = 0;
-  int2 e0 = na > 0 ? lin[0] : sent;
-  int2 e1 = na > 1 ? lin[1] : sent;
+  int2 e0 = make_int2(K, 0), e1 = make_int2(K, 0);
+  if (na > 0) e0 = lin[0];
+  if (na > 1) e1 = lin[1];
   int nout = 0;
-  int2* __restrict__ lout = a.list_out + (size_t)s * a.K;
+  int2* __restrict__ lout = a.list_out + (size_t)s * K;
   float sw2 = 0.f, wmx = 0.f;
 
-  auto atom = [&](int k, int k0, float uz, float n) {
-    const float* col = lds + (k - k0);
-    float delta, rho;
-    dot_delta_rho<JMAX>(ls, col, Jw, delta, rho);
-    const bool hit = e0.x == k;
-    const float wold = hit ? __int_as_float(e0.y) : 0.f;
-    if (hit) {
+  // one atom: decision and weight given its delta and rho (own term not yet added)
+  auto decide = [&](int k, float delta, float rho, float uz, float n) -> float {
+    float wold = 0.f;
+    if (e0.x == k) {
+      wold = __int_as_float(e0.y);
       e0 = e1;
       ++cur;
-      e1 = (cur + 1 < na) ? lin[cur + 1] : sent;
+      e1 = make_int2(K, 0);
+      if (cur + 1 < na) e1 = lin[cur + 1];
     }
     rho = fmaf(delta, wold, rho);
     const float lam = fmaf(ge, delta, gs);
-    const float rs = __frsqrt_rn(lam);
+    const float rs = __builtin_amdgcn_rsqf(lam);
     const float ger = ge * rho;
     const float mean = ger * rs * rs;
     const float q = 0.5f * ger * mean;
     const float lhs = uz * lam * rs;
-    const float rhs = (1.f - uz) * __expf(a.Ck[k] + q);
+    const float rhs = (1.f - uz) * __builtin_amdgcn_exp2f((Ck[k] + q) * kLog2e);
     const bool z = valid && (lhs < rhs);
     const float snew = z ? fmaf(n, rs, mean) : 0.f;
-    const float dw = snew - wold;
-    if (dw != 0.f) residual_axpy<JMAX>(ls, col, Jw, dw);
     if (z) {
       lout[nout++] = make_int2(k, __float_as_int(snew));
       sw2 = fmaf(snew, snew, sw2);
       wmx = fmaxf(wmx, fabsf(snew));
     }
-    const unsigned long long bal = __ballot(z);
-    if (lane == 0 && bal) atomicAdd(&cnt_lds[k], (int)__popcll(bal));
+    const int nz = (int)__popcll(__ballot(z));
+    if (lane == 0) cnt_w[k] = (uint8_t)nz;   // every (wave, atom) is visited exactly once
+    return snew - wold;
   };
 
   for (int tile = 0; tile < ntiles; ++tile) {
-    const int k0 = tile * a.KT, k1 = min(a.K, k0 + a.KT);
+    const int k0 = tile * a.KT, k1 = min(K, k0 + a.KT);
     if (ntiles > 1) {
       __syncthreads();
       load_tile(a, lds, k0, k1);
       __syncthreads();
     }
     for (int k = k0; k < k1; k += 2) {
+      const int ko = k - k0;
       const Block4 rb = philox10(ip, (uint32_t)(k >> 1), t, a.stream, a.key0, a.key1);
-      const float rad = sqrtf(-2.f * __logf(u01f(rb.w2)));
+      float dl0 = 0.f, dl1 = 0.f, rh0 = 0.f, rh1 = 0.f, g01 = 0.f;
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        if (!GUARD || (j & ~3) < Jrt) {
+          const float x0 = col[j][ko], x1 = col[j][ko + 1];
+          dl0 = fmaf(x0, x0, dl0);
+          dl1 = fmaf(x1, x1, dl1);
+          rh0 = fmaf(x0, r[j], rh0);
+          rh1 = fmaf(x1, r[j], rh1);
+          g01 = fmaf(x0, x1, g01);
+        }
+      }
+      const float u2 = u01f(rb.w2);
+      const float rad = __builtin_amdgcn_sqrtf(-2.f * kLn2 * __builtin_amdgcn_logf(u2));
       const float ang = u01f(rb.w3);                 // revolutions
       const float n0 = rad * __builtin_amdgcn_cosf(ang);
       const float n1 = rad * __builtin_amdgcn_sinf(ang);
-      atom(k, k0, u01f(rb.w0), n0);
-      if (k + 1 < k1) atom(k + 1, k0, u01f(rb.w1), n1);
+      const float dw0 = decide(k, dl0, rh0, u01f(rb.w0), n0);
+      float dw1 = 0.f;
+      if (k + 1 < k1) dw1 = decide(k + 1, dl1, fmaf(-dw0, g01, rh1), u01f(rb.w1), n1);
+      // re-read the pair's columns rather than keep 2 J values live across the draws
+      asm volatile("" ::: "memory");
+      if (dw0 != 0.f || dw1 != 0.f) {
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          if (!GUARD || (j & ~3) < Jrt) {
+            const float x0 = col[j][ko], x1 = col[j][ko + 1];
+            r[j] = fmaf(-x1, dw1, fmaf(-x0, dw0, r[j]));
+          }
+        }
+      }
     }
   }
 
   if (valid) a.nact_out[s] = nout;
   float r2 = 0.f;
 #pragma unroll
-  for (int j = 0; j < JMAX; ++j) r2 = fmaf(ls.r[j], ls.r[j], r2);
+  for (int j = 0; j < J; ++j) r2 = fmaf(r[j], r[j], r2);
 
   // deterministic block partials: fixed butterfly, then waves in order
   double dw2 = (double)sw2, dr2 = (double)r2;
@@ -212,48 +224,87 @@ __global__ __launch_bounds__(kSweepBlock) void sweep_kernel(SweepArgs a) {
   }
   __syncthreads();
   if (tid == 0) {
-    SweepPart p{0.0, 0.0, 0, 0.f, 0};
+    SweepPart pt{0.0, 0.0, 0, 0.f, 0};
     for (int w = 0; w < kSweepBlock / kWave; ++w) {
-      p.sum_w2 += s_w2[w];
-      p.sum_r2 += s_r2[w];
-      p.sum_z += s_z[w];
-      p.wmax = fmaxf(p.wmax, s_wm[w]);
+      pt.sum_w2 += s_w2[w];
+      pt.sum_r2 += s_r2[w];
+      pt.sum_z += s_z[w];
+      pt.wmax = fmaxf(pt.wmax, s_wm[w]);
     }
-    a.part[blockIdx.x] = p;
+    a.part[blk] = pt;
   }
-  for (int k = tid; k < a.K; k += kSweepBlock) {
-    const int c = cnt_lds[k];
+  for (int k = tid; k < K; k += kSweepBlock) {
+    int c = 0;
+    for (int w = 0; w < kSweepBlock / kWave; ++w) c += cnt_lds[w * K + k];
     if (c) atomicAdd(&a.cnt[k], c);
   }
 }
 
-hipError_t launch_sweep(int JMAX, int blocks, size_t lds, const SweepArgs& a, hipStream_t st) {
-  switch (JMAX) {
-#define BPFA_SWEEP_CASE(J) \
-  case J: {                                                                            \
-    hipError_t e_ = hipFuncSetAttribute((const void*)sweep_kernel<J>,                   \
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
-    if (e_ != hipSuccess) return e_;                                                    \
-    sweep_kernel<J><<<blocks, kSweepBlock, lds, st>>>(a);                               \
-    break;                                                                              \
+// per-block dispatch onto bodies compiled for exactly J = JLO, JLO+4, .., JHI
+template <int J, int JHI>
+__device__ __forceinline__ void dispatch_exact(const SweepArgs& a, int blk, int Jb) {
+  if constexpr (J <= JHI) {
+    if (Jb <= J) sweep_block<J, false>(a, blk, J);
+    else dispatch_exact<J + 4, JHI>(a, blk, Jb);
   }
-    BPFA_SWEEP_CASE(8)
-    BPFA_SWEEP_CASE(16)
-    BPFA_SWEEP_CASE(24)
-    BPFA_SWEEP_CASE(32)
-    BPFA_SWEEP_CASE(48)
-    BPFA_SWEEP_CASE(64)
-    BPFA_SWEEP_CASE(96)
-    BPFA_SWEEP_CASE(128)
-    BPFA_SWEEP_CASE(256)
-#undef BPFA_SWEEP_CASE
-    default:
-      return hipErrorInvalidValue;
-  }
+}
+
+template <int JLO, int JHI>
+__global__ __launch_bounds__(kSweepBlock) void sweep_exact_kernel(SweepArgs a, int block0) {
+  const int blk = block0 + (int)blockIdx.x;
+  dispatch_exact<JLO, JHI>(a, blk, a.block_J[blk]);
+}
+
+template <int JMAX>
+__global__ __launch_bounds__(kSweepBlock) void sweep_guarded_kernel(SweepArgs a, int block0) {
+  const int blk = block0 + (int)blockIdx.x;
+  sweep_block<JMAX, true>(a, blk, a.block_J[blk]);
+}
+
+template <typename F>
+static hipError_t launch_with_lds(F kernel, int blocks, size_t lds, const SweepArgs& a, int block0,
+                                  hipStream_t st) {
+  hipError_t e = hipFuncSetAttribute((const void*)kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  kernel<<<blocks, kSweepBlock, lds, st>>>(a, block0);
   return hipGetLastError();
 }
 
+// Blocks are in ascending J.  Ranges: J <= 16, J <= 32, J <= 64 run exact
+// bodies (each range its own kernel, so its own register allocation); larger
+// J run guarded bodies (128 or 256 registers).  Every range goes to its own
+// stream and the ranges start in descending J: a block's atom loop is
+// sequential, so the few long high-J blocks must overlap the bulk instead of
+// trailing it.
+hipError_t launch_sweep(const SweepLaunch& sl, size_t lds, const SweepArgs& a,
+                        const hipStream_t* streams) {
+  hipError_t e = hipSuccess;
+  for (int r = kSweepRanges - 1; r >= 0 && e == hipSuccess; --r) {
+    const int b0 = sl.block0[r], nb = sl.block0[r + 1] - sl.block0[r];
+    if (nb <= 0) continue;
+    const hipStream_t st = streams[r];
+    switch (r) {
+      case 0: e = launch_with_lds(sweep_exact_kernel<4, 16>, nb, lds, a, b0, st); break;
+      case 1: e = launch_with_lds(sweep_exact_kernel<20, 32>, nb, lds, a, b0, st); break;
+      case 2: e = launch_with_lds(sweep_exact_kernel<36, 64>, nb, lds, a, b0, st); break;
+      case 3: e = launch_with_lds(sweep_guarded_kernel<128>, nb, lds, a, b0, st); break;
+      default: e = launch_with_lds(sweep_guarded_kernel<256>, nb, lds, a, b0, st); break;
+    }
+  }
+  return e;
+}
+
 // ---- reduction of the sweep's block partials (fixed order) ---------------
+
+// largest power of two s with bound * s <= 2^50 and n * bound * s < 2^62
+__device__ double fixed_scale(double bound, double n) {
+  if (!(bound > 0.0) || !isfinite(bound)) return 1.0;
+  int e1, e2;
+  frexp(bound, &e1);        // bound < 2^e1
+  frexp(bound * n, &e2);    // n * bound < 2^e2
+  return ldexp(1.0, min(50 - e1, 62 - e2));
+}
 
 __global__ __launch_bounds__(256) void sweep_reduce_kernel(int blocks, const SweepPart* __restrict__ part,
                                                            DevScalars* scal) {
@@ -275,28 +326,27 @@ __global__ __launch_bounds__(256) void sweep_reduce_kernel(int blocks, const Swe
   s_z[threadIdx.x] = z;
   s_m[threadIdx.x] = m;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 1; i < 256; ++i) {
-      w2 += s_w2[i];
-      r2 += s_r2[i];
-      z += s_z[i];
-      m = fmaxf(m, s_m[i]);
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      s_w2[threadIdx.x] += s_w2[threadIdx.x + o];
+      s_r2[threadIdx.x] += s_r2[threadIdx.x + o];
+      s_z[threadIdx.x] += s_z[threadIdx.x + o];
+      s_m[threadIdx.x] = fmaxf(s_m[threadIdx.x], s_m[threadIdx.x + o]);
     }
-    scal->sum_w2 = w2;
-    scal->sum_r2_sweep = r2;
-    scal->sum_z = z;
-    scal->wmax = m;
-    // fixed-point scales of the dictionary statistics: every accumulated sum
-    // stays below 2^61 in magnitude
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    scal->sum_w2 = s_w2[0];
+    scal->sum_r2_sweep = s_r2[0];
+    scal->sum_z = s_z[0];
+    scal->wmax = s_m[0];
+    // fixed-point scales of the dictionary statistics: each rounded term
+    // stays below 2^50 in magnitude (exact rounding by the 1.5 * 2^52 add)
+    // and every sum of at most n_omega terms below 2^62
     const double nv = (double)max(scal->n_omega, 1);
-    const double wm = (double)m, ym = (double)scal->ymax;
-    int ex;
-    const double bc = nv * wm * wm;
-    frexp(bc, &ex);
-    scal->scale_c = bc > 0.0 ? ldexp(1.0, 61 - ex) : 1.0;
-    const double bb = nv * wm * ym;
-    frexp(bb, &ex);
-    scal->scale_b = bb > 0.0 ? ldexp(1.0, 61 - ex) : 1.0;
+    const double wm = (double)s_m[0], ym = (double)scal->ymax;
+    scal->scale_c = fixed_scale(wm * wm, nv);
+    scal->scale_b = fixed_scale(wm * ym, nv);
   }
 }
 

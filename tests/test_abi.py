@@ -8,7 +8,7 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "bpfa.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("bpfa.h", "bpfa_serve.h")]
 
 
 @pytest.fixture(scope="module")
@@ -21,9 +21,16 @@ def bpfa():
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(bpfa_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(bpfa_[a-z_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_headers_are_all_listed():
+    import glob
+    assert sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))) == sorted(HEADERS)
 
 
 def test_every_declared_symbol_is_exported(bpfa):
@@ -32,22 +39,28 @@ def test_every_declared_symbol_is_exported(bpfa):
     lib = ctypes.CDLL(bpfa.LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
-    assert sorted(bpfa.EXPORTED) == names
+    from paper_2311_15061_amd import serve
+    assert sorted(bpfa.EXPORTED + serve.EXPORTED) == names
 
 
 def test_struct_layouts_match_c(bpfa, tmp_path):
     src = tmp_path / "sz.c"
-    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "bpfa.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(bpfa_params),'
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "bpfa_serve.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(bpfa_params),'
                    ' offsetof(bpfa_params, stream), sizeof(bpfa_state_view),'
-                   ' offsetof(bpfa_state_view, mem), sizeof(bpfa_stats), offsetof(bpfa_stats, n_sweeps));'
+                   ' offsetof(bpfa_state_view, mem), sizeof(bpfa_stats), offsetof(bpfa_stats, n_sweeps),'
+                   ' sizeof(bpfa_server_params), offsetof(bpfa_server_params, device),'
+                   ' sizeof(bpfa_serve_result), sizeof(bpfa_serve_stats));'
                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
                                           check=True).stdout.split()]
+    from paper_2311_15061_amd import serve
     want = [ctypes.sizeof(bpfa.Params), bpfa.Params.stream.offset, ctypes.sizeof(bpfa.StateView),
-            bpfa.StateView.mem.offset, ctypes.sizeof(bpfa.Stats), bpfa.Stats.n_sweeps.offset]
+            bpfa.StateView.mem.offset, ctypes.sizeof(bpfa.Stats), bpfa.Stats.n_sweeps.offset,
+            ctypes.sizeof(serve.ServerParams), serve.ServerParams.device.offset,
+            ctypes.sizeof(serve.ServeResult), ctypes.sizeof(serve.ServeStats)]
     assert got == want
 
 

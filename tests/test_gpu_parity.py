@@ -146,6 +146,9 @@ def test_sparse_code_only_parity():
     ((40, 36), (6, 5), (1, 1), 20, 0.2),          # ragged grid, odd K
     ((30, 30), (10, 10), (1, 1), 200, 0.15),      # several LDS tiles, two statistics row groups
     ((20, 18, 8), (4, 4, 2), (1, 1, 2), 24, 0.25),  # 3-D video patches with a time stride
+    ((26, 26), (12, 12), (1, 1), 16, 0.35),       # |Obs| ~ 50: 36..64 register bodies
+    ((22, 22), (12, 12), (1, 1), 12, 0.65),       # |Obs| ~ 94: guarded 128-register bodies
+    ((28, 28), (12, 12), (1, 1), 20, 0.2),        # |Obs| spread over three ranges at once
 ])
 def test_parity_geometry_cases(shape, patch, stride, K, rho):
     y, m, g = case(shape, patch, stride, K, rho, seed=K)
@@ -153,6 +156,32 @@ def test_parity_geometry_cases(shape, patch, stride, K, rho):
     xh = prob.reconstruct()
     ref = ob.reconstruct(st, shape, patch, stride)
     assert_close(xh, ref, FP32_TOL, "reconstruction")
+    prob.close()
+
+
+def test_new_frame_keeps_codes():
+    """set_frame without resetting codes: every patch keeps its (z, s) across a new mask."""
+    wl = synth.workload("lattice64")
+    y, m, g = synth.make_frame(wl)
+    y2, m2, _ = synth.make_frame(wl, data_seed=99, rho=0.3)
+    prob = gpu_problem(y, m, wl.patch, wl.stride, wl.K, wl.method_seed)
+    prob.iterate(2)
+    before = prob.get_state()
+    prob.set_frame(y2.astype(np.float32), m2, reset_codes=False)
+    after = prob.get_state()
+    for k in ("D", "W", "Z", "logit_pi"):
+        assert np.array_equal(before[k], after[k]), k
+    prm, X, Mk = oracle_problem(y2, m2, wl.patch, wl.stride, wl.K, wl.method_seed)
+    st = ob.State(D=after["D"].astype(np.float64), W=after["W"].astype(np.float64),
+                  Z=after["Z"].astype(bool), ell=after["logit_pi"], gamma_s=after["gamma_s"],
+                  gamma_eps=after["gamma_eps"], t=after["t"])
+    prob.iterate(1)
+    gs = prob.get_state()
+    st, rep = ob.iterate(prm, X, Mk, st, follow_z=gs["Z"])
+    assert rep.hard_mismatches == 0
+    compare_state(gs, st, FP32_TOL, "kept codes")
+    prob.set_frame(y2.astype(np.float32), m2, reset_codes=True)
+    assert not prob.get_state()["Z"].any()
     prob.close()
 
 
