@@ -88,6 +88,87 @@ def cpu_baseline(wl, y, m, iters):
                       % (iters, wl.name, N, wl.K, dt, threads)}
 
 
+def serving_run(duration_s=8.0, rate=30.0, n_streams=4, seed=7, saturate_frames=48):
+    """Live-feed serving: Poisson arrivals at `rate` frames/s over `n_streams`
+    streams, sizes uniform over 256^2 / 512^2 / 1024^2, sampled fraction
+    U[5%, 25%] per frame, K = 128 10 x 10 dictionary learned on a separate
+    512^2 frame (20 iterations) and transferred to every stream; 5
+    sparse-coding iterations per frame plus a dictionary iteration every 10th
+    frame of a stream.  Then a saturation run submits `saturate_frames` at
+    once.  Frame contents are drawn from a few seeded lattice images per size
+    with a fresh mask per frame."""
+    import numpy as np
+    from paper_2311_15061_amd import bpfa, serve
+    import synth
+    base = synth.workload("stem512")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    images = {}
+    for side in synth.lattice.SERVING_SIZES:
+        images[side] = [synth.make_frame(base, data_seed=5000 + side + j, shape=(side, side))[0]
+                        for j in range(3)]
+    y, m, _ = synth.make_frame(base, data_seed=4242)
+    teacher = bpfa.Problem(y.astype(np.float32), m, base.patch, K=base.K, seed=0xD1C7)
+    teacher.iterate(20)
+    srv = serve.Server(patch=base.patch, K=base.K, n_streams=n_streams, sc_iters=5, dict_every=10,
+                       max_slots=2 * n_streams, hbm_budget=64 << 30, seed=0x5E7E, precision="bf16")
+    for st in range(n_streams):
+        srv.set_dictionary(st, teacher)
+    teacher.close()
+
+    def make_request():
+        side = int(rng.choice(synth.lattice.SERVING_SIZES))
+        img = images[side][int(rng.integers(len(images[side])))]
+        rho = float(rng.uniform(0.05, 0.25))
+        mask = synth.make_mask((side, side), rho, rng)
+        return int(rng.integers(n_streams)), side, img, mask
+
+    # warm start: every frame size once per slot pair, so that slot workspaces exist
+    for j in range(2 * n_streams):
+        side = synth.lattice.SERVING_SIZES[j % len(synth.lattice.SERVING_SIZES)]
+        srv.submit(j % n_streams, images[side][0], synth.make_mask((side, side), 0.1, rng))
+    srv.drain()
+    srv.poll(100000)
+
+    # Poisson arrivals, submitted from this thread at their scheduled times
+    t_arr = np.cumsum(rng.exponential(1.0 / rate, size=int(duration_s * rate * 1.5) + 8))
+    t_arr = t_arr[t_arr < duration_s]
+    reqs = [make_request() for _ in range(len(t_arr))]
+    sizes = {}
+    t0 = time.perf_counter()
+    for when, (st, side, img, mask) in zip(t_arr, reqs):
+        delay = t0 + when - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        ticket, _ = srv.submit(st, img, mask)
+        sizes[ticket] = side
+    srv.drain()
+    wall = time.perf_counter() - t0
+    res = srv.poll(100000)
+    lat = {side: [] for side in synth.lattice.SERVING_SIZES}
+    for r in res:
+        if r["status"] == 0:
+            lat[sizes[r["ticket"]]].append(r["latency_ms"])
+    out = {"arrival_rate": rate, "duration_s": duration_s, "frames": len(res),
+           "failed": sum(1 for r in res if r["status"] != 0),
+           "frames_per_s": len(res) / wall, "streams": n_streams}
+    for side, v in lat.items():
+        if v:
+            out["p50_ms_%d" % side] = float(np.percentile(v, 50))
+            out["p99_ms_%d" % side] = float(np.percentile(v, 99))
+            out["n_%d" % side] = len(v)
+    # saturation: everything at once
+    reqs = [make_request() for _ in range(saturate_frames)]
+    t0 = time.perf_counter()
+    for st, side, img, mask in reqs:
+        srv.submit(st, img, mask)
+    srv.drain()
+    out["saturated_frames_per_s"] = saturate_frames / (time.perf_counter() - t0)
+    srv.poll(100000)
+    out["slot_stats"] = srv.stats()
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +179,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=1, help="oracle iterations timed on the host")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-quality", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-seconds", type=float, default=8.0)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -188,6 +271,10 @@ def main():
         x = out_d.cpu().numpy()
         res["psnr_db"] = metrics.psnr(x, g)
         res["ssim"] = metrics.ssim(x, g)
+    if not args.no_serving:
+        sv = serving_run(duration_s=args.serving_seconds)
+        res["serving"] = sv
+        res["p99_frame_latency_ms_512"] = sv.get("p99_ms_512")
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(wl, y, m, args.cpu_iters)
     prob.close()

@@ -65,6 +65,9 @@ enum {
   BPFA_PRECISION_BF16 = 4u    /* reserved for the BF16 precision form; rejected (EINVAL) */
 };
 
+/* contraction precision of a handle (bpfa_set_precision) */
+enum { BPFA_FP32 = 0u, BPFA_BF16 = 1u };
+
 /* bpfa_transfer_dictionary selectors */
 enum { BPFA_XFER_D = 1u, BPFA_XFER_PI = 2u, BPFA_XFER_GAMMAS = 4u };
 
@@ -157,6 +160,16 @@ bpfa_status bpfa_iterate(bpfa_t h, int32_t n_iters, uint32_t flags);
  * mean of the values D^T w_i that the patches covering it give it.  out holds
  * prod(shape) floats of kind `mem`; host memory synchronises the stream. */
 bpfa_status bpfa_reconstruct(bpfa_t h, float* out, bpfa_mem mem);
+
+/* Precision form of the reconstruction's dense contraction y_i = D^T w_i
+ * (every patch's model, before the overlap average).  BPFA_FP32 (default):
+ * binary32 products and sums on the matrix cores.  BPFA_BF16: every operand
+ * is split into a BF16 head and a BF16 tail; the head product runs on the
+ * BF16 matrix cores with binary32 accumulation and one correction pass adds
+ * the head-tail cross products, so the error stays near 2^-16 of |d||w|.
+ * The sampler (z, s, D, pi, gammas) is binary32 / binary64 in both forms.
+ * Takes effect at the next bpfa_reconstruct.  EINVAL for another value. */
+bpfa_status bpfa_set_precision(bpfa_t h, uint32_t precision);
 
 /* Dictionary transfer between sources (feature summary): copy D (and, as
  * selected, logit pi and the gammas) from src to dst, device to device, on

@@ -45,11 +45,12 @@ typedef struct {
   int32_t max_slots;               /* frames in flight at most (>= 1) */
   uint64_t hbm_budget;             /* bytes of slot workspaces the server may hold */
   int32_t device;
+  int32_t precision;               /* BPFA_FP32 or BPFA_BF16: contraction precision of every slot */
 } bpfa_server_params;
 
 /* Defaults: 2-D 10 x 10 patches stride 1, K = 128, priors as bpfa_params_default,
  * 4 streams, 5 sparse-coding iterations, dictionary every 10 frames, 4 slots,
- * 16 GiB budget, device 0. */
+ * 16 GiB budget, device 0, BF16 precision form. */
 void bpfa_server_params_default(bpfa_server_params* p);
 
 /* Start a server.  EINVAL / ESHAPE for bad parameters, EDEVICE on HIP errors. */

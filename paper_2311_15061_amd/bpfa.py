@@ -17,13 +17,22 @@ OK, EINVAL, ESHAPE, ENOMEM, EDEVICE, ESTATE, ENUMERIC, EBUSY = 0, -1, -2, -3, -4
 HOST, DEVICE = 0, 1
 LEARN_DICT, SPARSE_CODE_ONLY, PRECISION_BF16 = 1, 2, 4
 XFER_D, XFER_PI, XFER_GAMMAS = 1, 2, 4
+FP32, BF16 = 0, 1
 _NAMES = {EINVAL: "EINVAL", ESHAPE: "ESHAPE", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE",
           ESTATE: "ESTATE", ENUMERIC: "ENUMERIC", EBUSY: "EBUSY"}
 
 EXPORTED = ["bpfa_params_default", "bpfa_workspace_size", "bpfa_create", "bpfa_set_frame",
-            "bpfa_reset_state", "bpfa_iterate", "bpfa_reconstruct", "bpfa_transfer_dictionary", "bpfa_get_state",
+            "bpfa_reset_state", "bpfa_iterate", "bpfa_reconstruct", "bpfa_set_precision",
+            "bpfa_transfer_dictionary", "bpfa_get_state",
             "bpfa_set_state", "bpfa_get_stats", "bpfa_set_timing", "bpfa_sync",
             "bpfa_get_patch_index", "bpfa_debug_philox", "bpfa_destroy", "bpfa_last_error"]
+
+
+def precision_code(precision):
+    codes = {"fp32": FP32, "bf16": BF16, FP32: FP32, BF16: BF16}
+    if precision not in codes:
+        raise ValueError("precision must be 'fp32' or 'bf16', got %r" % (precision,))
+    return codes[precision]
 
 
 class BpfaError(RuntimeError):
@@ -82,6 +91,7 @@ def _load():
         "bpfa_reset_state": (ctypes.c_int, [vp]),
         "bpfa_iterate": (ctypes.c_int, [vp, i32, u32]),
         "bpfa_reconstruct": (ctypes.c_int, [vp, vp, ctypes.c_int]),
+        "bpfa_set_precision": (ctypes.c_int, [vp, u32]),
         "bpfa_transfer_dictionary": (ctypes.c_int, [vp, vp, u32]),
         "bpfa_get_state": (ctypes.c_int, [vp, P(StateView)]),
         "bpfa_set_state": (ctypes.c_int, [vp, P(StateView)]),
@@ -240,6 +250,11 @@ class Problem:
         ptr, kind, keep = _buffer(out, np.float32)
         _check(lib.bpfa_reconstruct(self._h, ptr, kind))
         return out
+
+    def set_precision(self, precision):
+        """'fp32' (binary32 contractions) or 'bf16' (BF16 matrix-core contractions with one
+        binary32 correction pass)."""
+        _check(lib.bpfa_set_precision(self._h, precision_code(precision)))
 
     def transfer_dictionary(self, src, what=XFER_D | XFER_PI | XFER_GAMMAS):
         _check(lib.bpfa_transfer_dictionary(self._h, src._h, int(what)))

@@ -131,8 +131,17 @@ DictPlan make_dict_plan(const Geom& g) {
   pl.ent0[pl.RG] = (long long)K * (K + 1) / 2;
   pl.tri_entries = pl.ent0[pl.RG];
   pl.rec_len_total = pl.tri_entries + K;
-  const int target_blocks = 512;
-  pl.chunks = std::max(1, std::min(64, (target_blocks + g.P * pl.RG - 1) / (g.P * pl.RG)));
+  // chunk of observed pixels per block: as many visit records as the LDS
+  // left over by the largest row group holds (a multiple of the block size)
+  long long rec_max = 0;
+  for (int r = 0; r < pl.RG; ++r)
+    rec_max = std::max(rec_max, (pl.ent0[r + 1] - pl.ent0[r]) + (long long)(pl.row0[r + 1] - pl.row0[r]));
+  const long long room = (long long)kLdsBytes - rec_max * 8 - 2LL * (K + 1) * 4;
+  pl.chunk_visits = (int)std::max<long long>(kDictBlock, room / 10 / kDictBlock * kDictBlock);
+  // partial accumulators per (p, row group): set per frame from the observed
+  // pixels (bpfa_problem::dict_groups), at most this many
+  const long long mt = g.Mtot;
+  pl.chunks = (int)std::min<long long>(16, std::max<long long>(1, (mt + pl.chunk_visits - 1) / pl.chunk_visits));
   return pl;
 }
 
@@ -225,7 +234,10 @@ struct bpfa_problem {
   hipStream_t aux[kSweepRanges] = {};   // concurrent sweep ranges
   hipEvent_t ev_fork = nullptr, ev_join[kSweepRanges] = {};
   int cur = 0;
+  int precision = BPFA_FP32;    // contraction precision of the reconstruction
   int max_obs = 0, n_omega = 0;
+  int dict_groups = 1;          // statistics partials per (p, row group) for this frame
+  int dict_cv = 0;              // observed pixels per statistics chunk for this frame
   SweepLaunch sweep_ranges{};
   uint32_t key0 = 0, key1 = 0;
   int64_t t_host = 1;
@@ -331,6 +343,15 @@ bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask,
   HIPCHK(hipStreamSynchronize(h->st));
   h->max_obs = s.max_obs;
   h->n_omega = s.n_omega;
+  {
+    // about two statistics blocks per CU; chunks no larger than the LDS holds
+    const DictPlan& pl = h->L.plan;
+    const int need = (h->n_omega + pl.chunk_visits - 1) / pl.chunk_visits;
+    const int fill = 512 / (g.P * pl.RG);
+    h->dict_groups = std::max(1, std::min(pl.chunks, std::max(need, fill)));
+    const int per = (h->n_omega + h->dict_groups - 1) / h->dict_groups;
+    h->dict_cv = std::min(pl.chunk_visits, std::max(kDictBlock, (per + kDictBlock - 1) / kDictBlock * kDictBlock));
+  }
   if (h->max_obs > 256)
     return fail(BPFA_ESHAPE, "a patch has %d observed pixels; at most 256 are supported", h->max_obs);
   const int J4 = std::max(4, (h->max_obs + 3) & ~3);
@@ -602,8 +623,11 @@ bpfa_status bpfa_iterate(bpfa_t h, int32_t n_iters, uint32_t flags) {
     HIPCHK(launch_sweep_reduce(g, b, L.sweep_blocks, h->st));
     h->cur = 1 - h->cur;
     if (learn) {
-      HIPCHK(launch_dict_stats(g, b, L.plan, h->cur, L.Npad, h->st));
-      HIPCHK(launch_dict_reduce(g, b, L.plan, h->st));
+      DictPlan plan = L.plan;
+      plan.chunks = h->dict_groups;
+      plan.chunk_visits = h->dict_cv;
+      HIPCHK(launch_dict_stats(g, b, plan, h->cur, L.Npad, h->st));
+      HIPCHK(launch_dict_reduce(g, b, plan, h->st));
       HIPCHK(launch_dict_chain(g, b, L.plan, h->key0, h->key1, stream_word(2, h->prm.problem_id),
                                h->st));
     }
@@ -625,7 +649,7 @@ bpfa_status bpfa_reconstruct(bpfa_t h, float* out, bpfa_mem mem) {
   std::array<hipEvent_t, 2> ev{};
   bpfa_status r;
   if (h->timing && (r = record(h, &ev[0])) != BPFA_OK) return r;
-  HIPCHK(launch_recon(h->g, h->b, h->cur, h->L.Npad, dst, h->st));
+  HIPCHK(launch_recon(h->g, h->b, h->cur, h->L.Npad, dst, h->precision == BPFA_BF16, h->st));
   if (h->timing) {
     if ((r = record(h, &ev[1])) != BPFA_OK) return r;
     h->recon_events.push_back(ev);
@@ -634,6 +658,13 @@ bpfa_status bpfa_reconstruct(bpfa_t h, float* out, bpfa_mem mem) {
     HIPCHK(hipMemcpyAsync(out, dst, 4 * (size_t)h->g.Mtot, hipMemcpyDeviceToHost, h->st));
     return check_status(h);
   }
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_set_precision(bpfa_t h, uint32_t precision) {
+  if (!h) return fail(BPFA_EINVAL, "NULL handle");
+  if (precision != BPFA_FP32 && precision != BPFA_BF16) return fail(BPFA_EINVAL, "unknown precision");
+  h->precision = (int)precision;
   return BPFA_OK;
 }
 

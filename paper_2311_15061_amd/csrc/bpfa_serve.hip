@@ -214,7 +214,12 @@ Slot* acquire_slot(bpfa_server* s, const std::vector<int64_t>& shape, size_t nee
   std::vector<float> zimg((size_t)px, 0.f);
   std::vector<uint8_t> zmask((size_t)px, 0);
   bpfa_t h = nullptr;
-  const int st = bpfa_create(&fp, nullptr, 0, zimg.data(), zmask.data(), BPFA_HOST, &h);
+  int st = bpfa_create(&fp, nullptr, 0, zimg.data(), zmask.data(), BPFA_HOST, &h);
+  if (st == BPFA_OK) st = bpfa_set_precision(h, (uint32_t)s->prm.precision);
+  if (st != BPFA_OK && h) {
+    bpfa_destroy(h);
+    h = nullptr;
+  }
   lk.lock();
   if (st != BPFA_OK) {
     s->slots.erase(std::find(s->slots.begin(), s->slots.end(), sl));
@@ -302,13 +307,15 @@ void bpfa_server_params_default(bpfa_server_params* p) {
   p->dict_every = 10;
   p->max_slots = 4;
   p->hbm_budget = 16ull << 30;
+  p->precision = BPFA_BF16;
 }
 
 bpfa_status bpfa_server_create(const bpfa_server_params* p, bpfa_server_t* out) {
   if (!p || !out) return BPFA_EINVAL;
   *out = nullptr;
   if (p->n_streams < 1 || p->n_streams > 4096 || p->sc_iters < 1 || p->dict_every < 0 ||
-      p->max_slots < 1 || p->hbm_budget == 0)
+      p->max_slots < 1 || p->hbm_budget == 0 ||
+      (p->precision != BPFA_FP32 && p->precision != BPFA_BF16))
     return BPFA_EINVAL;
   // validate the patch geometry and priors on the smallest frame that holds one patch
   std::vector<int64_t> probe(4, 1);
@@ -379,6 +386,7 @@ bpfa_status bpfa_server_submit(bpfa_server_t s, int32_t stream, const int64_t* s
                                uint64_t* ticket) {
   if (!s || !shape || !image || !mask || !out || stream < 0 || stream >= s->prm.n_streams)
     return BPFA_EINVAL;
+  const Clock::time_point arrival = Clock::now();
   std::vector<int64_t> shp(shape, shape + s->prm.ndim);
   bpfa_params fp = frame_params(s->prm, shp);
   size_t need = 0;
@@ -398,7 +406,7 @@ bpfa_status bpfa_server_submit(bpfa_server_t s, int32_t stream, const int64_t* s
   std::memcpy(f->img, image, 4 * (size_t)f->pixels);
   std::memcpy(f->mask, mask, (size_t)f->pixels);
   std::lock_guard<std::mutex> lk(s->mu);
-  f->submit_t = Clock::now();
+  f->submit_t = arrival;
   f->ticket = s->next_ticket++;
   if (ticket) *ticket = f->ticket;
   s->streams[stream].fifo.push_back(f);

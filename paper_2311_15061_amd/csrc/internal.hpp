@@ -11,7 +11,8 @@ constexpr int kMaxDim = 4;
 constexpr int kSweepBlock = 256;      // 4 waves share one LDS copy of the dictionary tile
 constexpr int kSlotAlign = kSweepBlock;
 constexpr int kLdsTileBytes = 64 * 1024;
-constexpr int kDictBlock = 512;
+constexpr int kDictBlock = 1024;
+constexpr int kLdsBytes = 160 * 1024 - 1024;   // per block, leaving room for static arrays
 constexpr int kDictLdsEntries = 16384; // int64 accumulators per statistics block (128 KiB)
 constexpr int kSortBlock = 256;        // patches per block of the slot sort
 constexpr int kSweepRanges = 5;        // J <= 16, <= 32, <= 64 (exact bodies), <= 128, <= 256
@@ -115,9 +116,15 @@ struct DictPlan {
   int row0[65];                // row group r covers atoms [row0[r], row0[r+1])
   long long ent0[65];          // triangle entry offset of row0[r]
   int chunks = 1;
+  int chunk_visits = 0;        // observed pixels per chunk (LDS visit records)
   long long rec_len_total = 0; // sum over row groups of (entries + rows)
   long long tri_entries = 0;   // K (K + 1) / 2
 };
+
+// bytes of LDS of the statistics kernel
+inline size_t dict_stats_lds(int K, long long rec_stride, int chunk_visits) {
+  return (size_t)rec_stride * 8 + (size_t)2 * (K + 1) * 4 + (size_t)chunk_visits * 10;
+}
 
 // First block of each sweep launch range (ranges of ascending J).
 struct SweepLaunch {
@@ -143,8 +150,11 @@ hipError_t launch_dict_chain(const Geom& g, const Buffers& b, const DictPlan& pl
                              uint32_t key0, uint32_t key1, uint32_t stream, hipStream_t st);
 hipError_t launch_scalars(const Geom& g, const Buffers& b, const double* hyper, int learn_dict,
                           uint32_t key0, uint32_t key1, uint32_t problem_id, hipStream_t st);
-hipError_t launch_recon(const Geom& g, const Buffers& b, int cur, int Npad, float* out,
+hipError_t launch_recon(const Geom& g, const Buffers& b, int cur, int Npad, float* out, bool bf16,
                         hipStream_t st);
+hipError_t launch_recon_patches_mfma(const Geom& g, const Buffers& b, int cur, bool bf16,
+                                     hipStream_t st);
+size_t recon_mfma_lds(int P, bool bf16);
 hipError_t launch_lists_to_dense(const Geom& g, const Buffers& b, int cur, float* W, uint8_t* Z,
                                  hipStream_t st);
 hipError_t launch_dense_to_lists(const Geom& g, const Buffers& b, int cur, int Npad,

@@ -12,9 +12,11 @@
 // sum_p (X2_p - 2 d_p.B_p + d_p^T C_p d_p) with X2_p = sum_i m_ip x_ip^2.
 //
 // dict_stats_kernel: one block per (p, row group of the K x K triangle,
-//   chunk of observed pixels).  A lane takes observed pixel q and the patch
-//   whose origin is q - b(p); its active entries are staged in registers and
-//   its outer product is added into LDS.  Sums are 64-bit fixed point: the
+//   chunk of observed pixels).  The visits of the chunk (observed pixel q,
+//   the patch whose origin is q - b(p)) are first grouped by the patch's
+//   number of active atoms n_a in LDS, so a wavefront's lanes share a pair
+//   loop bound; then a lane stages a patch's active entries in registers and
+//   adds its outer product into LDS.  Sums are 64-bit fixed point: the
 //   binary64 product of two binary32 weights is exact, it is scaled by a power
 //   of two and rounded to an integer by adding 1.5 * 2^52 (exact for
 //   |x| < 2^51); integer adds are associative, so the statistics do not
@@ -22,7 +24,8 @@
 // dict_reduce_kernel: sums the chunk partials, one block per (p, row k),
 //   into the symmetric binary64 C_p, B_p and the diagonal.
 // dict_chain_kernel: one wavefront per p runs the chain with rows of C_p
-//   prefetched ahead of use, draws d_kp with the Philox DICT stream, and forms
+//   prefetched ahead of use, keeping u = C_p d current instead of reducing a
+//   dot product per step, draws d_kp with the Philox DICT stream, and forms
 //   the residual sum of squares.
 #include "internal.hpp"
 #include "philox.hpp"
@@ -32,7 +35,7 @@ namespace bpfa {
 constexpr int kStatsCap = 16;   // active entries of a patch held in registers
 
 struct DictPlanDev {
-  int RG, chunks, K, pad_;
+  int RG, chunks, K, chunk_visits;
   int row0[65];
   long long ent0[65];
   long long rec_stride;
@@ -48,6 +51,28 @@ __device__ __forceinline__ unsigned long long to_fixed(double x) {
                               0x4338000000000000LL);
 }
 
+// origin = q - b(p): every coordinate non-negative, on the stride grid, inside the grid
+__device__ __forceinline__ int visit_patch(const Geom& g, const int4 qc, const int* bc) {
+  const int qv[kMaxDim] = {qc.x, qc.y, qc.z, qc.w};
+  int pidx = 0;
+  bool ok = true;
+  for (int d = 0; d < g.ndim; ++d) {
+    const int od = qv[d] - bc[d];
+    const int gd = g.S[d] == 1 ? od : od / g.S[d];
+    ok = ok && od >= 0 && gd * g.S[d] == od && gd < g.G[d];
+    pidx = pidx * g.G[d] + gd;
+  }
+  return ok ? pidx : -1;
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+// LDS: rec int64 accumulators | 2 (K + 1) int bin counters | chunk visits
+// (slot int32, y float, n_a uint16).  Visits are bucketed by n_a inside the
+// block so each wavefront's pair loop runs to a bound its lanes share.
 __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
     Geom g, DictPlanDev pl, const int4* __restrict__ omega_c, const int32_t* __restrict__ omega,
     const float* __restrict__ image, const int32_t* __restrict__ pcoord,
@@ -65,34 +90,75 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
   const int E = (int)(pl.ent0[rg + 1] - e0);
   const int rec = E + (r1 - r0);
   const int K = g.K;
-  for (int e = threadIdx.x; e < rec; e += kDictBlock) acc[e] = 0;
-  __syncthreads();
+  int* bins = reinterpret_cast<int*>(acc + pl.rec_stride);          // K + 1 starts
+  int* cursor = bins + (K + 1);                                       // K + 1 fill cursors
+  int* v_slot = cursor + (K + 1);
+  float* v_y = reinterpret_cast<float*>(v_slot + pl.chunk_visits);
+  uint16_t* v_na = reinterpret_cast<uint16_t*>(v_y + pl.chunk_visits);
+  const int tid = threadIdx.x, lane = tid & (kWave - 1);
+  for (int e = tid; e < rec; e += kDictBlock) acc[e] = 0;
 
   const double sc = scal->scale_c, sb = scal->scale_b;
   const int nom = scal->n_omega;
-  const int per = (nom + pl.chunks - 1) / pl.chunks;
-  const int v0 = min(nom, c * per), v1 = min(nom, v0 + per);
   int bc[kMaxDim] = {0, 0, 0, 0};
   for (int d = 0; d < g.ndim; ++d) bc[d] = pcoord[p * kMaxDim + d];
-
   double x2 = 0.0;
-  for (int v = v0 + (int)threadIdx.x; v < v1; v += kDictBlock) {
-    const int4 qc = omega_c[v];
-    const int qv[kMaxDim] = {qc.x, qc.y, qc.z, qc.w};
-    // origin = q - b(p): every coordinate non-negative, on the stride grid, inside the grid
-    int pidx = 0;
-    bool ok = true;
-    for (int d = 0; d < g.ndim; ++d) {
-      const int od = qv[d] - bc[d];
-      const int gd = g.S[d] == 1 ? od : od / g.S[d];
-      ok = ok && od >= 0 && gd * g.S[d] == od && gd < g.G[d];
-      pidx = pidx * g.G[d] + gd;
+
+  // block c of its (p, row group) takes chunks c, c + chunks, ... of the observed pixels
+  for (int ch = c; ch * pl.chunk_visits < nom; ch += pl.chunks) {
+  const int v0 = ch * pl.chunk_visits, v1 = min(nom, v0 + pl.chunk_visits);
+  for (int e = tid; e <= K; e += kDictBlock) bins[e] = 0;
+  __syncthreads();
+
+  // pass 1: visits per n_a
+  for (int v = v0 + tid; v < v1; v += kDictBlock) {
+    const int pidx = visit_patch(g, omega_c[v], bc);
+    if (pidx >= 0) atomicAdd(&bins[nact[inv_perm[pidx]]], 1);
+  }
+  __syncthreads();
+  if (tid < kWave) {   // exclusive scan of the bins by one wavefront
+    int run = 0;
+    for (int b0 = 0; b0 <= K; b0 += kWave) {
+      const int b = b0 + lane;
+      const int x = b <= K ? bins[b] : 0;
+      int incl = x;
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+      }
+      if (b <= K) {
+        bins[b] = run + incl - x;
+        cursor[b] = run + incl - x;
+      }
+      run += __shfl(incl, kWave - 1);
     }
-    if (!ok) continue;
-    const int slot = inv_perm[pidx];
-    const int na = nact[slot];
-    const double y = (double)image[omega[v]];
-    if (rg == 0) x2 += y * y;
+  }
+  __syncthreads();
+  // pass 2: place the visits, grouped by n_a
+  for (int v = v0 + tid; v < v1; v += kDictBlock) {
+    const int pidx = visit_patch(g, omega_c[v], bc);
+    if (pidx >= 0) {
+      const int slot = inv_perm[pidx];
+      const int na = nact[slot];
+      const int pos = atomicAdd(&cursor[na], 1);
+      const float y = image[omega[v]];
+      v_slot[pos] = slot;
+      v_y[pos] = y;
+      v_na[pos] = (uint16_t)na;
+      // X2 here, where a thread's visits do not depend on the placement order
+      if (rg == 0) x2 += (double)y * (double)y;
+    }
+  }
+  __syncthreads();
+  const int nvis = cursor[K];
+  // pass 3: outer products into the accumulators
+  for (int vb = 0; vb < nvis; vb += kDictBlock) {
+    const int vi = vb + tid;
+    const bool on = vi < nvis;
+    const int slot = on ? v_slot[vi] : 0;
+    const int na = on ? (int)v_na[vi] : 0;
+    const double y = on ? (double)v_y[vi] : 0.0;
+    const int wmax = __builtin_amdgcn_readfirstlane(wave_max_i(na));
     const int2* L = list + (size_t)slot * K;
     int kk[kStatsCap];
     double ww[kStatsCap];
@@ -100,7 +166,7 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
     for (int a = 0; a < kStatsCap; ++a) {
       kk[a] = -1;
       ww[a] = 0.0;
-      if (a < na) {
+      if (a < wmax && a < na) {
         const int2 e = L[a];
         kk[a] = e.x;
         ww[a] = (double)__int_as_float(e.y);
@@ -109,39 +175,46 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
     const double ysb = y * sb;
 #pragma unroll
     for (int a = 0; a < kStatsCap; ++a) {
-      if (kk[a] >= r0 && kk[a] < r1) {
-        atomicAdd((unsigned long long*)&acc[E + (kk[a] - r0)], to_fixed(ww[a] * ysb));
-        const double wa = ww[a] * sc;
-        const int base = (int)(tri_off(kk[a], K) - e0) - kk[a];
+      if (a < wmax) {
+        if (kk[a] >= r0 && kk[a] < r1) {
+          atomicAdd((unsigned long long*)&acc[E + (kk[a] - r0)], to_fixed(ww[a] * ysb));
+          const double wa = ww[a] * sc;
+          const int base = (int)(tri_off(kk[a], K) - e0) - kk[a];
 #pragma unroll
-        for (int b = a; b < kStatsCap; ++b)
-          if (kk[b] >= 0) atomicAdd((unsigned long long*)&acc[base + kk[b]], to_fixed(wa * ww[b]));
+          for (int b = a; b < kStatsCap; ++b)
+            if (b < wmax && kk[b] >= 0)
+              atomicAdd((unsigned long long*)&acc[base + kk[b]], to_fixed(wa * ww[b]));
+        }
       }
     }
     // entries beyond the register stage: every pair (a, b), a <= b, with b >= kStatsCap
-    for (int b = kStatsCap; b < na; ++b) {
-      const int2 eb = L[b];
-      const double wb = (double)__int_as_float(eb.y);
-      if (eb.x >= r0 && eb.x < r1)
-        atomicAdd((unsigned long long*)&acc[E + (eb.x - r0)], to_fixed(wb * ysb));
-      for (int a = 0; a <= b; ++a) {
-        const int2 ea = L[a];
-        if (ea.x >= r0 && ea.x < r1) {
-          const int base = (int)(tri_off(ea.x, K) - e0) - ea.x;
-          atomicAdd((unsigned long long*)&acc[base + eb.x],
-                    to_fixed((double)__int_as_float(ea.y) * sc * wb));
+    if (wmax > kStatsCap) {
+      for (int b = kStatsCap; b < na; ++b) {
+        const int2 eb = L[b];
+        const double wb = (double)__int_as_float(eb.y);
+        if (eb.x >= r0 && eb.x < r1)
+          atomicAdd((unsigned long long*)&acc[E + (eb.x - r0)], to_fixed(wb * ysb));
+        for (int a = 0; a <= b; ++a) {
+          const int2 ea = L[a];
+          if (ea.x >= r0 && ea.x < r1) {
+            const int base = (int)(tri_off(ea.x, K) - e0) - ea.x;
+            atomicAdd((unsigned long long*)&acc[base + eb.x],
+                      to_fixed((double)__int_as_float(ea.y) * sc * wb));
+          }
         }
       }
     }
   }
+  __syncthreads();   // the visit records are rewritten by the next chunk
+  }
   __syncthreads();
   long long* out = dpart + (size_t)blockIdx.x * pl.rec_stride;
-  for (int e = threadIdx.x; e < rec; e += kDictBlock) out[e] = acc[e];
+  for (int e = tid; e < rec; e += kDictBlock) out[e] = acc[e];
   if (rg == 0) {
     for (int o = kWave / 2; o > 0; o >>= 1) x2 += __shfl_xor(x2, o);
-    if ((threadIdx.x & (kWave - 1)) == 0) s_x2[threadIdx.x / kWave] = x2;
+    if (lane == 0) s_x2[tid / kWave] = x2;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       double t = 0.0;
       for (int w = 0; w < kDictBlock / kWave; ++w) t += s_x2[w];
       dx2[p * pl.chunks + c] = t;
@@ -189,33 +262,68 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One wavefront per position p.  Lane l owns components j = l + 64 m of d
+// and of u = C_p d.  With g_k = gamma_eps / lam_k and the constant
+// t_k = g_k (B_k + C_kk d_k) + n_k / sqrt(lam_k) (d_k not yet redrawn),
+// step k is d_k' = t_k - g_k u_k, and every lane adds C_p[k][j] (d_k' - d_k)
+// to its u_j: no reduction per step, and at the end d.u = d^T C_p d.
 template <int KPL, int PF>
 __global__ __launch_bounds__(kWave) void dict_chain_kernel(
     Geom g, const double* __restrict__ Cfull, const double* __restrict__ Bvec,
     const double* __restrict__ diag, const double* __restrict__ x2p, DevScalars* scal,
     float* __restrict__ D, double* __restrict__ sumr2_p, uint32_t key0, uint32_t key1,
     uint32_t stream) {
-  __shared__ double s_B[64 * KPL], s_n[64 * KPL], s_diag[64 * KPL], s_d[64 * KPL];
   const int p = blockIdx.x, lane = threadIdx.x, K = g.K, P = g.P;
   const double* C = Cfull + (size_t)p * K * K;
   const uint32_t t = (uint32_t)scal->t;
-  double dreg[KPL];
+  const double ge = scal->gamma_eps;
+  double dreg[KPL], ureg[KPL], greg[KPL], treg[KPL], breg[KPL];
 #pragma unroll
   for (int m = 0; m < KPL; ++m) {
     const int j = lane + kWave * m;
-    dreg[m] = 0.0;
+    dreg[m] = ureg[m] = greg[m] = treg[m] = breg[m] = 0.0;
     if (j < K) {
       const Block4 rb = philox10((uint32_t)p, (uint32_t)j, t, stream, key0, key1);
-      s_n[j] = sqrt(-2.0 * log(u01d(rb.w0))) * cos(2.0 * M_PI * u01d(rb.w1));
-      s_B[j] = Bvec[(size_t)p * K + j];
-      s_diag[j] = diag[(size_t)p * K + j];
+      const double n = sqrt(-2.0 * log(u01d(rb.w0))) * cos(2.0 * M_PI * u01d(rb.w1));
+      const double cjj = diag[(size_t)p * K + j];
+      const double lam = (double)P + ge * cjj;
+      breg[m] = Bvec[(size_t)p * K + j];
       dreg[m] = (double)D[(size_t)j * P + p];
+      greg[m] = ge / lam;
+      treg[m] = fma(greg[m], fma(cjj, dreg[m], breg[m]), n / sqrt(lam));
     }
   }
-  __syncthreads();
-
-  // the chain over atoms, rows of C_p prefetched PF ahead
-  const double ge = scal->gamma_eps;
+  // u = C d with the old dictionary, rows streamed PF at a time
+  for (int kb = 0; kb < K; kb += PF) {
+    double v[PF][KPL];
+#pragma unroll
+    for (int u = 0; u < PF; ++u)
+#pragma unroll
+      for (int m = 0; m < KPL; ++m) {
+        const int j = lane + kWave * m, k = kb + u;
+        v[u][m] = (k < K && j < K) ? C[(size_t)k * K + j] : 0.0;
+      }
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int k = kb + u;
+      if (k < K) {
+        double dk = 0.0;
+#pragma unroll
+        for (int m = 0; m < KPL; ++m)
+          if ((k >> 6) == m) dk = readlane_d(dreg[m], k & 63);
+#pragma unroll
+        for (int m = 0; m < KPL; ++m) ureg[m] = fma(v[u][m], dk, ureg[m]);
+      }
+    }
+  }
+  // the chain, rows of C_p (= columns, by symmetry) prefetched PF ahead
   double ring[PF][KPL];
 #pragma unroll
   for (int u = 0; u < PF; ++u)
@@ -230,19 +338,24 @@ __global__ __launch_bounds__(kWave) void dict_chain_kernel(
     for (int u = 0; u < PF; ++u) {
       const int k = kb + u;
       if (k < K) {
-        double part = 0.0;
-#pragma unroll
-        for (int m = 0; m < KPL; ++m) {
-          const int j = lane + kWave * m;
-          if (j != k) part = fma(ring[u][m], dreg[m], part);
-        }
-        const double tot = wave_sum_d(part);
-        const double lam = (double)P + ge * s_diag[k];
-        const double dn = ge * (s_B[k] - tot) / lam + s_n[k] / sqrt(lam);
-        bad = bad || !isfinite(dn);
+        double uk = 0.0, dk = 0.0, gk = 0.0, tk = 0.0;
 #pragma unroll
         for (int m = 0; m < KPL; ++m)
+          if ((k >> 6) == m) {
+            const int kl = k & 63;
+            uk = readlane_d(ureg[m], kl);
+            dk = readlane_d(dreg[m], kl);
+            gk = readlane_d(greg[m], kl);
+            tk = readlane_d(treg[m], kl);
+          }
+        const double dn = fma(-gk, uk, tk);
+        bad = bad || !isfinite(dn);
+        const double delta = dn - dk;
+#pragma unroll
+        for (int m = 0; m < KPL; ++m) {
+          ureg[m] = fma(ring[u][m], delta, ureg[m]);
           if (k == lane + kWave * m) dreg[m] = dn;
+        }
         const int kn = k + PF;
 #pragma unroll
         for (int m = 0; m < KPL; ++m) {
@@ -252,44 +365,15 @@ __global__ __launch_bounds__(kWave) void dict_chain_kernel(
       }
     }
   }
-
-  // new atoms' column p; residual sum of squares at position p
-#pragma unroll
-  for (int m = 0; m < KPL; ++m) {
-    const int j = lane + kWave * m;
-    if (j < K) {
-      s_d[j] = dreg[m];
-      D[(size_t)j * P + p] = (float)dreg[m];
-    }
-  }
-  __syncthreads();
-  double cd[KPL];
-#pragma unroll
-  for (int m = 0; m < KPL; ++m) cd[m] = 0.0;
-  for (int kb = 0; kb < K; kb += PF) {
-    double v[PF][KPL];
-#pragma unroll
-    for (int u = 0; u < PF; ++u)
-#pragma unroll
-      for (int m = 0; m < KPL; ++m) {
-        const int j = lane + kWave * m, k = kb + u;
-        v[u][m] = (k < K && j < K) ? C[(size_t)k * K + j] : 0.0;
-      }
-#pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const int k = kb + u;
-      const double dk = k < K ? s_d[k] : 0.0;
-#pragma unroll
-      for (int m = 0; m < KPL; ++m) cd[m] = fma(v[u][m], dk, cd[m]);
-    }
-  }
+  // new atoms' column p; residual sum of squares X2 - 2 d.B + d.(C d)
   double quad = 0.0, lin = 0.0;
 #pragma unroll
   for (int m = 0; m < KPL; ++m) {
     const int j = lane + kWave * m;
     if (j < K) {
-      quad = fma(cd[m], dreg[m], quad);
-      lin = fma(s_B[j], dreg[m], lin);
+      D[(size_t)j * P + p] = (float)dreg[m];
+      quad = fma(ureg[m], dreg[m], quad);
+      lin = fma(breg[m], dreg[m], lin);
     }
   }
   quad = wave_sum_d(quad);
@@ -304,6 +388,7 @@ static DictPlanDev to_dev(const Geom& g, const DictPlan& plan) {
   DictPlanDev d{};
   d.RG = plan.RG;
   d.chunks = plan.chunks;
+  d.chunk_visits = plan.chunk_visits;
   d.K = g.K;
   long long stride = 0;
   for (int r = 0; r <= plan.RG; ++r) {
@@ -323,7 +408,8 @@ hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& pl
   (void)Npad;
   const DictPlanDev d = to_dev(g, plan);
   const int blocks = g.P * plan.RG * plan.chunks;
-  const size_t lds = (size_t)d.rec_stride * sizeof(long long);
+  // the LDS holds visit records for the largest chunk the plan allows
+  const size_t lds = dict_stats_lds(g.K, d.rec_stride, plan.chunk_visits);
   hipError_t e = hipFuncSetAttribute((const void*)dict_stats_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;

@@ -1,9 +1,8 @@
 // Overlap-averaged reconstruction and conversions of the sampler state.
 //
-// recon_patch_kernel: the patch models y_i = D^T w_i, one thread per (patch,
-//   run of 16 in-patch offsets) reading the patch's active list once; stored
-//   pixel-major, Y[p][i], so that neighbouring output pixels read
-//   neighbouring patches.
+// The patch models y_i = D^T w_i come from the matrix-core kernel
+// (kernels_recon_mfma.hip), stored pixel-major, Y[p][i], so that
+// neighbouring output pixels read neighbouring patches.
 // recon_pixel_kernel: one thread per image pixel q sums Y[p][i] over every
 //   patch i and in-patch offset p with o_i + b(p) = q, in ascending p, and
 //   divides by the number of such pairs (the coverage of q).
@@ -11,76 +10,59 @@
 
 namespace bpfa {
 
-constexpr int kReconChunk = 16;   // in-patch offsets per thread
-
-// thread (chunk c, slot s): y_i[p] for p in [16 c, 16 c + 16), one pass over the entries
-__global__ __launch_bounds__(256) void recon_patch_kernel(Geom g, const float* __restrict__ D,
-                                                          const int32_t* __restrict__ inv_perm,
-                                                          const int2* __restrict__ list,
-                                                          const int32_t* __restrict__ nact,
-                                                          float* __restrict__ Y) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = (int)(t % g.N);
-  const int c = (int)(t / g.N);
-  const int p0 = c * kReconChunk;
-  if (p0 >= g.P) return;
-  const int s = inv_perm[i];
-  const int na = nact[s];
-  const int2* L = list + (size_t)s * g.K;
-  float acc[kReconChunk];
-#pragma unroll
-  for (int u = 0; u < kReconChunk; ++u) acc[u] = 0.f;
-  const bool full = p0 + kReconChunk <= g.P;
-  for (int a = 0; a < na; ++a) {
-    const int2 e = L[a];
-    const float w = __int_as_float(e.y);
-    const float* row = D + (size_t)e.x * g.P + p0;
-#pragma unroll
-    for (int u = 0; u < kReconChunk; ++u)
-      if (full || p0 + u < g.P) acc[u] = fmaf(row[u], w, acc[u]);
-  }
-#pragma unroll
-  for (int u = 0; u < kReconChunk; ++u)
-    if (full || p0 + u < g.P) Y[(size_t)(p0 + u) * g.N + i] = acc[u];
-}
-
-__global__ __launch_bounds__(256) void recon_pixel_kernel(Geom g, const int32_t* __restrict__ pcoord,
-                                                          const float* __restrict__ Y,
+// The pairs (i, p) that cover q form a box: per dimension the in-patch
+// offsets b_d <= q_d congruent to q_d mod S_d with q_d - b_d <= (G_d - 1) S_d.
+// The box is walked in C order of b, i.e. in ascending p.
+__global__ __launch_bounds__(256) void recon_pixel_kernel(Geom g, const float* __restrict__ Y,
                                                           float* __restrict__ out) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= g.Mtot) return;
-  int qc[kMaxDim];
-  int rem = q;
-  for (int d = g.ndim - 1; d >= 0; --d) {
-    qc[d] = rem % g.M[d];
+  // per padded dimension (leading dimensions of size 1): first offset, count,
+  // and the strides of p and i
+  int lo[kMaxDim], cnt[kMaxDim], gs[kMaxDim], pst[kMaxDim], ist[kMaxDim], st[kMaxDim];
+  int rem = q, ps = 1, is = 1;
+  for (int e = kMaxDim - 1; e >= 0; --e) {
+    const int d = e - (kMaxDim - g.ndim);
+    if (d < 0) {
+      lo[e] = 0; cnt[e] = 1; gs[e] = 0; pst[e] = 0; ist[e] = 0; st[e] = 1;
+      continue;
+    }
+    const int qd = rem % g.M[d];
     rem /= g.M[d];
+    const int S = g.S[d];
+    int b0 = qd - (g.G[d] - 1) * S;          // congruent to qd mod S
+    if (b0 < 0) b0 += ((-b0 + S - 1) / S) * S;
+    const int b1 = min(g.B[d] - 1, qd);
+    lo[e] = b0;
+    cnt[e] = b1 >= b0 ? (b1 - b0) / S + 1 : 0;
+    gs[e] = (qd - b0) / S;
+    st[e] = S;
+    pst[e] = ps;
+    ist[e] = is;
+    ps *= g.B[d];
+    is *= g.G[d];
   }
+  const size_t N = (size_t)g.N;
   float acc = 0.f;
-  int cnt = 0;
-  for (int p = 0; p < g.P; ++p) {
-    int pidx = 0;
-    bool ok = true;
-    for (int d = 0; d < g.ndim; ++d) {
-      const int od = qc[d] - pcoord[p * kMaxDim + d];
-      const int gd = od / g.S[d];
-      ok = ok && od >= 0 && gd * g.S[d] == od && gd < g.G[d];
-      pidx = pidx * g.G[d] + gd;
-    }
-    if (ok) {
-      acc += Y[(size_t)p * g.N + pidx];
-      ++cnt;
-    }
-  }
-  out[q] = acc / (float)cnt;
+  for (int a0 = 0; a0 < cnt[0]; ++a0)
+    for (int a1 = 0; a1 < cnt[1]; ++a1)
+      for (int a2 = 0; a2 < cnt[2]; ++a2) {
+        const int p2 = (lo[0] + a0 * st[0]) * pst[0] + (lo[1] + a1 * st[1]) * pst[1] +
+                       (lo[2] + a2 * st[2]) * pst[2];
+        const int i2 = (gs[0] - a0) * ist[0] + (gs[1] - a1) * ist[1] + (gs[2] - a2) * ist[2];
+        const float* y = Y + (size_t)(p2 + lo[3] * pst[3]) * N + (i2 + gs[3] * ist[3]);
+        const size_t dy = (size_t)st[3] * pst[3] * N - (size_t)ist[3];
+        for (int a3 = 0; a3 < cnt[3]; ++a3, y += dy) acc += *y;
+      }
+  out[q] = acc / (float)(cnt[0] * cnt[1] * cnt[2] * cnt[3]);
 }
 
-hipError_t launch_recon(const Geom& g, const Buffers& b, int cur, int Npad, float* out,
+hipError_t launch_recon(const Geom& g, const Buffers& b, int cur, int Npad, float* out, bool bf16,
                         hipStream_t st) {
   (void)Npad;
-  const long long n = (long long)g.N * ((g.P + kReconChunk - 1) / kReconChunk);
-  recon_patch_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(g, b.D, b.inv_perm, b.list[cur],
-                                                                  b.nact[cur], b.Y);
-  recon_pixel_kernel<<<(g.Mtot + 255) / 256, 256, 0, st>>>(g, b.pcoord, b.Y, out);
+  hipError_t e = launch_recon_patches_mfma(g, b, cur, bf16, st);
+  if (e != hipSuccess) return e;
+  recon_pixel_kernel<<<(g.Mtot + 255) / 256, 256, 0, st>>>(g, b.Y, out);
   return hipGetLastError();
 }
 

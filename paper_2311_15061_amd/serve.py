@@ -17,7 +17,7 @@ class ServerParams(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("n_streams", ctypes.c_int32),
                 ("sc_iters", ctypes.c_int32), ("dict_every", ctypes.c_int32),
                 ("max_slots", ctypes.c_int32), ("hbm_budget", ctypes.c_uint64),
-                ("device", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("precision", ctypes.c_int32)]
 
 
 class ServeResult(ctypes.Structure):
@@ -68,7 +68,7 @@ class Server:
     """Live-feed server: per-stream dictionaries resident on the GPU, frames of any size."""
 
     def __init__(self, patch=(10, 10), stride=None, K=128, n_streams=4, sc_iters=5, dict_every=10,
-                 max_slots=4, hbm_budget=16 << 30, seed=0, device=0, **hyper):
+                 max_slots=4, hbm_budget=16 << 30, seed=0, device=0, precision="bf16", **hyper):
         p = ServerParams()
         lib.bpfa_server_params_default(ctypes.byref(p))
         p.ndim = len(patch)
@@ -77,6 +77,7 @@ class Server:
             p.patch[d], p.stride[d] = int(patch[d]), int(stride[d])
         p.K, p.n_streams, p.sc_iters, p.dict_every = int(K), int(n_streams), int(sc_iters), int(dict_every)
         p.max_slots, p.hbm_budget, p.seed, p.device = int(max_slots), int(hbm_budget), int(seed), int(device)
+        p.precision = _b.precision_code(precision)
         for k, v in hyper.items():
             setattr(p, k, float(v))
         self.params = p

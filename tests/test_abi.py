@@ -106,4 +106,5 @@ def test_bad_ndim_and_null_pointers(bpfa):
     assert bpfa.lib.bpfa_create(None, None, 0, None, None, 0, None) == bpfa.EINVAL
     assert bpfa.lib.bpfa_iterate(None, 1, 1) == bpfa.EINVAL
     assert bpfa.lib.bpfa_sync(None) == bpfa.EINVAL
+    assert bpfa.lib.bpfa_set_precision(None, bpfa.BF16) == bpfa.EINVAL
     bpfa.lib.bpfa_destroy(None)

@@ -37,10 +37,11 @@ def frames_for(stream, n, sizes=(40, 52)):
 
 
 def run_server(frames_by_stream, n_streams, max_slots=4, sc_iters=2, dict_every=3, budget=8 << 30,
-               order="interleave"):
-    print("server: streams=%d slots=%d" % (n_streams, max_slots), flush=True)
+               order="interleave", precision="bf16"):
+    print("server: streams=%d slots=%d %s" % (n_streams, max_slots, precision), flush=True)
     srv = serve.Server(patch=PATCH, K=K, n_streams=n_streams, sc_iters=sc_iters,
-                       dict_every=dict_every, max_slots=max_slots, hbm_budget=budget, seed=SEED)
+                       dict_every=dict_every, max_slots=max_slots, hbm_budget=budget, seed=SEED,
+                       precision=precision)
     tickets = {}
     if order == "interleave":
         n = max(len(v) for v in frames_by_stream.values())
@@ -62,7 +63,7 @@ def run_server(frames_by_stream, n_streams, max_slots=4, sc_iters=2, dict_every=
     return outs, stats
 
 
-def direct_sequence(frames, stream, sc_iters=2, dict_every=3):
+def direct_sequence(frames, stream, sc_iters=2, dict_every=3, precision="bf16"):
     """The same work through one problem handle per frame shape... sharing the
     stream's state through set_frame on a single handle per size would change
     shapes, so the state is carried explicitly with get/set_state."""
@@ -70,6 +71,7 @@ def direct_sequence(frames, stream, sc_iters=2, dict_every=3):
     outs = []
     for i, (y, m) in enumerate(frames):
         prob = bpfa.Problem(y, m, PATCH, K=K, seed=SEED, problem_id=stream)
+        prob.set_precision(precision)
         if state is not None:
             prob.set_state(D=state["D"], logit_pi=state["logit_pi"], gamma_s=state["gamma_s"],
                            gamma_eps=state["gamma_eps"], t=state["t"])
@@ -82,10 +84,11 @@ def direct_sequence(frames, stream, sc_iters=2, dict_every=3):
     return outs
 
 
-def test_stream_matches_direct_problem_path():
+@pytest.mark.parametrize("precision", ["bf16", "fp32"])
+def test_stream_matches_direct_problem_path(precision):
     frames = frames_for(1, 4)
-    outs, stats = run_server({1: frames}, n_streams=2)
-    ref = direct_sequence(frames, stream=1)
+    outs, stats = run_server({1: frames}, n_streams=2, precision=precision)
+    ref = direct_sequence(frames, stream=1, precision=precision)
     for i in range(len(frames)):
         st, out, r = outs[(1, i)]
         assert st == bpfa.OK
@@ -124,6 +127,7 @@ def test_transferred_dictionary():
                  gamma_eps=ts["gamma_eps"], t=1)
     for i, (y2, m2) in enumerate(frames):
         prob = bpfa.Problem(y2, m2, PATCH, K=K, seed=SEED, problem_id=2)
+        prob.set_precision("bf16")
         prob.set_state(**state)
         prob.iterate(2, bpfa.SPARSE_CODE_ONLY)
         assert np.array_equal(res[i]["out"], prob.reconstruct())
