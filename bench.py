@@ -181,6 +181,9 @@ def main():
     ap.add_argument("--no-quality", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-seconds", type=float, default=8.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES three times (the "
+                         "reference kernel that scales the HBM byte counters) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -197,6 +200,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n, "copies": 3}), flush=True)
+        return
     wl = synth.workload(args.workload)
     iters = args.iters or wl.iters
     y, m, g = synth.make_frame(wl)
@@ -267,10 +279,28 @@ def main():
                      "ops_per_update": sweep_ops_per_update(obs_per_patch),
                      "kernel_source_hash": kernel_source_hash()},
     }
+    # the reconstruction's contraction in both precision forms, on the final state
+    rec_ms = {}
+    outs = {}
+    for prec in ("fp32", "bf16"):
+        prob.set_precision(prec)
+        o = torch.empty(wl.shape, dtype=torch.float32, device="cuda")
+        prob.reconstruct(o)
+        prob.set_timing(True)
+        for _ in range(10):
+            prob.reconstruct(o)
+        rec_ms[prec] = prob.stats()["ms_recon"] / 10
+        prob.set_timing(False)
+        outs[prec] = o.cpu().numpy().astype(np.float64)
+    prob.set_precision("fp32")
+    res["reconstruct_ms"] = rec_ms
     if not args.no_quality:
         x = out_d.cpu().numpy()
         res["psnr_db"] = metrics.psnr(x, g)
         res["ssim"] = metrics.ssim(x, g)
+        res["psnr_db_bf16"] = metrics.psnr(outs["bf16"], g)
+        res["bf16_vs_fp32_rel_err"] = float(np.linalg.norm(outs["bf16"] - outs["fp32"]) /
+                                            np.linalg.norm(outs["fp32"]))
     if not args.no_serving:
         sv = serving_run(duration_s=args.serving_seconds)
         res["serving"] = sv

@@ -21,19 +21,39 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def build(verbose=False, extra=()):
+def _run(cmd):
+    return subprocess.run(cmd, capture_output=True, text=True)
+
+
+def build(verbose=False, extra=(), jobs=None):
+    """Compile every source to an object in parallel, then link the shared library."""
+    import concurrent.futures
+    import tempfile
     os.makedirs(LIB_DIR, exist_ok=True)
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB_PATH + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-o", tmp, *sources()]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libbpfa.so")
-    if verbose and res.stderr:
-        sys.stderr.write(res.stderr)
+    jobs = jobs or min(16, os.cpu_count() or 1)
+    with tempfile.TemporaryDirectory(prefix="bpfa_build_") as obj_dir:
+        cmds, objs = [], []
+        for src in sources():
+            obj = os.path.join(obj_dir, os.path.basename(src) + ".o")
+            objs.append(obj)
+            cmds.append([hipcc, *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-c",
+                         "-o", obj, src])
+        with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
+            results = list(ex.map(_run, cmds))
+        for cmd, res in zip(cmds, results):
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            if res.returncode != 0:
+                sys.stderr.write(res.stdout + res.stderr)
+                raise RuntimeError("hipcc failed on %s" % cmd[-1])
+            if verbose and res.stderr:
+                sys.stderr.write(res.stderr)
+        tmp = LIB_PATH + ".tmp"
+        res = _run([hipcc, *HIPCC_FLAGS, *extra, "-o", tmp, *objs])
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("hipcc failed linking libbpfa.so")
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
 

@@ -61,7 +61,7 @@ struct Layout {
   DictPlan plan;
   // byte offsets
   size_t image, mask, poff, pcoord, obs_bits, obs_count, perm, inv_perm, inv_prev, obs_idx, obs_val, block_J, sort_hist, sort_bin,
-      omega, omega_c, omega_blk, D, list0, list1, nact0, nact1, Ck, ell, scal, nk, sw_cnt, sw_part, dpart,
+      omega, omega_c, omega_blk, vslot, omega_y, D, list0, list1, nact0, nact1, Ck, ell, scal, nk, sw_cnt, sw_part, dpart,
       dx2, Cfull, Bvec, diag, x2p, sumr2_p, Y, recon, total;
 };
 
@@ -136,12 +136,14 @@ DictPlan make_dict_plan(const Geom& g) {
   long long rec_max = 0;
   for (int r = 0; r < pl.RG; ++r)
     rec_max = std::max(rec_max, (pl.ent0[r + 1] - pl.ent0[r]) + (long long)(pl.row0[r + 1] - pl.row0[r]));
-  const long long room = (long long)kLdsBytes - rec_max * 8 - 2LL * (K + 1) * 4;
-  pl.chunk_visits = (int)std::max<long long>(kDictBlock, room / 10 / kDictBlock * kDictBlock);
+  const long long room = (long long)kLdsBytes - rec_max * 8 - (long long)(K + 1) * 4;
+  pl.chunk_visits = (int)std::max<long long>(
+      kDictBlock, std::min<long long>(kDictBlock * kDictVpt, room / 10 / kDictBlock * kDictBlock));
   // partial accumulators per (p, row group): set per frame from the observed
   // pixels (bpfa_problem::dict_groups), at most this many
   const long long mt = g.Mtot;
   pl.chunks = (int)std::min<long long>(16, std::max<long long>(1, (mt + pl.chunk_visits - 1) / pl.chunk_visits));
+  if (pl.chunks > 1 && pl.chunks < 8) pl.chunks = 8;   // room for the XCD-aligned chunking
   return pl;
 }
 
@@ -196,6 +198,8 @@ Layout make_layout(const Geom& g) {
   L.omega = take(4 * (size_t)g.Mtot);
   L.omega_c = take(16 * (size_t)g.Mtot);
   L.omega_blk = take(4 * (((size_t)g.Mtot + 255) / 256 + 1));
+  L.vslot = take(4 * P * (size_t)g.Mtot);
+  L.omega_y = take(4 * (size_t)g.Mtot);
   L.D = take(4 * K * P);
   L.list0 = take(8 * Np * K);
   L.list1 = take(8 * Np * K);
@@ -344,11 +348,16 @@ bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask,
   h->max_obs = s.max_obs;
   h->n_omega = s.n_omega;
   {
-    // about two statistics blocks per CU; chunks no larger than the LDS holds
+    // chunks of observed pixels per (p, row group): enough for every CU, no larger than
+    // the LDS visit records hold, and a multiple of 8 where possible so that all the
+    // blocks of one chunk (every p) run on one XCD and share its L2 copy of the
+    // chunk's active lists
     const DictPlan& pl = h->L.plan;
     const int need = (h->n_omega + pl.chunk_visits - 1) / pl.chunk_visits;
-    const int fill = 512 / (g.P * pl.RG);
-    h->dict_groups = std::max(1, std::min(pl.chunks, std::max(need, fill)));
+    const int fill = 256 / (g.P * pl.RG);
+    int groups = std::max(1, std::max(need, fill));
+    if (pl.chunks >= 8) groups = (groups + 7) / 8 * 8;
+    h->dict_groups = std::max(1, std::min(pl.chunks, groups));
     const int per = (h->n_omega + h->dict_groups - 1) / h->dict_groups;
     h->dict_cv = std::min(pl.chunk_visits, std::max(kDictBlock, (per + kDictBlock - 1) / kDictBlock * kDictBlock));
   }
@@ -356,6 +365,7 @@ bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask,
     return fail(BPFA_ESHAPE, "a patch has %d observed pixels; at most 256 are supported", h->max_obs);
   const int J4 = std::max(4, (h->max_obs + 3) & ~3);
   HIPCHK(launch_slots(g, h->b, h->L.Npad, J4, h->st));
+  HIPCHK(launch_visit_table(g, h->b, h->n_omega, h->st));
   // launch ranges of the sweep: blocks ascend in J
   const int nblk = h->L.sweep_blocks;
   std::vector<int32_t> bj(nblk);
@@ -474,6 +484,8 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
   b.sort_bin = (int32_t*)(w + L.sort_bin);
   b.omega = (int32_t*)(w + L.omega);
   b.omega_c = (int4*)(w + L.omega_c);
+  b.vslot = (int32_t*)(w + L.vslot);
+  b.omega_y = (float*)(w + L.omega_y);
   b.omega_blk = (int32_t*)(w + L.omega_blk);
   b.D = (float*)(w + L.D);
   b.list[0] = (int2*)(w + L.list0);
@@ -626,7 +638,8 @@ bpfa_status bpfa_iterate(bpfa_t h, int32_t n_iters, uint32_t flags) {
       DictPlan plan = L.plan;
       plan.chunks = h->dict_groups;
       plan.chunk_visits = h->dict_cv;
-      HIPCHK(launch_dict_stats(g, b, plan, h->cur, L.Npad, h->st));
+      plan.xcd = plan.chunks % 8 == 0;
+      HIPCHK(launch_dict_stats(g, b, plan, h->cur, h->n_omega, h->st));
       HIPCHK(launch_dict_reduce(g, b, plan, h->st));
       HIPCHK(launch_dict_chain(g, b, L.plan, h->key0, h->key1, stream_word(2, h->prm.problem_id),
                                h->st));

@@ -12,6 +12,7 @@ constexpr int kSweepBlock = 256;      // 4 waves share one LDS copy of the dicti
 constexpr int kSlotAlign = kSweepBlock;
 constexpr int kLdsTileBytes = 64 * 1024;
 constexpr int kDictBlock = 1024;
+constexpr int kDictVpt = 8;       // visits per thread of one statistics chunk, held in registers
 constexpr int kLdsBytes = 160 * 1024 - 1024;   // per block, leaving room for static arrays
 constexpr int kDictLdsEntries = 16384; // int64 accumulators per statistics block (128 KiB)
 constexpr int kSortBlock = 256;        // patches per block of the slot sort
@@ -99,6 +100,8 @@ struct Buffers {
   long long* nk = nullptr;       // K
   int32_t* sw_cnt = nullptr;     // sweep blocks x K
   SweepPart* sw_part = nullptr;  // sweep blocks
+  int32_t* vslot = nullptr;      // [p][Mtot]: slot of the patch that observed pixel v shows at offset p, or -1
+  float* omega_y = nullptr;      // Mtot: value of observed pixel v
   long long* dpart = nullptr;    // dictionary statistics partials
   double* dx2 = nullptr;         // P x chunks: sum of y^2 over visits
   double* Cfull = nullptr;       // P x K x K
@@ -117,13 +120,14 @@ struct DictPlan {
   long long ent0[65];          // triangle entry offset of row0[r]
   int chunks = 1;
   int chunk_visits = 0;        // observed pixels per chunk (LDS visit records)
+  int xcd = 0;                 // chunks is a multiple of 8: map each chunk's blocks to one XCD
   long long rec_len_total = 0; // sum over row groups of (entries + rows)
   long long tri_entries = 0;   // K (K + 1) / 2
 };
 
 // bytes of LDS of the statistics kernel
 inline size_t dict_stats_lds(int K, long long rec_stride, int chunk_visits) {
-  return (size_t)rec_stride * 8 + (size_t)2 * (K + 1) * 4 + (size_t)chunk_visits * 10;
+  return (size_t)rec_stride * 8 + (size_t)(K + 1) * 4 + (size_t)chunk_visits * 10;
 }
 
 // First block of each sweep launch range (ranges of ascending J).
@@ -136,6 +140,7 @@ struct SweepLaunch {
 hipError_t launch_index(const Geom& g, const Buffers& b, int Npad, hipStream_t st);
 hipError_t launch_slots(const Geom& g, const Buffers& b, int Npad, int Jcap4, hipStream_t st);
 hipError_t launch_omega(const Geom& g, const Buffers& b, hipStream_t st);
+hipError_t launch_visit_table(const Geom& g, const Buffers& b, int n_omega, hipStream_t st);
 hipError_t launch_init_dict(const Geom& g, const Buffers& b, uint32_t key0, uint32_t key1,
                             uint32_t stream, hipStream_t st);
 hipError_t launch_sweep(const SweepLaunch& sl, size_t lds, const SweepArgs& a,
@@ -143,7 +148,7 @@ hipError_t launch_sweep(const SweepLaunch& sl, size_t lds, const SweepArgs& a,
 hipError_t launch_sort(const Geom& g, const Buffers& b, int Npad, hipStream_t st);
 hipError_t launch_sweep_reduce(const Geom& g, const Buffers& b, int blocks, hipStream_t st);
 hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& plan, int cur,
-                             int Npad, hipStream_t st);
+                             int n_omega, hipStream_t st);
 hipError_t launch_dict_reduce(const Geom& g, const Buffers& b, const DictPlan& plan,
                               hipStream_t st);
 hipError_t launch_dict_chain(const Geom& g, const Buffers& b, const DictPlan& plan,
@@ -152,9 +157,8 @@ hipError_t launch_scalars(const Geom& g, const Buffers& b, const double* hyper, 
                           uint32_t key0, uint32_t key1, uint32_t problem_id, hipStream_t st);
 hipError_t launch_recon(const Geom& g, const Buffers& b, int cur, int Npad, float* out, bool bf16,
                         hipStream_t st);
-hipError_t launch_recon_patches_mfma(const Geom& g, const Buffers& b, int cur, bool bf16,
-                                     hipStream_t st);
-size_t recon_mfma_lds(int P, bool bf16);
+hipError_t launch_recon_patches_mfma(const Geom& g, const Buffers& b, int cur, hipStream_t st);
+size_t recon_mfma_lds(int P);
 hipError_t launch_lists_to_dense(const Geom& g, const Buffers& b, int cur, float* W, uint8_t* Z,
                                  hipStream_t st);
 hipError_t launch_dense_to_lists(const Geom& g, const Buffers& b, int cur, int Npad,

@@ -35,7 +35,7 @@ namespace bpfa {
 constexpr int kStatsCap = 16;   // active entries of a patch held in registers
 
 struct DictPlanDev {
-  int RG, chunks, K, chunk_visits;
+  int RG, chunks, K, chunk_visits, xcd;
   int row0[65];
   long long ent0[65];
   long long rec_stride;
@@ -70,38 +70,73 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
-// LDS: rec int64 accumulators | 2 (K + 1) int bin counters | chunk visits
-// (slot int32, y float, n_a uint16).  Visits are bucketed by n_a inside the
-// block so each wavefront's pair loop runs to a bound its lanes share.
+// Per frame: for every position p and observed pixel v (in omega order), the
+// slot of the patch whose origin is q_v - b(p), or -1 when that origin is
+// off the grid; and the observed values in omega order.
+__global__ __launch_bounds__(256) void visit_table_kernel(Geom g, int nom, const int4* __restrict__ omega_c,
+                                                          const int32_t* __restrict__ omega,
+                                                          const float* __restrict__ image,
+                                                          const int32_t* __restrict__ pcoord,
+                                                          const int32_t* __restrict__ inv_perm,
+                                                          int32_t* __restrict__ vslot,
+                                                          float* __restrict__ omega_y) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (v >= nom) return;
+  int bc[kMaxDim] = {0, 0, 0, 0};
+  for (int d = 0; d < g.ndim; ++d) bc[d] = pcoord[p * kMaxDim + d];
+  const int pidx = visit_patch(g, omega_c[v], bc);
+  vslot[(size_t)p * g.Mtot + v] = pidx >= 0 ? inv_perm[pidx] : -1;
+  if (p == 0) omega_y[v] = image[omega[v]];
+}
+
+hipError_t launch_visit_table(const Geom& g, const Buffers& b, int n_omega, hipStream_t st) {
+  if (n_omega <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((n_omega + 255) / 256), (unsigned)g.P);
+  visit_table_kernel<<<grid, 256, 0, st>>>(g, n_omega, b.omega_c, b.omega, b.image, b.pcoord,
+                                           b.inv_perm, b.vslot, b.omega_y);
+  return hipGetLastError();
+}
+
+// LDS: rec int64 accumulators | K + 1 int bin starts | chunk visits (slot
+// int32, y float, n_a uint16).  Visits are bucketed by n_a inside the block so
+// each wavefront's pair loop runs to a bound its lanes share.
 __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
-    Geom g, DictPlanDev pl, const int4* __restrict__ omega_c, const int32_t* __restrict__ omega,
-    const float* __restrict__ image, const int32_t* __restrict__ pcoord,
-    const int32_t* __restrict__ inv_perm, const int2* __restrict__ list,
+    Geom g, DictPlanDev pl, int nom, const int32_t* __restrict__ vslot,
+    const float* __restrict__ omega_y, const int2* __restrict__ list,
     const int32_t* __restrict__ nact, const DevScalars* __restrict__ scal,
     long long* __restrict__ dpart, double* __restrict__ dx2) {
   extern __shared__ long long acc[];
   __shared__ double s_x2[kDictBlock / kWave];
-  const int per_p = pl.RG * pl.chunks;
-  const int p = blockIdx.x / per_p;
-  const int rg = (blockIdx.x % per_p) / pl.chunks;
-  const int c = blockIdx.x % pl.chunks;
+  __shared__ int s_total;
+  // block -> (chunk c, position p, row group rg).  Workgroups are dispatched
+  // round-robin over the 8 XCDs; with chunks a multiple of 8 every block of
+  // chunk c has blockIdx = c mod 8, so the P blocks that read the same
+  // patches' lists share one L2.
+  int c, prg;
+  if (pl.xcd) {
+    const int cg = pl.chunks >> 3, j = blockIdx.x >> 3;
+    c = (blockIdx.x & 7) + 8 * (j % cg);
+    prg = j / cg;
+  } else {
+    c = blockIdx.x % pl.chunks;
+    prg = blockIdx.x / pl.chunks;
+  }
+  const int p = prg / pl.RG, rg = prg % pl.RG;
   const int r0 = pl.row0[rg], r1 = pl.row0[rg + 1];
   const long long e0 = pl.ent0[rg];
   const int E = (int)(pl.ent0[rg + 1] - e0);
   const int rec = E + (r1 - r0);
   const int K = g.K;
-  int* bins = reinterpret_cast<int*>(acc + pl.rec_stride);          // K + 1 starts
-  int* cursor = bins + (K + 1);                                       // K + 1 fill cursors
-  int* v_slot = cursor + (K + 1);
+  int* bins = reinterpret_cast<int*>(acc + pl.rec_stride);          // K + 1 counts, then starts
+  int* v_slot = bins + (K + 1);
   float* v_y = reinterpret_cast<float*>(v_slot + pl.chunk_visits);
   uint16_t* v_na = reinterpret_cast<uint16_t*>(v_y + pl.chunk_visits);
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
   for (int e = tid; e < rec; e += kDictBlock) acc[e] = 0;
 
   const double sc = scal->scale_c, sb = scal->scale_b;
-  const int nom = scal->n_omega;
-  int bc[kMaxDim] = {0, 0, 0, 0};
-  for (int d = 0; d < g.ndim; ++d) bc[d] = pcoord[p * kMaxDim + d];
+  const int32_t* vs = vslot + (size_t)p * g.Mtot;
   double x2 = 0.0;
 
   // block c of its (p, row group) takes chunks c, c + chunks, ... of the observed pixels
@@ -110,10 +145,28 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
   for (int e = tid; e <= K; e += kDictBlock) bins[e] = 0;
   __syncthreads();
 
-  // pass 1: visits per n_a
-  for (int v = v0 + tid; v < v1; v += kDictBlock) {
-    const int pidx = visit_patch(g, omega_c[v], bc);
-    if (pidx >= 0) atomicAdd(&bins[nact[inv_perm[pidx]]], 1);
+  // pass 1: this thread's visits (at most kDictVpt) in registers; rank within its n_a bin
+  int r_slot[kDictVpt], r_na[kDictVpt], r_rank[kDictVpt];
+  float r_y[kDictVpt];
+#pragma unroll
+  for (int u = 0; u < kDictVpt; ++u) {
+    const int v = v0 + tid + u * kDictBlock;
+    r_slot[u] = -1;
+    r_y[u] = 0.f;
+    if (v < v1) {
+      r_slot[u] = vs[v];
+      r_y[u] = omega_y[v];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kDictVpt; ++u) r_na[u] = r_slot[u] >= 0 ? nact[r_slot[u]] : 0;
+#pragma unroll
+  for (int u = 0; u < kDictVpt; ++u) {
+    r_rank[u] = 0;
+    if (r_slot[u] >= 0) {
+      r_rank[u] = atomicAdd(&bins[r_na[u]], 1);
+      if (rg == 0) x2 += (double)r_y[u] * (double)r_y[u];
+    }
   }
   __syncthreads();
   if (tid < kWave) {   // exclusive scan of the bins by one wavefront
@@ -126,31 +179,23 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
         const int y = __shfl_up(incl, o);
         if (lane >= o) incl += y;
       }
-      if (b <= K) {
-        bins[b] = run + incl - x;
-        cursor[b] = run + incl - x;
-      }
+      if (b <= K) bins[b] = run + incl - x;
       run += __shfl(incl, kWave - 1);
     }
+    if (lane == 0) s_total = run;
   }
   __syncthreads();
   // pass 2: place the visits, grouped by n_a
-  for (int v = v0 + tid; v < v1; v += kDictBlock) {
-    const int pidx = visit_patch(g, omega_c[v], bc);
-    if (pidx >= 0) {
-      const int slot = inv_perm[pidx];
-      const int na = nact[slot];
-      const int pos = atomicAdd(&cursor[na], 1);
-      const float y = image[omega[v]];
-      v_slot[pos] = slot;
-      v_y[pos] = y;
-      v_na[pos] = (uint16_t)na;
-      // X2 here, where a thread's visits do not depend on the placement order
-      if (rg == 0) x2 += (double)y * (double)y;
+#pragma unroll
+  for (int u = 0; u < kDictVpt; ++u)
+    if (r_slot[u] >= 0) {
+      const int pos = bins[r_na[u]] + r_rank[u];
+      v_slot[pos] = r_slot[u];
+      v_y[pos] = r_y[u];
+      v_na[pos] = (uint16_t)r_na[u];
     }
-  }
   __syncthreads();
-  const int nvis = cursor[K];
+  const int nvis = s_total;
   // pass 3: outer products into the accumulators
   for (int vb = 0; vb < nvis; vb += kDictBlock) {
     const int vi = vb + tid;
@@ -208,7 +253,7 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
   __syncthreads();   // the visit records are rewritten by the next chunk
   }
   __syncthreads();
-  long long* out = dpart + (size_t)blockIdx.x * pl.rec_stride;
+  long long* out = dpart + (size_t)(prg * pl.chunks + c) * pl.rec_stride;
   for (int e = tid; e < rec; e += kDictBlock) out[e] = acc[e];
   if (rg == 0) {
     for (int o = kWave / 2; o > 0; o >>= 1) x2 += __shfl_xor(x2, o);
@@ -389,6 +434,7 @@ static DictPlanDev to_dev(const Geom& g, const DictPlan& plan) {
   d.RG = plan.RG;
   d.chunks = plan.chunks;
   d.chunk_visits = plan.chunk_visits;
+  d.xcd = plan.xcd;
   d.K = g.K;
   long long stride = 0;
   for (int r = 0; r <= plan.RG; ++r) {
@@ -404,8 +450,7 @@ static DictPlanDev to_dev(const Geom& g, const DictPlan& plan) {
 }
 
 hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& plan, int cur,
-                             int Npad, hipStream_t st) {
-  (void)Npad;
+                             int n_omega, hipStream_t st) {
   const DictPlanDev d = to_dev(g, plan);
   const int blocks = g.P * plan.RG * plan.chunks;
   // the LDS holds visit records for the largest chunk the plan allows
@@ -413,9 +458,9 @@ hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& pl
   hipError_t e = hipFuncSetAttribute((const void*)dict_stats_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  dict_stats_kernel<<<blocks, kDictBlock, lds, st>>>(g, d, b.omega_c, b.omega, b.image, b.pcoord,
-                                                     b.inv_perm, b.list[cur], b.nact[cur], b.scal,
-                                                     b.dpart, b.dx2);
+  dict_stats_kernel<<<blocks, kDictBlock, lds, st>>>(g, d, n_omega, b.vslot, b.omega_y,
+                                                     b.list[cur], b.nact[cur], b.scal, b.dpart,
+                                                     b.dx2);
   return hipGetLastError();
 }
 

@@ -1,14 +1,80 @@
 // Overlap-averaged reconstruction and conversions of the sampler state.
 //
-// The patch models y_i = D^T w_i come from the matrix-core kernel
-// (kernels_recon_mfma.hip), stored pixel-major, Y[p][i], so that
-// neighbouring output pixels read neighbouring patches.
+// recon_sparse_kernel (binary32 form): the patch models y_i = D^T w_i from
+//   the active lists, one thread per (patch, run of 32 in-patch offsets), the
+//   dictionary's columns of that run staged in LDS; stored pixel-major,
+//   Y[p][i], so that neighbouring output pixels read neighbouring patches.
+//   (The BF16 form is the matrix-core kernel in kernels_recon_mfma.hip.)
 // recon_pixel_kernel: one thread per image pixel q sums Y[p][i] over every
 //   patch i and in-patch offset p with o_i + b(p) = q, in ascending p, and
 //   divides by the number of such pairs (the coverage of q).
 #include "internal.hpp"
 
 namespace bpfa {
+
+constexpr int kRsChunk = 32;       // in-patch offsets per thread
+constexpr int kRsStride = 36;      // LDS row stride (floats) of a dictionary atom's run
+constexpr int kRsCap = 16;         // active entries of a patch held in registers
+
+// grid (patch blocks, offset runs); LDS K x kRsStride floats
+__global__ __launch_bounds__(256) void recon_sparse_kernel(Geom g, const float* __restrict__ D,
+                                                           const int32_t* __restrict__ inv_perm,
+                                                           const int2* __restrict__ list,
+                                                           const int32_t* __restrict__ nact,
+                                                           float* __restrict__ Y) {
+  extern __shared__ __attribute__((aligned(16))) float dl[];
+  const int tid = threadIdx.x, P = g.P, K = g.K;
+  const int p0 = blockIdx.y * kRsChunk;
+  const int pc = min(kRsChunk, P - p0);
+  for (int idx = tid; idx < K * kRsChunk; idx += 256) {
+    const int k = idx / kRsChunk, u = idx - k * kRsChunk;
+    dl[k * kRsStride + u] = u < pc ? D[(size_t)k * P + p0 + u] : 0.f;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * 256 + tid;
+  if (i >= g.N) return;
+  const int s = inv_perm[i];
+  const int na = nact[s];
+  const int2* L = list + (size_t)s * K;
+  int ek[kRsCap];
+  float ew[kRsCap];
+#pragma unroll
+  for (int a = 0; a < kRsCap; ++a) {
+    ek[a] = 0;
+    ew[a] = 0.f;
+    if (a < na) {
+      const int2 e = L[a];
+      ek[a] = e.x;
+      ew[a] = __int_as_float(e.y);
+    }
+  }
+  float acc[kRsChunk];
+#pragma unroll
+  for (int u = 0; u < kRsChunk; ++u) acc[u] = 0.f;
+  auto add = [&](int k, float w) {
+    const float4* row = reinterpret_cast<const float4*>(dl + k * kRsStride);
+#pragma unroll
+    for (int q = 0; q < kRsChunk / 4; ++q) {
+      const float4 d = row[q];
+      acc[4 * q + 0] = fmaf(d.x, w, acc[4 * q + 0]);
+      acc[4 * q + 1] = fmaf(d.y, w, acc[4 * q + 1]);
+      acc[4 * q + 2] = fmaf(d.z, w, acc[4 * q + 2]);
+      acc[4 * q + 3] = fmaf(d.w, w, acc[4 * q + 3]);
+    }
+  };
+#pragma unroll
+  for (int a = 0; a < kRsCap; ++a)
+    if (a < na) add(ek[a], ew[a]);
+  for (int a = kRsCap; a < na; ++a) {
+    const int2 e = L[a];
+    add(e.x, __int_as_float(e.y));
+  }
+#pragma unroll
+  for (int u = 0; u < kRsChunk; ++u)
+    if (u < pc) Y[(size_t)(p0 + u) * g.N + i] = acc[u];
+}
+
+size_t recon_sparse_lds(int K) { return (size_t)K * kRsStride * 4; }
 
 // The pairs (i, p) that cover q form a box: per dimension the in-patch
 // offsets b_d <= q_d congruent to q_d mod S_d with q_d - b_d <= (G_d - 1) S_d.
@@ -60,8 +126,17 @@ __global__ __launch_bounds__(256) void recon_pixel_kernel(Geom g, const float* _
 hipError_t launch_recon(const Geom& g, const Buffers& b, int cur, int Npad, float* out, bool bf16,
                         hipStream_t st) {
   (void)Npad;
-  hipError_t e = launch_recon_patches_mfma(g, b, cur, bf16, st);
-  if (e != hipSuccess) return e;
+  if (bf16) {
+    const hipError_t e = launch_recon_patches_mfma(g, b, cur, st);
+    if (e != hipSuccess) return e;
+  } else {
+    const size_t lds = recon_sparse_lds(g.K);
+    const hipError_t e = hipFuncSetAttribute((const void*)recon_sparse_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const dim3 grid((unsigned)((g.N + 255) / 256), (unsigned)((g.P + kRsChunk - 1) / kRsChunk));
+    recon_sparse_kernel<<<grid, 256, lds, st>>>(g, b.D, b.inv_perm, b.list[cur], b.nact[cur], b.Y);
+  }
   recon_pixel_kernel<<<(g.Mtot + 255) / 256, 256, 0, st>>>(g, b.Y, out);
   return hipGetLastError();
 }

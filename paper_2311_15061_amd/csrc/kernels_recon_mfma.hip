@@ -6,11 +6,11 @@
 // wavefronts each own 32 patches (one 32-column tile of C) and every
 // 32-row tile of P; atoms are staged through LDS 64 at a time.
 //
-//  * FP32 form: v_mfma_f32_32x32x2_f32, binary32 products, binary32 sums.
-//  * BF16 form (precision form): each operand is split x = hi + lo with
-//    hi = bf16(x), lo = bf16(x - hi); C += hi.hi (v_mfma_f32_32x32x16_bf16)
-//    plus one correction pass hi.lo + lo.hi, accumulated in binary32; the
-//    dropped lo.lo term is below 2^-16 of |x||w|.
+// This is the BF16 precision form: each operand is split x = hi + lo with
+// hi = bf16(x), lo = bf16(x - hi); C += hi.hi (v_mfma_f32_32x32x16_bf16) plus
+// one correction pass hi.lo + lo.hi, accumulated in binary32; the dropped
+// lo.lo term is below 2^-16 of |x||w|.  (The binary32 form works from the
+// sparse lists on the vector ALUs: recon_sparse_kernel.)
 //
 // Output Y[p][i] (pixel-major), read by recon_pixel_kernel for the average.
 #include "internal.hpp"
@@ -23,7 +23,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kRmTile = 128;         // patches per block
 constexpr int kRmKc = 64;            // atoms per LDS stage
 constexpr int kRmStride = kRmKc + 8; // row stride (16-bit units) of the bf16 tiles
-constexpr int kRmStrideF = kRmKc + 1;// row stride (floats) of the fp32 tiles
+constexpr int kRmCap = 16;           // active entries of a patch held in registers
 
 __device__ __forceinline__ uint16_t bf16_bits(float x) {   // round to nearest even
   const uint32_t u = __float_as_uint(x);
@@ -31,8 +31,8 @@ __device__ __forceinline__ uint16_t bf16_bits(float x) {   // round to nearest e
 }
 __device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// MT: 32-row tiles of P (P <= 32 MT); BF16: precision form
-template <int MT, bool BF16>
+// MT: 32-row tiles of P (P <= 32 MT)
+template <int MT>
 __global__ __launch_bounds__(256) void recon_mfma_kernel(Geom g, const float* __restrict__ D,
                                                          const int32_t* __restrict__ inv_perm,
                                                          const int2* __restrict__ list,
@@ -45,12 +45,25 @@ __global__ __launch_bounds__(256) void recon_mfma_kernel(Geom g, const float* __
   // this thread densifies patch i0 + tid of the tile (first 128 threads)
   const int my_i = i0 + tid;
   const bool owner = tid < kRmTile && my_i < N;
-  int na = 0, cur = 0;
-  const int2* L = nullptr;
+  int na = 0;
+  const int2* L = list;
   if (owner) {
     const int s = inv_perm[my_i];
     na = nact[s];
     L = list + (size_t)s * K;
+  }
+  // the patch's first kRmCap entries, loaded once (independent loads)
+  int ek[kRmCap];
+  float ew[kRmCap];
+#pragma unroll
+  for (int a = 0; a < kRmCap; ++a) {
+    ek[a] = -1;
+    ew[a] = 0.f;
+    if (a < na) {
+      const int2 e = L[a];
+      ek[a] = e.x;
+      ew[a] = __int_as_float(e.y);
+    }
   }
   f32x16 acc[MT];
 #pragma unroll
@@ -60,7 +73,7 @@ __global__ __launch_bounds__(256) void recon_mfma_kernel(Geom g, const float* __
 
   for (int kc = 0; kc < K; kc += kRmKc) {
     __syncthreads();
-    if constexpr (BF16) {
+    {
       uint16_t* a_hi = reinterpret_cast<uint16_t*>(smem);
       uint16_t* a_lo = a_hi + MT * 32 * kRmStride;
       uint16_t* b_hi = a_lo + MT * 32 * kRmStride;
@@ -81,14 +94,21 @@ __global__ __launch_bounds__(256) void recon_mfma_kernel(Geom g, const float* __
       }
       __syncthreads();
       if (owner) {
-        while (cur < na) {
-          const int2 e = L[cur];
-          if (e.x >= kc + kRmKc) break;
-          const float w = __int_as_float(e.y);
-          const uint16_t h = bf16_bits(w);
-          b_hi[tid * kRmStride + (e.x - kc)] = h;
-          b_lo[tid * kRmStride + (e.x - kc)] = bf16_bits(w - bf16_value(h));
-          ++cur;
+#pragma unroll
+        for (int a = 0; a < kRmCap; ++a)
+          if (ek[a] >= kc && ek[a] < kc + kRmKc) {
+            const uint16_t h = bf16_bits(ew[a]);
+            b_hi[tid * kRmStride + (ek[a] - kc)] = h;
+            b_lo[tid * kRmStride + (ek[a] - kc)] = bf16_bits(ew[a] - bf16_value(h));
+          }
+        for (int a = kRmCap; a < na; ++a) {   // entries beyond the register stage
+          const int2 e = L[a];
+          if (e.x >= kc && e.x < kc + kRmKc) {
+            const float w = __int_as_float(e.y);
+            const uint16_t h = bf16_bits(w);
+            b_hi[tid * kRmStride + (e.x - kc)] = h;
+            b_lo[tid * kRmStride + (e.x - kc)] = bf16_bits(w - bf16_value(h));
+          }
         }
       }
       __syncthreads();
@@ -106,38 +126,6 @@ __global__ __launch_bounds__(256) void recon_mfma_kernel(Geom g, const float* __
           acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[m], 0, 0, 0);
         }
       }
-    } else {
-      float* a = reinterpret_cast<float*>(smem);
-      float* b = a + MT * 32 * kRmStrideF;
-      for (int idx = tid; idx < MT * 32 * kRmKc; idx += 256) {
-        const int kk = idx / (MT * 32), m = idx - kk * (MT * 32);
-        const int k = kc + kk;
-        a[m * kRmStrideF + kk] = (m < P && k < K) ? D[(size_t)k * P + m] : 0.f;
-      }
-      for (int idx = tid; idx < kRmTile * kRmKc; idx += 256) {
-        const int n = idx / kRmKc, kk = idx - n * kRmKc;
-        b[n * kRmStrideF + kk] = 0.f;
-      }
-      __syncthreads();
-      if (owner) {
-        while (cur < na) {
-          const int2 e = L[cur];
-          if (e.x >= kc + kRmKc) break;
-          b[tid * kRmStrideF + (e.x - kc)] = __int_as_float(e.y);
-          ++cur;
-        }
-      }
-      __syncthreads();
-      const int col = lane & 31, kq = lane >> 5;
-#pragma unroll 4
-      for (int ks = 0; ks < kRmKc; ks += 2) {
-        const float bv = b[(wv * 32 + col) * kRmStrideF + ks + kq];
-#pragma unroll
-        for (int m = 0; m < MT; ++m) {
-          const float av = a[(m * 32 + col) * kRmStrideF + ks + kq];
-          acc[m] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[m], 0, 0, 0);
-        }
-      }
     }
   }
   // lane holds column (patch) lane % 32 and rows 8 (r / 4) + 4 (lane / 32) + r % 4
@@ -153,45 +141,33 @@ __global__ __launch_bounds__(256) void recon_mfma_kernel(Geom g, const float* __
   }
 }
 
-size_t recon_mfma_lds(int P, bool bf16) {
+size_t recon_mfma_lds(int P) {
   const int MT = (P + 31) / 32;
-  if (bf16) return (size_t)2 * 2 * (MT * 32 + kRmTile) * kRmStride;
-  return (size_t)4 * (MT * 32 + kRmTile) * kRmStrideF;
+  return (size_t)2 * 2 * (MT * 32 + kRmTile) * kRmStride;
 }
 
 template <int MT>
-static hipError_t launch_mt(const Geom& g, const Buffers& b, int cur, bool bf16, hipStream_t st) {
-  const size_t lds = recon_mfma_lds(g.P, bf16);
+static hipError_t launch_mt(const Geom& g, const Buffers& b, int cur, hipStream_t st) {
+  const size_t lds = recon_mfma_lds(g.P);
   const int blocks = (g.N + kRmTile - 1) / kRmTile;
-  hipError_t e;
-  if (bf16) {
-    e = hipFuncSetAttribute((const void*)recon_mfma_kernel<MT, true>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    recon_mfma_kernel<MT, true><<<blocks, 256, lds, st>>>(g, b.D, b.inv_perm, b.list[cur],
-                                                          b.nact[cur], b.Y);
-  } else {
-    e = hipFuncSetAttribute((const void*)recon_mfma_kernel<MT, false>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    recon_mfma_kernel<MT, false><<<blocks, 256, lds, st>>>(g, b.D, b.inv_perm, b.list[cur],
-                                                           b.nact[cur], b.Y);
-  }
+  const hipError_t e = hipFuncSetAttribute((const void*)recon_mfma_kernel<MT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  recon_mfma_kernel<MT><<<blocks, 256, lds, st>>>(g, b.D, b.inv_perm, b.list[cur], b.nact[cur], b.Y);
   return hipGetLastError();
 }
 
 // patch models on the matrix cores; P up to 256
-hipError_t launch_recon_patches_mfma(const Geom& g, const Buffers& b, int cur, bool bf16,
-                                     hipStream_t st) {
+hipError_t launch_recon_patches_mfma(const Geom& g, const Buffers& b, int cur, hipStream_t st) {
   switch ((g.P + 31) / 32) {
-    case 1: return launch_mt<1>(g, b, cur, bf16, st);
-    case 2: return launch_mt<2>(g, b, cur, bf16, st);
-    case 3: return launch_mt<3>(g, b, cur, bf16, st);
-    case 4: return launch_mt<4>(g, b, cur, bf16, st);
-    case 5: return launch_mt<5>(g, b, cur, bf16, st);
-    case 6: return launch_mt<6>(g, b, cur, bf16, st);
-    case 7: return launch_mt<7>(g, b, cur, bf16, st);
-    case 8: return launch_mt<8>(g, b, cur, bf16, st);
+    case 1: return launch_mt<1>(g, b, cur, st);
+    case 2: return launch_mt<2>(g, b, cur, st);
+    case 3: return launch_mt<3>(g, b, cur, st);
+    case 4: return launch_mt<4>(g, b, cur, st);
+    case 5: return launch_mt<5>(g, b, cur, st);
+    case 6: return launch_mt<6>(g, b, cur, st);
+    case 7: return launch_mt<7>(g, b, cur, st);
+    case 8: return launch_mt<8>(g, b, cur, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -149,6 +149,8 @@ def test_sparse_code_only_parity():
     ((26, 26), (12, 12), (1, 1), 16, 0.35),       # |Obs| ~ 50: 36..64 register bodies
     ((22, 22), (12, 12), (1, 1), 12, 0.65),       # |Obs| ~ 94: guarded 128-register bodies
     ((28, 28), (12, 12), (1, 1), 20, 0.2),        # |Obs| spread over three ranges at once
+    ((96, 96), (6, 6), (1, 1), 16, 0.95),         # 8 statistics chunks, one XCD per chunk
+    ((400, 400), (4, 4), (1, 1), 8, 0.9),         # statistics blocks loop over several chunks
 ])
 def test_parity_geometry_cases(shape, patch, stride, K, rho):
     y, m, g = case(shape, patch, stride, K, rho, seed=K)
