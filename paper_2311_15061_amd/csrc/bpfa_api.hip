@@ -60,8 +60,8 @@ struct Layout {
   size_t sweep_lds = 0;
   DictPlan plan;
   // byte offsets
-  size_t image, mask, poff, pcoord, obs_bits, obs_count, perm, inv_perm, inv_prev, obs_idx, obs_val, block_J, sort_hist, sort_bin,
-      omega, omega_c, omega_blk, vslot, omega_y, D, list0, list1, nact0, nact1, Ck, ell, scal, nk, sw_cnt, sw_part, dpart,
+  size_t image, mask, poff, pcoord, obs_bits, obs_count, perm, inv_perm, obs_idx, obs_val, block_J, sort_hist, sort_bin,
+      omega, omega_c, omega_blk, vpatch, omega_y, D, list0, list1, nact0, nact1, Ck, ell, scal, nk, sw_cnt, sw_part, dpart,
       dx2, Cfull, Bvec, diag, x2p, sumr2_p, Y, recon, total;
 };
 
@@ -136,7 +136,7 @@ DictPlan make_dict_plan(const Geom& g) {
   long long rec_max = 0;
   for (int r = 0; r < pl.RG; ++r)
     rec_max = std::max(rec_max, (pl.ent0[r + 1] - pl.ent0[r]) + (long long)(pl.row0[r + 1] - pl.row0[r]));
-  const long long room = (long long)kLdsBytes - rec_max * 8 - (long long)(K + 1) * 4;
+  const long long room = (long long)kLdsBytes - (rec_max + kWave) * 8 - (long long)(K + 1) * 4;
   pl.chunk_visits = (int)std::max<long long>(
       kDictBlock, std::min<long long>(kDictBlock * kDictVpt, room / 10 / kDictBlock * kDictBlock));
   // partial accumulators per (p, row group): set per frame from the observed
@@ -165,8 +165,8 @@ Layout make_layout(const Geom& g) {
   L.KS = L.KT + 1;
   if (L.KS % 2 == 0) L.KS += 1;
   L.sweep_blocks = L.Npad / kSweepBlock;
-  // tile, then per-wave z counts (bytes)
-  L.sweep_lds = (size_t)P1 * L.KS * 4 + align_up((size_t)g.K * (kSweepBlock / kWave), 4);
+  // tile, then per-wave z counts (bytes), then C_k (floats)
+  L.sweep_lds = (size_t)P1 * L.KS * 4 + align_up((size_t)g.K * (kSweepBlock / kWave), 4) + 4 * (size_t)g.K;
   L.plan = make_dict_plan(g);
   long long rec_stride = 0;
   for (int r = 0; r < L.plan.RG; ++r) {
@@ -189,7 +189,6 @@ Layout make_layout(const Geom& g) {
   L.obs_count = take(4 * N);
   L.perm = take(4 * Np);
   L.inv_perm = take(4 * N);
-  L.inv_prev = take(4 * N);
   L.obs_idx = take(2 * (size_t)L.Jcap * Np);
   L.obs_val = take(4 * (size_t)L.Jcap * Np);
   L.block_J = take(4 * (Np / kSweepBlock));
@@ -198,7 +197,7 @@ Layout make_layout(const Geom& g) {
   L.omega = take(4 * (size_t)g.Mtot);
   L.omega_c = take(16 * (size_t)g.Mtot);
   L.omega_blk = take(4 * (((size_t)g.Mtot + 255) / 256 + 1));
-  L.vslot = take(4 * P * (size_t)g.Mtot);
+  L.vpatch = take(4 * P * (size_t)g.Mtot);
   L.omega_y = take(4 * (size_t)g.Mtot);
   L.D = take(4 * K * P);
   L.list0 = take(8 * Np * K);
@@ -319,7 +318,7 @@ bpfa_status check_status(bpfa_problem* h) {
 }
 
 // Upload a frame and rebuild the patch index.  keep_codes: the active lists
-// follow their patches into the new slot order (otherwise they are cleared).
+// (stored by patch, not by slot) stay as they are; otherwise they are cleared.
 bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask, bpfa_mem mem,
                        bool keep_codes) {
   const Geom& g = h->g;
@@ -329,15 +328,9 @@ bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask,
   if (r != BPFA_OK) return r;
   std::array<hipEvent_t, 2> ev{};
   if (h->timing && (r = record(h, &ev[0])) != BPFA_OK) return r;
-  if (keep_codes)
-    HIPCHK(hipMemcpyAsync(h->b.inv_prev, h->b.inv_perm, 4 * (size_t)g.N, hipMemcpyDeviceToDevice,
-                          h->st));
   HIPCHK(launch_index(g, h->b, h->L.Npad, h->st));
   HIPCHK(launch_sort(g, h->b, h->L.Npad, h->st));
-  if (keep_codes) {
-    HIPCHK(launch_remap_lists(g, h->b, h->cur, h->st));
-    h->cur = 1 - h->cur;
-  } else {
+  if (!keep_codes) {
     HIPCHK(hipMemsetAsync(h->b.nact[0], 0, 4 * (size_t)h->L.Npad, h->st));
     HIPCHK(hipMemsetAsync(h->b.nact[1], 0, 4 * (size_t)h->L.Npad, h->st));
   }
@@ -476,7 +469,6 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
   b.obs_count = (int32_t*)(w + L.obs_count);
   b.perm = (uint32_t*)(w + L.perm);
   b.inv_perm = (int32_t*)(w + L.inv_perm);
-  b.inv_prev = (int32_t*)(w + L.inv_prev);
   b.obs_idx = (uint16_t*)(w + L.obs_idx);
   b.obs_val = (float*)(w + L.obs_val);
   b.block_J = (int32_t*)(w + L.block_J);
@@ -484,7 +476,7 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
   b.sort_bin = (int32_t*)(w + L.sort_bin);
   b.omega = (int32_t*)(w + L.omega);
   b.omega_c = (int4*)(w + L.omega_c);
-  b.vslot = (int32_t*)(w + L.vslot);
+  b.vpatch = (int32_t*)(w + L.vpatch);
   b.omega_y = (float*)(w + L.omega_y);
   b.omega_blk = (int32_t*)(w + L.omega_blk);
   b.D = (float*)(w + L.D);
@@ -641,8 +633,12 @@ bpfa_status bpfa_iterate(bpfa_t h, int32_t n_iters, uint32_t flags) {
       plan.xcd = plan.chunks % 8 == 0;
       HIPCHK(launch_dict_stats(g, b, plan, h->cur, h->n_omega, h->st));
       HIPCHK(launch_dict_reduce(g, b, plan, h->st));
-      HIPCHK(launch_dict_chain(g, b, L.plan, h->key0, h->key1, stream_word(2, h->prm.problem_id),
-                               h->st));
+      if (g.K <= kChainLdsMaxK && g.K % 2 == 0)
+        HIPCHK(launch_dict_chain_lds(g, b, h->key0, h->key1, stream_word(2, h->prm.problem_id),
+                                     h->st));
+      else
+        HIPCHK(launch_dict_chain(g, b, L.plan, h->key0, h->key1,
+                                 stream_word(2, h->prm.problem_id), h->st));
     }
     if (h->timing && (r = record(h, &ev[2])) != BPFA_OK) return r;
     HIPCHK(launch_scalars(g, b, hyper, learn, h->key0, h->key1, h->prm.problem_id, h->st));

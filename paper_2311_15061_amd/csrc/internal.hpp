@@ -13,6 +13,7 @@ constexpr int kSlotAlign = kSweepBlock;
 constexpr int kLdsTileBytes = 64 * 1024;
 constexpr int kDictBlock = 1024;
 constexpr int kDictVpt = 8;       // visits per thread of one statistics chunk, held in registers
+constexpr int kChainLdsMaxK = 128;  // largest K whose binary64 C_p (K x K) the chain stages in LDS
 constexpr int kLdsBytes = 160 * 1024 - 1024;   // per block, leaving room for static arrays
 constexpr int kDictLdsEntries = 16384; // int64 accumulators per statistics block (128 KiB)
 constexpr int kSortBlock = 256;        // patches per block of the slot sort
@@ -65,8 +66,8 @@ struct SweepArgs {
   const float* D;                // K x P
   const float* Ck;               // K: logit pi_k + ln(gamma_s) / 2
   const DevScalars* scal;
-  const int2* list_in;           // [Npad][K] active (atom, weight bits), ascending atom
-  const int32_t* nact_in;        // [Npad]
+  const int2* list_in;           // [N][K] by patch: active (atom, weight bits), ascending atom
+  const int32_t* nact_in;        // [N] by patch
   int2* list_out;
   int32_t* nact_out;
   int32_t* cnt;                  // [gridDim][K] z counts per block
@@ -82,7 +83,6 @@ struct Buffers {
   int32_t* obs_count = nullptr;  // N
   uint32_t* perm = nullptr;      // Npad slot -> patch
   int32_t* inv_perm = nullptr;   // N patch -> slot
-  int32_t* inv_prev = nullptr;   // N: patch -> slot of the previous frame
   uint16_t* obs_idx = nullptr;   // [Jcap][Npad]
   float* obs_val = nullptr;      // [Jcap][Npad]
   int32_t* block_J = nullptr;    // Npad / kSweepBlock
@@ -100,7 +100,7 @@ struct Buffers {
   long long* nk = nullptr;       // K
   int32_t* sw_cnt = nullptr;     // sweep blocks x K
   SweepPart* sw_part = nullptr;  // sweep blocks
-  int32_t* vslot = nullptr;      // [p][Mtot]: slot of the patch that observed pixel v shows at offset p, or -1
+  int32_t* vpatch = nullptr;     // [p][Mtot]: patch that shows observed pixel v at offset p, or -1
   float* omega_y = nullptr;      // Mtot: value of observed pixel v
   long long* dpart = nullptr;    // dictionary statistics partials
   double* dx2 = nullptr;         // P x chunks: sum of y^2 over visits
@@ -127,7 +127,7 @@ struct DictPlan {
 
 // bytes of LDS of the statistics kernel
 inline size_t dict_stats_lds(int K, long long rec_stride, int chunk_visits) {
-  return (size_t)rec_stride * 8 + (size_t)(K + 1) * 4 + (size_t)chunk_visits * 10;
+  return (size_t)(rec_stride + kWave) * 8 + (size_t)(K + 1) * 4 + (size_t)chunk_visits * 10;
 }
 
 // First block of each sweep launch range (ranges of ascending J).
@@ -151,6 +151,8 @@ hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& pl
                              int n_omega, hipStream_t st);
 hipError_t launch_dict_reduce(const Geom& g, const Buffers& b, const DictPlan& plan,
                               hipStream_t st);
+hipError_t launch_dict_chain_lds(const Geom& g, const Buffers& b, uint32_t key0, uint32_t key1,
+                                 uint32_t stream, hipStream_t st);
 hipError_t launch_dict_chain(const Geom& g, const Buffers& b, const DictPlan& plan,
                              uint32_t key0, uint32_t key1, uint32_t stream, hipStream_t st);
 hipError_t launch_scalars(const Geom& g, const Buffers& b, const double* hyper, int learn_dict,
@@ -164,7 +166,6 @@ hipError_t launch_lists_to_dense(const Geom& g, const Buffers& b, int cur, float
 hipError_t launch_dense_to_lists(const Geom& g, const Buffers& b, int cur, int Npad,
                                  const float* W, const uint8_t* Z, int* bad, hipStream_t st);
 hipError_t launch_ck(const Geom& g, const Buffers& b, hipStream_t st);
-hipError_t launch_remap_lists(const Geom& g, const Buffers& b, int cur, hipStream_t st);
 hipError_t launch_set_t(DevScalars* scal, long long t, hipStream_t st);
 hipError_t launch_reset_scalars(const Geom& g, const Buffers& b, double ell0, double gamma_s0,
                                 double gamma_eps0, hipStream_t st);

@@ -34,6 +34,7 @@ namespace bpfa {
 
 constexpr int kStatsCap = 16;   // active entries of a patch held in registers
 
+
 struct DictPlanDev {
   int RG, chunks, K, chunk_visits, xcd;
   int row0[65];
@@ -70,15 +71,48 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
+// Pair accumulation of one visit.  Branch-free: an entry that does not
+// contribute (past the patch's n_a, or outside the block's row group) adds an
+// exact zero to the lane's own sink entry, so no lane toggles the exec mask
+// and the scalar unit (one per CU) stays out of the inner loop.
+struct StatsRow {
+  long long* acc;
+  long long* sink;
+  int r0, r1;
+  long long e0;
+  int E, K;
+  double sc, ysb;
+  // accumulator offset of row k: entry (k, j), j >= k, is at row_off(k) + j
+  __device__ __forceinline__ int row_off(int k) const { return (int)(tri_off(k, K) - e0) - k; }
+};
+
+template <int NB>
+__device__ __forceinline__ void stats_pairs(const StatsRow& sr, const int (&kk)[kStatsCap],
+                                            const double (&ww)[kStatsCap]) {
+#pragma unroll
+  for (int a = 0; a < NB; ++a) {
+    const bool ina = kk[a] >= sr.r0 && kk[a] < sr.r1;   // kk = -1 past n_a
+    const double wa = ina ? ww[a] : 0.0;
+    atomicAdd((unsigned long long*)(ina ? sr.acc + sr.E + (kk[a] - sr.r0) : sr.sink),
+              to_fixed(wa * sr.ysb));
+    const double was = wa * sr.sc;
+    const int row = sr.row_off(ina ? kk[a] : 0);
+#pragma unroll
+    for (int b = a; b < NB; ++b) {
+      long long* pc = (ina && kk[b] >= 0) ? sr.acc + (row + kk[b]) : sr.sink;
+      atomicAdd((unsigned long long*)pc, to_fixed(was * ww[b]));
+    }
+  }
+}
+
 // Per frame: for every position p and observed pixel v (in omega order), the
-// slot of the patch whose origin is q_v - b(p), or -1 when that origin is
-// off the grid; and the observed values in omega order.
+// patch whose origin is q_v - b(p), or -1 when that origin is off the grid;
+// and the observed values in omega order.
 __global__ __launch_bounds__(256) void visit_table_kernel(Geom g, int nom, const int4* __restrict__ omega_c,
                                                           const int32_t* __restrict__ omega,
                                                           const float* __restrict__ image,
                                                           const int32_t* __restrict__ pcoord,
-                                                          const int32_t* __restrict__ inv_perm,
-                                                          int32_t* __restrict__ vslot,
+                                                          int32_t* __restrict__ vpatch,
                                                           float* __restrict__ omega_y) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   const int p = blockIdx.y;
@@ -86,7 +120,7 @@ __global__ __launch_bounds__(256) void visit_table_kernel(Geom g, int nom, const
   int bc[kMaxDim] = {0, 0, 0, 0};
   for (int d = 0; d < g.ndim; ++d) bc[d] = pcoord[p * kMaxDim + d];
   const int pidx = visit_patch(g, omega_c[v], bc);
-  vslot[(size_t)p * g.Mtot + v] = pidx >= 0 ? inv_perm[pidx] : -1;
+  vpatch[(size_t)p * g.Mtot + v] = pidx;
   if (p == 0) omega_y[v] = image[omega[v]];
 }
 
@@ -94,15 +128,15 @@ hipError_t launch_visit_table(const Geom& g, const Buffers& b, int n_omega, hipS
   if (n_omega <= 0) return hipSuccess;
   const dim3 grid((unsigned)((n_omega + 255) / 256), (unsigned)g.P);
   visit_table_kernel<<<grid, 256, 0, st>>>(g, n_omega, b.omega_c, b.omega, b.image, b.pcoord,
-                                           b.inv_perm, b.vslot, b.omega_y);
+                                           b.vpatch, b.omega_y);
   return hipGetLastError();
 }
 
-// LDS: rec int64 accumulators | K + 1 int bin starts | chunk visits (slot
+// LDS: rec int64 accumulators | 64 per-lane sinks | K + 1 int bin starts | chunk visits (patch
 // int32, y float, n_a uint16).  Visits are bucketed by n_a inside the block so
 // each wavefront's pair loop runs to a bound its lanes share.
 __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
-    Geom g, DictPlanDev pl, int nom, const int32_t* __restrict__ vslot,
+    Geom g, DictPlanDev pl, int nom, const int32_t* __restrict__ vpatch,
     const float* __restrict__ omega_y, const int2* __restrict__ list,
     const int32_t* __restrict__ nact, const DevScalars* __restrict__ scal,
     long long* __restrict__ dpart, double* __restrict__ dx2) {
@@ -111,13 +145,14 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
   __shared__ int s_total;
   // block -> (chunk c, position p, row group rg).  Workgroups are dispatched
   // round-robin over the 8 XCDs; with chunks a multiple of 8 every block of
-  // chunk c has blockIdx = c mod 8, so the P blocks that read the same
-  // patches' lists share one L2.
+  // chunk c has blockIdx = c mod 8, and an XCD takes all (p, rg) blocks of
+  // one chunk before its next chunk, so the blocks that read the same
+  // patches' lists (a band of image rows) run together on one L2.
   int c, prg;
   if (pl.xcd) {
-    const int cg = pl.chunks >> 3, j = blockIdx.x >> 3;
-    c = (blockIdx.x & 7) + 8 * (j % cg);
-    prg = j / cg;
+    const int npr = gridDim.x / pl.chunks, j = blockIdx.x >> 3;
+    c = (blockIdx.x & 7) + 8 * (j / npr);
+    prg = j % npr;
   } else {
     c = blockIdx.x % pl.chunks;
     prg = blockIdx.x / pl.chunks;
@@ -128,15 +163,15 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
   const int E = (int)(pl.ent0[rg + 1] - e0);
   const int rec = E + (r1 - r0);
   const int K = g.K;
-  int* bins = reinterpret_cast<int*>(acc + pl.rec_stride);          // K + 1 counts, then starts
-  int* v_slot = bins + (K + 1);
-  float* v_y = reinterpret_cast<float*>(v_slot + pl.chunk_visits);
+  int* bins = reinterpret_cast<int*>(acc + pl.rec_stride + kWave); // K + 1 counts, then starts
+  int* v_pat = bins + (K + 1);
+  float* v_y = reinterpret_cast<float*>(v_pat + pl.chunk_visits);
   uint16_t* v_na = reinterpret_cast<uint16_t*>(v_y + pl.chunk_visits);
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
   for (int e = tid; e < rec; e += kDictBlock) acc[e] = 0;
 
   const double sc = scal->scale_c, sb = scal->scale_b;
-  const int32_t* vs = vslot + (size_t)p * g.Mtot;
+  const int32_t* vs = vpatch + (size_t)p * g.Mtot;
   double x2 = 0.0;
 
   // block c of its (p, row group) takes chunks c, c + chunks, ... of the observed pixels
@@ -146,24 +181,24 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
   __syncthreads();
 
   // pass 1: this thread's visits (at most kDictVpt) in registers; rank within its n_a bin
-  int r_slot[kDictVpt], r_na[kDictVpt], r_rank[kDictVpt];
+  int r_pat[kDictVpt], r_na[kDictVpt], r_rank[kDictVpt];
   float r_y[kDictVpt];
 #pragma unroll
   for (int u = 0; u < kDictVpt; ++u) {
     const int v = v0 + tid + u * kDictBlock;
-    r_slot[u] = -1;
+    r_pat[u] = -1;
     r_y[u] = 0.f;
     if (v < v1) {
-      r_slot[u] = vs[v];
+      r_pat[u] = vs[v];
       r_y[u] = omega_y[v];
     }
   }
 #pragma unroll
-  for (int u = 0; u < kDictVpt; ++u) r_na[u] = r_slot[u] >= 0 ? nact[r_slot[u]] : 0;
+  for (int u = 0; u < kDictVpt; ++u) r_na[u] = r_pat[u] >= 0 ? nact[r_pat[u]] : 0;
 #pragma unroll
   for (int u = 0; u < kDictVpt; ++u) {
     r_rank[u] = 0;
-    if (r_slot[u] >= 0) {
+    if (r_pat[u] >= 0) {
       r_rank[u] = atomicAdd(&bins[r_na[u]], 1);
       if (rg == 0) x2 += (double)r_y[u] * (double)r_y[u];
     }
@@ -188,9 +223,9 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
   // pass 2: place the visits, grouped by n_a
 #pragma unroll
   for (int u = 0; u < kDictVpt; ++u)
-    if (r_slot[u] >= 0) {
+    if (r_pat[u] >= 0) {
       const int pos = bins[r_na[u]] + r_rank[u];
-      v_slot[pos] = r_slot[u];
+      v_pat[pos] = r_pat[u];
       v_y[pos] = r_y[u];
       v_na[pos] = (uint16_t)r_na[u];
     }
@@ -200,53 +235,63 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
   for (int vb = 0; vb < nvis; vb += kDictBlock) {
     const int vi = vb + tid;
     const bool on = vi < nvis;
-    const int slot = on ? v_slot[vi] : 0;
+    const int pid = on ? v_pat[vi] : 0;
     const int na = on ? (int)v_na[vi] : 0;
     const double y = on ? (double)v_y[vi] : 0.0;
     const int wmax = __builtin_amdgcn_readfirstlane(wave_max_i(na));
-    const int2* L = list + (size_t)slot * K;
+    const int2* L = list + (size_t)pid * K;
+    // the first entries up to the wave's bound, loads issued together (a
+    // clamped index stays inside the patch's list row)
+    int2 raw[kStatsCap];
+#pragma unroll
+    for (int a = 0; a < kStatsCap; ++a) {
+      raw[a] = make_int2(-1, 0);
+      if (a < wmax) raw[a] = L[min(a, K - 1)];
+    }
     int kk[kStatsCap];
     double ww[kStatsCap];
 #pragma unroll
     for (int a = 0; a < kStatsCap; ++a) {
-      kk[a] = -1;
-      ww[a] = 0.0;
-      if (a < wmax && a < na) {
-        const int2 e = L[a];
-        kk[a] = e.x;
-        ww[a] = (double)__int_as_float(e.y);
-      }
+      const bool in = a < na;
+      kk[a] = in ? raw[a].x : -1;
+      ww[a] = in ? (double)__int_as_float(raw[a].y) : 0.0;
     }
     const double ysb = y * sb;
-#pragma unroll
-    for (int a = 0; a < kStatsCap; ++a) {
-      if (a < wmax) {
-        if (kk[a] >= r0 && kk[a] < r1) {
-          atomicAdd((unsigned long long*)&acc[E + (kk[a] - r0)], to_fixed(ww[a] * ysb));
-          const double wa = ww[a] * sc;
-          const int base = (int)(tri_off(kk[a], K) - e0) - kk[a];
-#pragma unroll
-          for (int b = a; b < kStatsCap; ++b)
-            if (b < wmax && kk[b] >= 0)
-              atomicAdd((unsigned long long*)&acc[base + kk[b]], to_fixed(wa * ww[b]));
-        }
-      }
+    long long* const sink = acc + pl.rec_stride + lane;
+    const StatsRow sr{acc, sink, r0, r1, e0, E, K, sc, ysb};
+    switch ((min(wmax, kStatsCap) + 1) >> 1) {
+      case 1: stats_pairs<2>(sr, kk, ww); break;
+      case 2: stats_pairs<4>(sr, kk, ww); break;
+      case 3: stats_pairs<6>(sr, kk, ww); break;
+      case 4: stats_pairs<8>(sr, kk, ww); break;
+      case 5: stats_pairs<10>(sr, kk, ww); break;
+      case 6: stats_pairs<12>(sr, kk, ww); break;
+      case 7: stats_pairs<14>(sr, kk, ww); break;
+      case 8: stats_pairs<16>(sr, kk, ww); break;
+      default: break;
     }
-    // entries beyond the register stage: every pair (a, b), a <= b, with b >= kStatsCap
-    if (wmax > kStatsCap) {
-      for (int b = kStatsCap; b < na; ++b) {
-        const int2 eb = L[b];
-        const double wb = (double)__int_as_float(eb.y);
-        if (eb.x >= r0 && eb.x < r1)
-          atomicAdd((unsigned long long*)&acc[E + (eb.x - r0)], to_fixed(wb * ysb));
-        for (int a = 0; a <= b; ++a) {
-          const int2 ea = L[a];
-          if (ea.x >= r0 && ea.x < r1) {
-            const int base = (int)(tri_off(ea.x, K) - e0) - ea.x;
-            atomicAdd((unsigned long long*)&acc[base + eb.x],
-                      to_fixed((double)__int_as_float(ea.y) * sc * wb));
-          }
-        }
+    // entries beyond the register stage (rare): pairs (a, b), a <= b, b >= kStatsCap
+    for (int b = kStatsCap; b < wmax; ++b) {
+      int2 eb = make_int2(-1, 0);
+      if (b < na) eb = L[b];
+      const bool inb = b < na;
+      const double wb = inb ? (double)__int_as_float(eb.y) : 0.0;
+      const bool inbr = inb && eb.x >= r0 && eb.x < r1;
+      atomicAdd((unsigned long long*)(inbr ? acc + E + (eb.x - r0) : sink),
+                to_fixed((inbr ? wb : 0.0) * ysb));
+#pragma unroll
+      for (int a = 0; a < kStatsCap; ++a) {
+        const bool ok = inb && kk[a] >= r0 && kk[a] < r1;
+        long long* pc = ok ? acc + (sr.row_off(kk[a]) + eb.x) : sink;
+        atomicAdd((unsigned long long*)pc, to_fixed(ok ? ww[a] * sc * wb : 0.0));
+      }
+      for (int a = kStatsCap; a <= b; ++a) {
+        int2 ea = make_int2(-1, 0);
+        if (a < na) ea = L[a];
+        const bool ok = inb && a < na && ea.x >= r0 && ea.x < r1;
+        long long* pc = ok ? acc + (sr.row_off(ea.x) + eb.x) : sink;
+        atomicAdd((unsigned long long*)pc,
+                  to_fixed(ok ? (double)__int_as_float(ea.y) * sc * wb : 0.0));
       }
     }
   }
@@ -319,14 +364,15 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 // t_k = g_k (B_k + C_kk d_k) + n_k / sqrt(lam_k) (d_k not yet redrawn),
 // step k is d_k' = t_k - g_k u_k, and every lane adds C_p[k][j] (d_k' - d_k)
 // to its u_j: no reduction per step, and at the end d.u = d^T C_p d.
+// C: C_p (K x K, symmetric) in global memory or LDS; Bp, diagp: B_p and the
+// diagonal of C_p; x2: X2_p.
 template <int KPL, int PF>
-__global__ __launch_bounds__(kWave) void dict_chain_kernel(
-    Geom g, const double* __restrict__ Cfull, const double* __restrict__ Bvec,
-    const double* __restrict__ diag, const double* __restrict__ x2p, DevScalars* scal,
-    float* __restrict__ D, double* __restrict__ sumr2_p, uint32_t key0, uint32_t key1,
-    uint32_t stream) {
-  const int p = blockIdx.x, lane = threadIdx.x, K = g.K, P = g.P;
-  const double* C = Cfull + (size_t)p * K * K;
+__device__ __forceinline__ void chain_run(const Geom& g, int p, int lane, const double* C,
+                                          const double* Bp, const double* diagp, double x2,
+                                          DevScalars* scal, float* __restrict__ D,
+                                          double* __restrict__ sumr2_p, uint32_t key0,
+                                          uint32_t key1, uint32_t stream) {
+  const int K = g.K, P = g.P;
   const uint32_t t = (uint32_t)scal->t;
   const double ge = scal->gamma_eps;
   double dreg[KPL], ureg[KPL], greg[KPL], treg[KPL], breg[KPL];
@@ -337,9 +383,9 @@ __global__ __launch_bounds__(kWave) void dict_chain_kernel(
     if (j < K) {
       const Block4 rb = philox10((uint32_t)p, (uint32_t)j, t, stream, key0, key1);
       const double n = sqrt(-2.0 * log(u01d(rb.w0))) * cos(2.0 * M_PI * u01d(rb.w1));
-      const double cjj = diag[(size_t)p * K + j];
+      const double cjj = diagp[j];
       const double lam = (double)P + ge * cjj;
-      breg[m] = Bvec[(size_t)p * K + j];
+      breg[m] = Bp[j];
       dreg[m] = (double)D[(size_t)j * P + p];
       greg[m] = ge / lam;
       treg[m] = fma(greg[m], fma(cjj, dreg[m], breg[m]), n / sqrt(lam));
@@ -424,9 +470,47 @@ __global__ __launch_bounds__(kWave) void dict_chain_kernel(
   quad = wave_sum_d(quad);
   lin = wave_sum_d(lin);
   if (lane == 0) {
-    sumr2_p[p] = x2p[p] - 2.0 * lin + quad;
+    sumr2_p[p] = x2 - 2.0 * lin + quad;
     if (bad) atomicOr(&scal->status, 1);
   }
+}
+
+template <int KPL, int PF>
+__global__ __launch_bounds__(kWave) void dict_chain_kernel(
+    Geom g, const double* __restrict__ Cfull, const double* __restrict__ Bvec,
+    const double* __restrict__ diag, const double* __restrict__ x2p, DevScalars* scal,
+    float* __restrict__ D, double* __restrict__ sumr2_p, uint32_t key0, uint32_t key1,
+    uint32_t stream) {
+  const int p = blockIdx.x, K = g.K;
+  chain_run<KPL, PF>(g, p, threadIdx.x, Cfull + (size_t)p * K * K, Bvec + (size_t)p * K,
+                     diag + (size_t)p * K, x2p[p], scal, D, sumr2_p, key0, key1, stream);
+}
+
+// K <= kChainLdsMaxK: the chain with C_p staged in LDS.  One block per p copies
+// the binary64 C_p (K x K), B_p and the diagonal with all its threads, then
+// wavefront 0 runs the chain reading rows from LDS instead of HBM.
+template <int KPL>
+__global__ __launch_bounds__(1024) void dict_chain_lds_kernel(
+    Geom g, const double* __restrict__ Cfull, const double* __restrict__ Bvec,
+    const double* __restrict__ diag, const double* __restrict__ x2p, DevScalars* scal,
+    float* __restrict__ D, double* __restrict__ sumr2_p, uint32_t key0, uint32_t key1,
+    uint32_t stream) {
+  extern __shared__ double Cs[];                 // K x K
+  __shared__ double s_B[kChainLdsMaxK], s_diag[kChainLdsMaxK];
+  const int p = blockIdx.x, K = g.K, tid = threadIdx.x;
+  const double* C = Cfull + (size_t)p * K * K;
+  const int n2 = K * K / 2;                      // K even here: double2 copies
+  const double2* C2 = reinterpret_cast<const double2*>(C);
+  double2* Cs2 = reinterpret_cast<double2*>(Cs);
+  for (int e = tid; e < n2; e += 1024) Cs2[e] = C2[e];
+  for (int e = 2 * n2 + tid; e < K * K; e += 1024) Cs[e] = C[e];
+  for (int k = tid; k < K; k += 1024) {
+    s_B[k] = Bvec[(size_t)p * K + k];
+    s_diag[k] = diag[(size_t)p * K + k];
+  }
+  __syncthreads();
+  if (tid < kWave)
+    chain_run<KPL, 16>(g, p, tid, Cs, s_B, s_diag, x2p[p], scal, D, sumr2_p, key0, key1, stream);
 }
 
 static DictPlanDev to_dev(const Geom& g, const DictPlan& plan) {
@@ -458,7 +542,7 @@ hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& pl
   hipError_t e = hipFuncSetAttribute((const void*)dict_stats_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  dict_stats_kernel<<<blocks, kDictBlock, lds, st>>>(g, d, n_omega, b.vslot, b.omega_y,
+  dict_stats_kernel<<<blocks, kDictBlock, lds, st>>>(g, d, n_omega, b.vpatch, b.omega_y,
                                                      b.list[cur], b.nact[cur], b.scal, b.dpart,
                                                      b.dx2);
   return hipGetLastError();
@@ -487,6 +571,27 @@ hipError_t launch_dict_chain(const Geom& g, const Buffers& b, const DictPlan& pl
   else if (kpl <= 16) BPFA_CHAIN(16, 2);
   else return hipErrorInvalidValue;
 #undef BPFA_CHAIN
+  return hipGetLastError();
+}
+
+hipError_t launch_dict_chain_lds(const Geom& g, const Buffers& b, uint32_t key0, uint32_t key1,
+                                 uint32_t stream, hipStream_t st) {
+  if (g.K > kChainLdsMaxK) return hipErrorInvalidValue;
+  const size_t lds = (size_t)g.K * g.K * 8;
+  hipError_t e;
+  if (g.K <= kWave) {
+    e = hipFuncSetAttribute((const void*)dict_chain_lds_kernel<1>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    dict_chain_lds_kernel<1><<<g.P, 1024, lds, st>>>(g, b.Cfull, b.Bvec, b.diag, b.x2p, b.scal,
+                                                     b.D, b.sumr2_p, key0, key1, stream);
+  } else {
+    e = hipFuncSetAttribute((const void*)dict_chain_lds_kernel<2>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    dict_chain_lds_kernel<2><<<g.P, 1024, lds, st>>>(g, b.Cfull, b.Bvec, b.diag, b.x2p, b.scal,
+                                                     b.D, b.sumr2_p, key0, key1, stream);
+  }
   return hipGetLastError();
 }
 

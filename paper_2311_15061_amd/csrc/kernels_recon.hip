@@ -18,7 +18,6 @@ constexpr int kRsCap = 16;         // active entries of a patch held in register
 
 // grid (patch blocks, offset runs); LDS K x kRsStride floats
 __global__ __launch_bounds__(256) void recon_sparse_kernel(Geom g, const float* __restrict__ D,
-                                                           const int32_t* __restrict__ inv_perm,
                                                            const int2* __restrict__ list,
                                                            const int32_t* __restrict__ nact,
                                                            float* __restrict__ Y) {
@@ -33,21 +32,13 @@ __global__ __launch_bounds__(256) void recon_sparse_kernel(Geom g, const float* 
   __syncthreads();
   const int i = blockIdx.x * 256 + tid;
   if (i >= g.N) return;
-  const int s = inv_perm[i];
-  const int na = nact[s];
-  const int2* L = list + (size_t)s * K;
-  int ek[kRsCap];
-  float ew[kRsCap];
+  const int na = nact[i];
+  const int2* L = list + (size_t)i * K;
+  // the first kRsCap entries, loaded without conditions so the loads issue back
+  // to back (a clamped index stays inside the list row)
+  int2 raw[kRsCap];
 #pragma unroll
-  for (int a = 0; a < kRsCap; ++a) {
-    ek[a] = 0;
-    ew[a] = 0.f;
-    if (a < na) {
-      const int2 e = L[a];
-      ek[a] = e.x;
-      ew[a] = __int_as_float(e.y);
-    }
-  }
+  for (int a = 0; a < kRsCap; ++a) raw[a] = L[min(a, K - 1)];
   float acc[kRsChunk];
 #pragma unroll
   for (int u = 0; u < kRsChunk; ++u) acc[u] = 0.f;
@@ -64,7 +55,7 @@ __global__ __launch_bounds__(256) void recon_sparse_kernel(Geom g, const float* 
   };
 #pragma unroll
   for (int a = 0; a < kRsCap; ++a)
-    if (a < na) add(ek[a], ew[a]);
+    if (a < na) add(raw[a].x, __int_as_float(raw[a].y));
   for (int a = kRsCap; a < na; ++a) {
     const int2 e = L[a];
     add(e.x, __int_as_float(e.y));
@@ -135,7 +126,7 @@ hipError_t launch_recon(const Geom& g, const Buffers& b, int cur, int Npad, floa
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const dim3 grid((unsigned)((g.N + 255) / 256), (unsigned)((g.P + kRsChunk - 1) / kRsChunk));
-    recon_sparse_kernel<<<grid, 256, lds, st>>>(g, b.D, b.inv_perm, b.list[cur], b.nact[cur], b.Y);
+    recon_sparse_kernel<<<grid, 256, lds, st>>>(g, b.D, b.list[cur], b.nact[cur], b.Y);
   }
   recon_pixel_kernel<<<(g.Mtot + 255) / 256, 256, 0, st>>>(g, b.Y, out);
   return hipGetLastError();
@@ -143,20 +134,20 @@ hipError_t launch_recon(const Geom& g, const Buffers& b, int cur, int Npad, floa
 
 // ---- state conversions ----------------------------------------------------
 
-__global__ __launch_bounds__(256) void lists_to_dense_kernel(Geom g, const uint32_t* __restrict__ perm,
-                                                             const int2* __restrict__ list,
+// per-patch active lists -> dense W, Z (patch order)
+__global__ __launch_bounds__(256) void lists_to_dense_kernel(Geom g, const int2* __restrict__ list,
                                                              const int32_t* __restrict__ nact,
                                                              float* __restrict__ W,
                                                              uint8_t* __restrict__ Z) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= g.N) return;
-  const size_t row = (size_t)perm[s] * g.K;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  const size_t row = (size_t)i * g.K;
   if (W)
     for (int k = 0; k < g.K; ++k) W[row + k] = 0.f;
   if (Z)
     for (int k = 0; k < g.K; ++k) Z[row + k] = 0;
-  const int na = nact[s];
-  const int2* L = list + (size_t)s * g.K;
+  const int na = nact[i];
+  const int2* L = list + row;
   for (int a = 0; a < na; ++a) {
     const int2 e = L[a];
     if (W) W[row + e.x] = __int_as_float(e.y);
@@ -166,24 +157,21 @@ __global__ __launch_bounds__(256) void lists_to_dense_kernel(Geom g, const uint3
 
 hipError_t launch_lists_to_dense(const Geom& g, const Buffers& b, int cur, float* W, uint8_t* Z,
                                  hipStream_t st) {
-  lists_to_dense_kernel<<<(g.N + 255) / 256, 256, 0, st>>>(g, b.perm, b.list[cur], b.nact[cur], W,
-                                                           Z);
+  lists_to_dense_kernel<<<(g.N + 255) / 256, 256, 0, st>>>(g, b.list[cur], b.nact[cur], W, Z);
   return hipGetLastError();
 }
 
-// W, Z dense in patch order -> per-slot active lists.  A row whose Z and W
+// W, Z dense in patch order -> per-patch active lists.  A row whose Z and W
 // disagree (W != 0 where Z = 0) sets *bad.
-__global__ __launch_bounds__(256) void dense_to_lists_kernel(Geom g, const int32_t* __restrict__ inv_perm,
-                                                             const float* __restrict__ W,
+__global__ __launch_bounds__(256) void dense_to_lists_kernel(Geom g, const float* __restrict__ W,
                                                              const uint8_t* __restrict__ Z,
                                                              int2* __restrict__ list,
                                                              int32_t* __restrict__ nact,
                                                              int* __restrict__ bad) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.N) return;
-  const int s = inv_perm[i];
   const size_t row = (size_t)i * g.K;
-  int2* L = list + (size_t)s * g.K;
+  int2* L = list + row;
   int na = 0;
   for (int k = 0; k < g.K; ++k) {
     const float w = W[row + k];
@@ -191,38 +179,13 @@ __global__ __launch_bounds__(256) void dense_to_lists_kernel(Geom g, const int32
     if (z) L[na++] = make_int2(k, __float_as_int(w));
     else if (w != 0.f) atomicOr(bad, 1);
   }
-  nact[s] = na;
+  nact[i] = na;
 }
 
 hipError_t launch_dense_to_lists(const Geom& g, const Buffers& b, int cur, int Npad,
                                  const float* W, const uint8_t* Z, int* bad, hipStream_t st) {
   (void)Npad;
-  dense_to_lists_kernel<<<(g.N + 255) / 256, 256, 0, st>>>(g, b.inv_perm, W, Z, b.list[cur],
-                                                           b.nact[cur], bad);
-  return hipGetLastError();
-}
-
-// codes kept across a new frame: slot rows move from the previous slot order to the new one
-__global__ __launch_bounds__(256) void remap_lists_kernel(Geom g, const int32_t* __restrict__ prev_inv,
-                                                          const int32_t* __restrict__ inv_perm,
-                                                          const int2* __restrict__ list_in,
-                                                          const int32_t* __restrict__ nact_in,
-                                                          int2* __restrict__ list_out,
-                                                          int32_t* __restrict__ nact_out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.N) return;
-  const int so = prev_inv[i], sn = inv_perm[i];
-  const int na = nact_in[so];
-  const int2* src = list_in + (size_t)so * g.K;
-  int2* dst = list_out + (size_t)sn * g.K;
-  for (int a = 0; a < na; ++a) dst[a] = src[a];
-  nact_out[sn] = na;
-}
-
-hipError_t launch_remap_lists(const Geom& g, const Buffers& b, int cur, hipStream_t st) {
-  remap_lists_kernel<<<(g.N + 255) / 256, 256, 0, st>>>(g, b.inv_prev, b.inv_perm, b.list[cur],
-                                                        b.nact[cur], b.list[1 - cur],
-                                                        b.nact[1 - cur]);
+  dense_to_lists_kernel<<<(g.N + 255) / 256, 256, 0, st>>>(g, W, Z, b.list[cur], b.nact[cur], bad);
   return hipGetLastError();
 }
 

@@ -34,7 +34,6 @@ __device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float
 // MT: 32-row tiles of P (P <= 32 MT)
 template <int MT>
 __global__ __launch_bounds__(256) void recon_mfma_kernel(Geom g, const float* __restrict__ D,
-                                                         const int32_t* __restrict__ inv_perm,
                                                          const int2* __restrict__ list,
                                                          const int32_t* __restrict__ nact,
                                                          float* __restrict__ Y) {
@@ -48,22 +47,20 @@ __global__ __launch_bounds__(256) void recon_mfma_kernel(Geom g, const float* __
   int na = 0;
   const int2* L = list;
   if (owner) {
-    const int s = inv_perm[my_i];
-    na = nact[s];
-    L = list + (size_t)s * K;
+    na = nact[my_i];
+    L = list + (size_t)my_i * K;
   }
-  // the patch's first kRmCap entries, loaded once (independent loads)
+  // the patch's first kRmCap entries, loaded without conditions so the loads
+  // issue back to back (a clamped index stays inside the list row)
+  int2 raw[kRmCap];
+#pragma unroll
+  for (int a = 0; a < kRmCap; ++a) raw[a] = L[min(a, K - 1)];
   int ek[kRmCap];
   float ew[kRmCap];
 #pragma unroll
   for (int a = 0; a < kRmCap; ++a) {
-    ek[a] = -1;
-    ew[a] = 0.f;
-    if (a < na) {
-      const int2 e = L[a];
-      ek[a] = e.x;
-      ew[a] = __int_as_float(e.y);
-    }
+    ek[a] = a < na ? raw[a].x : -1;
+    ew[a] = __int_as_float(raw[a].y);
   }
   f32x16 acc[MT];
 #pragma unroll
@@ -153,7 +150,7 @@ static hipError_t launch_mt(const Geom& g, const Buffers& b, int cur, hipStream_
   const hipError_t e = hipFuncSetAttribute((const void*)recon_mfma_kernel<MT>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  recon_mfma_kernel<MT><<<blocks, 256, lds, st>>>(g, b.D, b.inv_perm, b.list[cur], b.nact[cur], b.Y);
+  recon_mfma_kernel<MT><<<blocks, 256, lds, st>>>(g, b.D, b.list[cur], b.nact[cur], b.Y);
   return hipGetLastError();
 }
 

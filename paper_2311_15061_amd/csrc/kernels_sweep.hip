@@ -28,7 +28,9 @@
 //    update on it; the residual takes both updates in one second pass;
 //  * one Philox block per pair: two z uniforms and one Box-Muller pair;
 //  * active atoms travel between iterations as per-patch lists
-//    (atom, weight) in ascending atom order.
+//    (atom, weight) in ascending atom order, stored in patch order (not slot
+//    order) so that the dictionary statistics, which visit patches by
+//    position, read neighbouring rows.
 #include "internal.hpp"
 #include "philox.hpp"
 
@@ -38,6 +40,7 @@ typedef __attribute__((address_space(3))) float lds_f;
 
 constexpr float kLn2 = 0.69314718055994531f;
 constexpr float kLog2e = 1.44269504088896341f;
+constexpr int kPass1Batch = 8;   // list entries loaded together when rebuilding the residual
 
 __device__ __forceinline__ void load_tile(const SweepArgs& a, float* lds, int k0, int k1) {
   const int kt = k1 - k0;
@@ -88,11 +91,14 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int blk, int Jrt
     r[j] = x;
   }
   uint8_t* const cnt_w = cnt_lds + wid * K;
-  const float* __restrict__ Ck = a.Ck;
+  // C_k in LDS: a wave-uniform global load per atom would make every decision
+  // wait (in-order return) for the list prefetch issued before it
+  lds_f* const ck = (lds_f*)(cnt_lds + (kSweepBlock / kWave) * K);
+  for (int k = tid; k < K; k += kSweepBlock) ck[k] = a.Ck[k];
 
   const int ntiles = (K + a.KT - 1) / a.KT;
-  const int na = valid ? a.nact_in[s] : 0;
-  const int2* __restrict__ lin = a.list_in + (size_t)s * K;
+  const int na = valid ? a.nact_in[ip] : 0;
+  const int2* __restrict__ lin = a.list_in + (size_t)ip * K;
 
   // pass 1: residual of the previous sample, r = x - sum_k d_k w_k on Obs(i)
   int ia = 0;
@@ -101,20 +107,26 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int blk, int Jrt
     __syncthreads();
     load_tile(a, lds, k0, k1);
     __syncthreads();
+    // entries in batches whose loads issue together (a clamped index stays in
+    // the row); the entries of the tile form a prefix of each batch
     for (;;) {
-      bool more = ia < na;
-      int2 e = make_int2(0, 0);
-      if (more) e = lin[ia];
-      more = more && e.x < k1;
-      if (!__any(more)) break;
-      if (more) {
-        const float w = __int_as_float(e.y);
-        const int ko = e.x - k0;
+      int2 eb[kPass1Batch];
 #pragma unroll
-        for (int j = 0; j < J; ++j)
-          if (!GUARD || (j & ~3) < Jrt) r[j] = fmaf(-col[j][ko], w, r[j]);
-        ++ia;
+      for (int u = 0; u < kPass1Batch; ++u) eb[u] = lin[min(ia + u, K - 1)];
+      int used = 0;
+#pragma unroll
+      for (int u = 0; u < kPass1Batch; ++u) {
+        if (ia + u < na && eb[u].x < k1) {
+          const float w = __int_as_float(eb[u].y);
+          const int ko = eb[u].x - k0;
+#pragma unroll
+          for (int j = 0; j < J; ++j)
+            if (!GUARD || (j & ~3) < Jrt) r[j] = fmaf(-col[j][ko], w, r[j]);
+          used = u + 1;
+        }
       }
+      ia += used;
+      if (!__any(used == kPass1Batch)) break;
     }
   }
 
@@ -124,7 +136,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int blk, int Jrt
   if (na > 0) e0 = lin[0];
   if (na > 1) e1 = lin[1];
   int nout = 0;
-  int2* __restrict__ lout = a.list_out + (size_t)s * K;
+  int2* __restrict__ lout = a.list_out + (size_t)ip * K;
   float sw2 = 0.f, wmx = 0.f;
 
   // one atom: decision and weight given its delta and rho (own term not yet added)
@@ -144,7 +156,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int blk, int Jrt
     const float mean = ger * rs * rs;
     const float q = 0.5f * ger * mean;
     const float lhs = uz * lam * rs;
-    const float rhs = (1.f - uz) * __builtin_amdgcn_exp2f((Ck[k] + q) * kLog2e);
+    const float rhs = (1.f - uz) * __builtin_amdgcn_exp2f((ck[k] + q) * kLog2e);
     const bool z = valid && (lhs < rhs);
     const float snew = z ? fmaf(n, rs, mean) : 0.f;
     if (z) {
@@ -201,7 +213,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int blk, int Jrt
     }
   }
 
-  if (valid) a.nact_out[s] = nout;
+  if (valid) a.nact_out[ip] = nout;
   float r2 = 0.f;
 #pragma unroll
   for (int j = 0; j < J; ++j) r2 = fmaf(r[j], r[j], r2);
