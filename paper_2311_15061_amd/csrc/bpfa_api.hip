@@ -57,6 +57,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
   int Npad = 0, Jcap = 0, KT = 0, KS = 0, sweep_blocks = 0;
+  long long rec_stride = 0;     // statistics partial record length (int64 entries)
   size_t sweep_lds = 0;
   DictPlan plan;
   // byte offsets
@@ -165,8 +166,8 @@ Layout make_layout(const Geom& g) {
   L.KS = L.KT + 1;
   if (L.KS % 2 == 0) L.KS += 1;
   L.sweep_blocks = L.Npad / kSweepBlock;
-  // tile, then per-wave z counts (bytes), then C_k (floats)
-  L.sweep_lds = (size_t)P1 * L.KS * 4 + align_up((size_t)g.K * (kSweepBlock / kWave), 4) + 4 * (size_t)g.K;
+  // tile, then per-wave z counts (bytes)
+  L.sweep_lds = (size_t)P1 * L.KS * 4 + align_up((size_t)g.K * (kSweepBlock / kWave), 4);
   L.plan = make_dict_plan(g);
   long long rec_stride = 0;
   for (int r = 0; r < L.plan.RG; ++r) {
@@ -174,6 +175,7 @@ Layout make_layout(const Geom& g) {
         (L.plan.ent0[r + 1] - L.plan.ent0[r]) + (L.plan.row0[r + 1] - L.plan.row0[r]);
     rec_stride = std::max(rec_stride, len);
   }
+  L.rec_stride = rec_stride;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -241,6 +243,7 @@ struct bpfa_problem {
   int max_obs = 0, n_omega = 0;
   int dict_groups = 1;          // statistics partials per (p, row group) for this frame
   int dict_cv = 0;              // observed pixels per statistics chunk for this frame
+  int n_cu = 256;               // compute units of the device
   SweepLaunch sweep_ranges{};
   uint32_t key0 = 0, key1 = 0;
   int64_t t_host = 1;
@@ -341,18 +344,30 @@ bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask,
   h->max_obs = s.max_obs;
   h->n_omega = s.n_omega;
   {
-    // chunks of observed pixels per (p, row group): enough for every CU, no larger than
-    // the LDS visit records hold, and a multiple of 8 where possible so that all the
-    // blocks of one chunk (every p) run on one XCD and share its L2 copy of the
-    // chunk's active lists
+    // The statistics blocks run in rounds of (CUs x blocks per CU): pick the
+    // chunk count c >= need that minimises rounds(c) / c, the time per visit,
+    // so that the last round is not a near-empty tail (ties: the smaller c,
+    // fewer partials to reduce).
     const DictPlan& pl = h->L.plan;
-    const int need = (h->n_omega + pl.chunk_visits - 1) / pl.chunk_visits;
-    const int fill = 256 / (g.P * pl.RG);
-    int groups = std::max(1, std::max(need, fill));
-    if (pl.chunks >= 8) groups = (groups + 7) / 8 * 8;
-    h->dict_groups = std::max(1, std::min(pl.chunks, groups));
-    const int per = (h->n_omega + h->dict_groups - 1) / h->dict_groups;
-    h->dict_cv = std::min(pl.chunk_visits, std::max(kDictBlock, (per + kDictBlock - 1) / kDictBlock * kDictBlock));
+    const int need = std::min(pl.chunks, std::max(1, (h->n_omega + pl.chunk_visits - 1) / pl.chunk_visits));
+    auto cv_of = [&](int cc) {
+      const int per = (h->n_omega + cc - 1) / cc;
+      return std::min(pl.chunk_visits, std::max(kDictBlock, (per + kDictBlock - 1) / kDictBlock * kDictBlock));
+    };
+    int best = need;
+    double best_cost = 1e300;
+    for (int cc = need; cc <= pl.chunks; ++cc) {
+      const size_t lds = dict_stats_lds(g.K, h->L.rec_stride, cv_of(cc));
+      const long long slots = (long long)h->n_cu * std::max<long long>(1, (160 * 1024) / (long long)lds);
+      const long long blocks = (long long)g.P * pl.RG * cc;
+      const double cost = (double)((blocks + slots - 1) / slots) / cc;
+      if (cost < best_cost * (1.0 - 1e-9)) {
+        best_cost = cost;
+        best = cc;
+      }
+    }
+    h->dict_groups = best;
+    h->dict_cv = cv_of(best);
   }
   if (h->max_obs > 256)
     return fail(BPFA_ESHAPE, "a patch has %d observed pixels; at most 256 are supported", h->max_obs);
@@ -449,6 +464,12 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
       return bail(fail(BPFA_EDEVICE, "auxiliary stream creation failed"));
   if (hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess)
     return bail(fail(BPFA_EDEVICE, "event creation failed"));
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, params->device) ==
+            hipSuccess && ncu > 0)
+      h->n_cu = ncu;
+  }
   if (workspace) {
     if (ws_bytes < h->L.total)
       return bail(fail(BPFA_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, h->L.total));

@@ -91,10 +91,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int blk, int Jrt
     r[j] = x;
   }
   uint8_t* const cnt_w = cnt_lds + wid * K;
-  // C_k in LDS: a wave-uniform global load per atom would make every decision
-  // wait (in-order return) for the list prefetch issued before it
-  lds_f* const ck = (lds_f*)(cnt_lds + (kSweepBlock / kWave) * K);
-  for (int k = tid; k < K; k += kSweepBlock) ck[k] = a.Ck[k];
+  const float* __restrict__ Ck = a.Ck;
 
   const int ntiles = (K + a.KT - 1) / a.KT;
   const int na = valid ? a.nact_in[ip] : 0;
@@ -156,7 +153,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int blk, int Jrt
     const float mean = ger * rs * rs;
     const float q = 0.5f * ger * mean;
     const float lhs = uz * lam * rs;
-    const float rhs = (1.f - uz) * __builtin_amdgcn_exp2f((ck[k] + q) * kLog2e);
+    const float rhs = (1.f - uz) * __builtin_amdgcn_exp2f((Ck[k] + q) * kLog2e);
     const bool z = valid && (lhs < rhs);
     const float snew = z ? fmaf(n, rs, mean) : 0.f;
     if (z) {
@@ -261,14 +258,19 @@ __device__ __forceinline__ void dispatch_exact(const SweepArgs& a, int blk, int 
   }
 }
 
+// The few blocks of the higher-J ranges run beside the bulk range on the
+// same CUs; their atom loops are the sweep's critical path, so their waves
+// take a higher issue priority (s_setprio) and the bulk fills the gaps.
 template <int JLO, int JHI>
 __global__ __launch_bounds__(kSweepBlock) void sweep_exact_kernel(SweepArgs a, int block0) {
+  if constexpr (JLO > 16) __builtin_amdgcn_s_setprio(JLO > 32 ? 3 : 2);
   const int blk = block0 + (int)blockIdx.x;
   dispatch_exact<JLO, JHI>(a, blk, a.block_J[blk]);
 }
 
 template <int JMAX>
 __global__ __launch_bounds__(kSweepBlock) void sweep_guarded_kernel(SweepArgs a, int block0) {
+  __builtin_amdgcn_s_setprio(3);
   const int blk = block0 + (int)blockIdx.x;
   sweep_block<JMAX, true>(a, blk, a.block_J[blk]);
 }
