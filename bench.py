@@ -176,7 +176,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="stem512")
     ap.add_argument("--iters", type=int, default=None, help="Gibbs iterations per frame")
-    ap.add_argument("--cpu-iters", type=int, default=1, help="oracle iterations timed on the host")
+    ap.add_argument("--cpu-iters", type=int, default=3, help="oracle iterations timed on the host")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-quality", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
