@@ -155,8 +155,12 @@ def residual(X, Mk, D, W):
     return Mk * (X - W @ D)
 
 
-def sweep(params, X, Mk, st, follow_z=None, tie_tol=1e-4):
+def sweep(params, X, Mk, st, follow_z=None, tie_tol=1e-4, patch_ids=None):
     """Step 1: z/s sweep.  Patches are independent; atoms go in ascending order.
+
+    patch_ids: the grid index of every row of X (default 0..N-1); a subset of
+    the patches can be swept on its own because patches are independent given
+    (D, pi, gamma) and each draws from its own Philox counters.
 
     Follow mode (follow_z given): where the drawn z differs from follow_z at a
     point whose log-odds lie within tie_tol * (1 + |ell_k| + |ln(gs/lam)|/2 + q)
@@ -172,7 +176,7 @@ def sweep(params, X, Mk, st, follow_z=None, tie_tol=1e-4):
     Mf = Mk.astype(np.float64)
     gs, ge = st.gamma_s, st.gamma_eps
     rep = SweepReport()
-    ii = np.arange(N, dtype=np.uint64)
+    ii = np.arange(N, dtype=np.uint64) if patch_ids is None else np.asarray(patch_ids, np.uint64)
     for k in range(K):
         dk = st.D[k]
         w_old = W[:, k]
@@ -206,18 +210,22 @@ def sweep(params, X, Mk, st, follow_z=None, tie_tol=1e-4):
     return W, Z, R, rep
 
 
-def dictionary_update(params, Mk, st, W, R):
+def dictionary_update(params, Mk, st, W, R, positions=None, prior_P=None):
     """Step 2: atoms in order; every position p of d_k from its conditional.
 
     R is the residual of the current dictionary and W; both the returned D and
-    the residual reflect the new atoms.
+    the residual reflect the new atoms.  Positions are independent given W, so
+    the columns of a subset of positions can be updated on their own: pass the
+    column subsets of Mk, R and st.D, their position indices and the full
+    patch dimension P (the prior precision).
     """
     K, P = st.D.shape
     D = st.D.copy()
     R = R.copy()
     Mf = Mk.astype(np.float64)
     ge = st.gamma_eps
-    pp = np.arange(P, dtype=np.uint64)
+    pp = np.arange(P, dtype=np.uint64) if positions is None else np.asarray(positions, np.uint64)
+    P = P if prior_P is None else prior_P
     for k in range(K):
         w = W[:, k]
         rows = np.nonzero(w)[0]

@@ -79,6 +79,15 @@ class Stats(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libbpfa.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    # One HIP runtime per process.  PyTorch ships its own HIP runtime with the
+    # same soname (libamdhip64.so.7) but asks for it under another name, so if
+    # this library were loaded first the process would end up with two
+    # runtimes (and torch's stream handles and device state would not be this
+    # library's).  Importing torch first makes the library bind to torch's copy.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, u32, i64, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64,
                               ctypes.c_uint64)

@@ -1,0 +1,142 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark times (one problem handle per frame, LEARN_DICT iterations).
+
+* 512 x 512 frame (10x10 patches, K = 128): two whole iterations against the
+  binary64 oracle in follow mode, every output compared (the oracle takes a
+  few seconds per iteration at this size).
+* 1024 x 1024 frame (K = 256) and the 256 x 256 x 64 video (8x8x4 patches,
+  time stride 2, K = 192): the second iteration is checked on samples the
+  oracle computes one by one -- the sweep of 1500 sampled patches (patches
+  are independent given D, pi and gamma), the dictionary draws of 6 sampled
+  positions (positions are independent given W), the pi draws, and the gamma
+  draws from the whole-frame sums.
+Bars: z equal away from certified near-ties, floating point within 1e-5.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import bpfa as ob  # noqa: E402
+from oracle import patches  # noqa: E402
+from parity_util import FP32_TOL, assert_close  # noqa: E402
+
+from paper_2311_15061_amd import bpfa  # noqa: E402
+import synth  # noqa: E402
+
+
+def _params(wl):
+    return ob.Params(K=wl.K, seed=wl.method_seed, problem_id=0)
+
+
+def _gpu(wl, y, m):
+    print("case: %s shape=%s patch=%s stride=%s K=%d" % (wl.name, wl.shape, wl.patch, wl.stride, wl.K),
+          flush=True)
+    return bpfa.Problem(np.asarray(y, np.float32), m, wl.patch, wl.stride, K=wl.K, seed=wl.method_seed)
+
+
+def _state(gs, rows=None):
+    W, Z = gs["W"], gs["Z"]
+    if rows is not None:
+        W, Z = W[rows], Z[rows]
+    return ob.State(D=gs["D"].astype(np.float64), W=W.astype(np.float64), Z=Z.astype(bool),
+                    ell=gs["logit_pi"], gamma_s=gs["gamma_s"], gamma_eps=gs["gamma_eps"], t=gs["t"])
+
+
+def test_stem512_two_iterations_whole_frame():
+    wl = synth.workload("stem512")
+    y, m, _ = synth.make_frame(wl)
+    prm = _params(wl)
+    X, Mk = patches.extract(y, m, wl.patch, wl.stride)
+    prob = _gpu(wl, y, m)
+    st = ob.init_state(prm, X.shape[0], X.shape[1])
+    for it in range(2):
+        prob.iterate(1, bpfa.LEARN_DICT)
+        gs = prob.get_state()
+        st, rep = ob.iterate(prm, X, Mk, st, follow_z=gs["Z"])
+        print("iteration %d: near-ties %d" % (it, rep.near_ties), flush=True)
+        assert rep.hard_mismatches == 0, rep.hard_sites[:5]
+        assert np.array_equal(gs["Z"].astype(bool), st.Z)
+        assert_close(gs["W"], st.W, FP32_TOL, "W")
+        assert_close(gs["D"], st.D, FP32_TOL, "D")
+        assert abs(gs["gamma_s"] / st.gamma_s - 1) < FP32_TOL
+        assert abs(gs["gamma_eps"] / st.gamma_eps - 1) < FP32_TOL
+        assert np.all(np.abs(gs["logit_pi"] - st.ell) <= FP32_TOL * (1 + np.abs(st.ell)))
+    xh = prob.reconstruct()
+    assert_close(xh, ob.reconstruct(st, wl.shape, wl.patch, wl.stride), FP32_TOL, "reconstruction")
+    prob.close()
+
+
+def _rows(image, mask, wl, rows):
+    """X and Mk of the given patch rows only."""
+    org = patches.patch_origins(wl.shape, wl.patch, wl.stride)[rows]
+    off = patches.patch_offsets(wl.patch)
+    coords = org[:, None, :] + off[None, :, :]
+    idx = np.ravel_multi_index(tuple(coords[..., d] for d in range(len(wl.shape))), wl.shape)
+    return np.asarray(image, np.float64).ravel()[idx], np.asarray(mask).ravel()[idx] != 0
+
+
+def _cols(image, mask, wl, cols):
+    """X and Mk of all patches at the given in-patch positions."""
+    org = patches.patch_origins(wl.shape, wl.patch, wl.stride)
+    off = patches.patch_offsets(wl.patch)[cols]
+    coords = org[:, None, :] + off[None, :, :]
+    idx = np.ravel_multi_index(tuple(coords[..., d] for d in range(len(wl.shape))), wl.shape)
+    return np.asarray(image, np.float64).ravel()[idx], np.asarray(mask).ravel()[idx] != 0
+
+
+def _residual_sum_of_squares(image, mask, wl, W, D, chunk=1 << 16):
+    N = W.shape[0]
+    total, n_obs = 0.0, 0
+    for i0 in range(0, N, chunk):
+        rows = np.arange(i0, min(N, i0 + chunk))
+        X, Mk = _rows(image, mask, wl, rows)
+        R = Mk * (X - W[rows].astype(np.float64) @ D)
+        total += float((R * R).sum())
+        n_obs += int(Mk.sum())
+    return total, n_obs
+
+
+@pytest.mark.parametrize("name", ["stem1024", "video256"])
+def test_full_size_second_iteration_on_samples(name):
+    wl = synth.workload(name)
+    y, m, _ = synth.make_frame(wl)
+    prm = _params(wl)
+    prob = _gpu(wl, y, m)
+    prob.iterate(1, bpfa.LEARN_DICT)
+    g1 = prob.get_state()
+    prob.iterate(1, bpfa.LEARN_DICT)
+    g2 = prob.get_state()
+    prob.close()
+    N, K = g1["W"].shape
+    P = g1["D"].shape[1]
+    rng = np.random.Generator(np.random.PCG64(2024))
+
+    # sweep of sampled patches from the GPU's state after iteration 1
+    S = np.sort(rng.choice(N, size=1500, replace=False))
+    Xs, Ms = _rows(y, m, wl, S)
+    W, Z, _, rep = ob.sweep(prm, Xs, Ms, _state(g1, S), follow_z=g2["Z"][S], patch_ids=S)
+    print("%s: sampled sweep near-ties %d" % (name, rep.near_ties), flush=True)
+    assert rep.hard_mismatches == 0, rep.hard_sites[:5]
+    assert np.array_equal(g2["Z"][S].astype(bool), Z)
+    assert_close(g2["W"][S], W, FP32_TOL, "sampled W")
+
+    # dictionary draws of sampled positions, given the GPU's codes after the sweep
+    cols = np.sort(rng.choice(P, size=6, replace=False))
+    Xc, Mc = _cols(y, m, wl, cols)
+    W2 = g2["W"].astype(np.float64)
+    D1 = g1["D"].astype(np.float64)
+    R = Mc * (Xc - W2 @ D1[:, cols])
+    sub = ob.State(D=D1[:, cols], W=W2, Z=g2["Z"].astype(bool), ell=g1["logit_pi"],
+                   gamma_s=g1["gamma_s"], gamma_eps=g1["gamma_eps"], t=g1["t"])
+    Dc, _ = ob.dictionary_update(prm, Mc, sub, W2, R, positions=cols, prior_P=P)
+    assert_close(g2["D"][:, cols], Dc, FP32_TOL, "sampled D columns")
+
+    # pi and gamma draws from the whole-frame counts and sums
+    ell = ob.pi_update(prm, g2["Z"].astype(bool), g1["t"])
+    assert np.all(np.abs(g2["logit_pi"] - ell) <= FP32_TOL * (1 + np.abs(ell)))
+    gsd = ob.gamma_s_update(prm, g2["Z"].astype(bool), W2, g1["t"])
+    assert abs(g2["gamma_s"] / gsd - 1) < FP32_TOL
+    r2, n_obs = _residual_sum_of_squares(y, m, wl, g2["W"], g2["D"].astype(np.float64))
+    ged = ob.gamma_eps_update(prm, np.ones((1, n_obs), bool), np.sqrt(np.full((1, 1), r2)), g1["t"])
+    assert abs(g2["gamma_eps"] / ged - 1) < FP32_TOL
