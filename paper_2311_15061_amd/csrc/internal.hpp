@@ -11,7 +11,7 @@ constexpr int kMaxDim = 4;
 constexpr int kSweepBlock = 256;      // 4 waves share one LDS copy of the dictionary tile
 constexpr int kSlotAlign = kSweepBlock;
 constexpr int kLdsTileBytes = 64 * 1024;
-constexpr int kDictBlock = 1024;
+constexpr int kDictBlock = 768;
 constexpr int kDictVpt = 8;       // visits per thread of one statistics chunk, held in registers
 constexpr int kChainLdsMaxK = 128;  // largest K whose binary64 C_p (K x K) the chain stages in LDS
 constexpr int kLdsBytes = 160 * 1024 - 1024;   // per block, leaving room for static arrays

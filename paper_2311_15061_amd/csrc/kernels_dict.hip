@@ -232,22 +232,36 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
   __syncthreads();
   const int nvis = s_total;
   // pass 3: outer products into the accumulators
-  for (int vb = 0; vb < nvis; vb += kDictBlock) {
+  // each iteration's list rows are fetched one iteration ahead, so the gather
+  // latency overlaps the previous visits' accumulation
+  auto fetch = [&](int vb, int& pid, int& na, double& y, int& wmax, int2 (&raw)[kStatsCap]) {
     const int vi = vb + tid;
     const bool on = vi < nvis;
-    const int pid = on ? v_pat[vi] : 0;
-    const int na = on ? (int)v_na[vi] : 0;
-    const double y = on ? (double)v_y[vi] : 0.0;
-    const int wmax = __builtin_amdgcn_readfirstlane(wave_max_i(na));
+    pid = on ? v_pat[vi] : 0;
+    na = on ? (int)v_na[vi] : 0;
+    y = on ? (double)v_y[vi] : 0.0;
+    wmax = __builtin_amdgcn_readfirstlane(wave_max_i(na));
     const int2* L = list + (size_t)pid * K;
     // the first entries up to the wave's bound, loads issued together (a
     // clamped index stays inside the patch's list row)
-    int2 raw[kStatsCap];
 #pragma unroll
     for (int a = 0; a < kStatsCap; ++a) {
       raw[a] = make_int2(-1, 0);
       if (a < wmax) raw[a] = L[min(a, K - 1)];
     }
+  };
+  int pid = 0, na = 0, wmax = 0;
+  double y = 0.0;
+  int2 raw[kStatsCap];
+  fetch(0, pid, na, y, wmax, raw);
+  for (int vb = 0; vb < nvis; vb += kDictBlock) {
+    int pid_n = 0, na_n = 0, wmax_n = 0;
+    double y_n = 0.0;
+    int2 raw_n[kStatsCap];
+#pragma unroll
+    for (int a = 0; a < kStatsCap; ++a) raw_n[a] = make_int2(-1, 0);
+    if (vb + kDictBlock < nvis) fetch(vb + kDictBlock, pid_n, na_n, y_n, wmax_n, raw_n);
+    const int2* L = list + (size_t)pid * K;
     int kk[kStatsCap];
     double ww[kStatsCap];
 #pragma unroll
@@ -294,6 +308,12 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
                   to_fixed(ok ? (double)__int_as_float(ea.y) * sc * wb : 0.0));
       }
     }
+    pid = pid_n;
+    na = na_n;
+    y = y_n;
+    wmax = wmax_n;
+#pragma unroll
+    for (int a = 0; a < kStatsCap; ++a) raw[a] = raw_n[a];
   }
   __syncthreads();   // the visit records are rewritten by the next chunk
   }
