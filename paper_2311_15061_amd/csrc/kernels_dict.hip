@@ -33,6 +33,15 @@
 namespace bpfa {
 
 constexpr int kStatsCap = 16;   // active entries of a patch held in registers
+constexpr int kStatsAhead = 1;  // statistics iterations whose list rows are in flight
+
+// a visit of the statistics pass: patch, its n_a and observed value, the
+// wave's bound on n_a, and the first kStatsCap list entries
+struct VisitRow {
+  int pid, na, wmax;
+  double y;
+  int2 raw[kStatsCap];
+};
 
 
 struct DictPlanDev {
@@ -232,35 +241,42 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
   __syncthreads();
   const int nvis = s_total;
   // pass 3: outer products into the accumulators
-  // each iteration's list rows are fetched one iteration ahead, so the gather
-  // latency overlaps the previous visits' accumulation
-  auto fetch = [&](int vb, int& pid, int& na, double& y, int& wmax, int2 (&raw)[kStatsCap]) {
+  // each iteration's list rows are fetched kStatsAhead iterations ahead, so
+  // the gather latency overlaps the accumulation of the visits before it
+  auto fetch = [&](int vb, VisitRow& f) {
     const int vi = vb + tid;
     const bool on = vi < nvis;
-    pid = on ? v_pat[vi] : 0;
-    na = on ? (int)v_na[vi] : 0;
-    y = on ? (double)v_y[vi] : 0.0;
-    wmax = __builtin_amdgcn_readfirstlane(wave_max_i(na));
-    const int2* L = list + (size_t)pid * K;
+    f.pid = on ? v_pat[vi] : 0;
+    f.na = on ? (int)v_na[vi] : 0;
+    f.y = on ? (double)v_y[vi] : 0.0;
+    f.wmax = __builtin_amdgcn_readfirstlane(wave_max_i(f.na));
+    const int2* L = list + (size_t)f.pid * K;
     // the first entries up to the wave's bound, loads issued together (a
     // clamped index stays inside the patch's list row)
 #pragma unroll
     for (int a = 0; a < kStatsCap; ++a) {
-      raw[a] = make_int2(-1, 0);
-      if (a < wmax) raw[a] = L[min(a, K - 1)];
+      f.raw[a] = make_int2(-1, 0);
+      if (a < f.wmax) f.raw[a] = L[min(a, K - 1)];
     }
   };
-  int pid = 0, na = 0, wmax = 0;
-  double y = 0.0;
-  int2 raw[kStatsCap];
-  fetch(0, pid, na, y, wmax, raw);
-  for (int vb = 0; vb < nvis; vb += kDictBlock) {
-    int pid_n = 0, na_n = 0, wmax_n = 0;
-    double y_n = 0.0;
-    int2 raw_n[kStatsCap];
+  auto clear = [&](VisitRow& f) {
+    f.pid = f.na = f.wmax = 0;
+    f.y = 0.0;
 #pragma unroll
-    for (int a = 0; a < kStatsCap; ++a) raw_n[a] = make_int2(-1, 0);
-    if (vb + kDictBlock < nvis) fetch(vb + kDictBlock, pid_n, na_n, y_n, wmax_n, raw_n);
+    for (int a = 0; a < kStatsCap; ++a) f.raw[a] = make_int2(-1, 0);
+  };
+  VisitRow q[kStatsAhead + 1];
+#pragma unroll
+  for (int d = 0; d < kStatsAhead; ++d) {
+    clear(q[d]);
+    if (d * kDictBlock < nvis) fetch(d * kDictBlock, q[d]);
+  }
+  for (int vb = 0; vb < nvis; vb += kDictBlock) {
+    clear(q[kStatsAhead]);
+    if (vb + kStatsAhead * kDictBlock < nvis) fetch(vb + kStatsAhead * kDictBlock, q[kStatsAhead]);
+    const int pid = q[0].pid, na = q[0].na, wmax = q[0].wmax;
+    const double y = q[0].y;
+    const int2 (&raw)[kStatsCap] = q[0].raw;
     const int2* L = list + (size_t)pid * K;
     int kk[kStatsCap];
     double ww[kStatsCap];
@@ -308,12 +324,8 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
                   to_fixed(ok ? (double)__int_as_float(ea.y) * sc * wb : 0.0));
       }
     }
-    pid = pid_n;
-    na = na_n;
-    y = y_n;
-    wmax = wmax_n;
 #pragma unroll
-    for (int a = 0; a < kStatsCap; ++a) raw[a] = raw_n[a];
+    for (int d = 0; d < kStatsAhead; ++d) q[d] = q[d + 1];
   }
   __syncthreads();   // the visit records are rewritten by the next chunk
   }
