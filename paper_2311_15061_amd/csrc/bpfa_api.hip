@@ -653,13 +653,14 @@ bpfa_status bpfa_iterate(bpfa_t h, int32_t n_iters, uint32_t flags) {
       plan.chunk_visits = h->dict_cv;
       plan.xcd = plan.chunks % 8 == 0;
       HIPCHK(launch_dict_stats(g, b, plan, h->cur, h->n_omega, h->st));
-      HIPCHK(launch_dict_reduce(g, b, plan, h->st));
-      if (g.K <= kChainLdsMaxK && g.K % 2 == 0)
-        HIPCHK(launch_dict_chain_lds(g, b, h->key0, h->key1, stream_word(2, h->prm.problem_id),
-                                     h->st));
-      else
+      if (g.K <= kChainLdsMaxK && plan.RG == 1) {
+        HIPCHK(launch_dict_reduce_chain_lds(g, b, plan, h->key0, h->key1,
+                                            stream_word(2, h->prm.problem_id), h->st));
+      } else {
+        HIPCHK(launch_dict_reduce(g, b, plan, h->st));
         HIPCHK(launch_dict_chain(g, b, L.plan, h->key0, h->key1,
                                  stream_word(2, h->prm.problem_id), h->st));
+      }
     }
     if (h->timing && (r = record(h, &ev[2])) != BPFA_OK) return r;
     HIPCHK(launch_scalars(g, b, hyper, learn, h->key0, h->key1, h->prm.problem_id, h->st));

@@ -151,8 +151,9 @@ hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& pl
                              int n_omega, hipStream_t st);
 hipError_t launch_dict_reduce(const Geom& g, const Buffers& b, const DictPlan& plan,
                               hipStream_t st);
-hipError_t launch_dict_chain_lds(const Geom& g, const Buffers& b, uint32_t key0, uint32_t key1,
-                                 uint32_t stream, hipStream_t st);
+hipError_t launch_dict_reduce_chain_lds(const Geom& g, const Buffers& b, const DictPlan& plan,
+                                        uint32_t key0, uint32_t key1, uint32_t stream,
+                                        hipStream_t st);
 hipError_t launch_dict_chain(const Geom& g, const Buffers& b, const DictPlan& plan,
                              uint32_t key0, uint32_t key1, uint32_t stream, hipStream_t st);
 hipError_t launch_scalars(const Geom& g, const Buffers& b, const double* hyper, int learn_dict,

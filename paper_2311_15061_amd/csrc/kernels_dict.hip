@@ -403,7 +403,8 @@ __device__ __forceinline__ void chain_run(const Geom& g, int p, int lane, const 
                                           const double* Bp, const double* diagp, double x2,
                                           DevScalars* scal, float* __restrict__ D,
                                           double* __restrict__ sumr2_p, uint32_t key0,
-                                          uint32_t key1, uint32_t stream) {
+                                          uint32_t key1, uint32_t stream,
+                                          const double* u0 = nullptr) {
   const int K = g.K, P = g.P;
   const uint32_t t = (uint32_t)scal->t;
   const double ge = scal->gamma_eps;
@@ -423,8 +424,15 @@ __device__ __forceinline__ void chain_run(const Geom& g, int p, int lane, const 
       treg[m] = fma(greg[m], fma(cjj, dreg[m], breg[m]), n / sqrt(lam));
     }
   }
-  // u = C d with the old dictionary, rows streamed PF at a time
-  for (int kb = 0; kb < K; kb += PF) {
+  // u = C d with the old dictionary: given (u0), or rows streamed PF at a time
+  if (u0) {
+#pragma unroll
+    for (int m = 0; m < KPL; ++m) {
+      const int j = lane + kWave * m;
+      if (j < K) ureg[m] = u0[j];
+    }
+  }
+  for (int kb = 0; u0 == nullptr && kb < K; kb += PF) {
     double v[PF][KPL];
 #pragma unroll
     for (int u = 0; u < PF; ++u)
@@ -518,31 +526,75 @@ __global__ __launch_bounds__(kWave) void dict_chain_kernel(
                      diag + (size_t)p * K, x2p[p], scal, D, sumr2_p, key0, key1, stream);
 }
 
-// K <= kChainLdsMaxK: the chain with C_p staged in LDS.  One block per p copies
-// the binary64 C_p (K x K), B_p and the diagonal with all its threads, then
-// wavefront 0 runs the chain reading rows from LDS instead of HBM.
+// K <= kChainLdsMaxK (one row group): the chunk partials are summed into the
+// packed upper triangle of C_p (binary64, coalesced), B_p and X2_p.
+__global__ __launch_bounds__(256) void dict_reduce_tri_kernel(
+    Geom g, DictPlanDev pl, const long long* __restrict__ dpart, const double* __restrict__ dx2,
+    const DevScalars* __restrict__ scal, double* __restrict__ Ctri, double* __restrict__ Bvec,
+    double* __restrict__ x2p) {
+  const int K = g.K, E = K * (K + 1) / 2;
+  const int per_p = (E + K + 255) / 256;
+  const int p = blockIdx.x / per_p;
+  const int e = (blockIdx.x % per_p) * 256 + threadIdx.x;
+  const long long* rec = dpart + (size_t)p * pl.chunks * pl.rec_stride;
+  if (e < E + K) {
+    long long sum = 0;
+    for (int c = 0; c < pl.chunks; ++c) sum += rec[(size_t)c * pl.rec_stride + e];
+    if (e < E) Ctri[(size_t)p * E + e] = (double)sum * (1.0 / scal->scale_c);
+    else Bvec[(size_t)p * K + (e - E)] = (double)sum / scal->scale_b;
+  }
+  if (e == 0) {
+    double x2 = 0.0;
+    for (int c = 0; c < pl.chunks; ++c) x2 += dx2[p * pl.chunks + c];
+    x2p[p] = x2;
+  }
+}
+
+// The chain with C_p staged in LDS.  One block per p expands the packed
+// triangle into the symmetric K x K matrix in LDS, forms u = C_p d (old d) with
+// all its threads (partial sums over 1024 / K slices of k, added in a fixed
+// order), then wavefront 0 runs the chain reading rows from LDS.
 template <int KPL>
 __global__ __launch_bounds__(1024) void dict_chain_lds_kernel(
-    Geom g, const double* __restrict__ Cfull, const double* __restrict__ Bvec,
-    const double* __restrict__ diag, const double* __restrict__ x2p, DevScalars* scal,
-    float* __restrict__ D, double* __restrict__ sumr2_p, uint32_t key0, uint32_t key1,
-    uint32_t stream) {
-  extern __shared__ double Cs[];                 // K x K
-  __shared__ double s_B[kChainLdsMaxK], s_diag[kChainLdsMaxK];
-  const int p = blockIdx.x, K = g.K, tid = threadIdx.x;
-  const double* C = Cfull + (size_t)p * K * K;
-  const int n2 = K * K / 2;                      // K even here: double2 copies
-  const double2* C2 = reinterpret_cast<const double2*>(C);
-  double2* Cs2 = reinterpret_cast<double2*>(Cs);
-  for (int e = tid; e < n2; e += 1024) Cs2[e] = C2[e];
-  for (int e = 2 * n2 + tid; e < K * K; e += 1024) Cs[e] = C[e];
+    Geom g, const double* __restrict__ Ctri, const double* __restrict__ Bvec,
+    const double* __restrict__ x2p, DevScalars* scal, float* __restrict__ D,
+    double* __restrict__ sumr2_p, uint32_t key0, uint32_t key1, uint32_t stream) {
+  extern __shared__ double Cs[];                 // K x K, then the u partials
+  __shared__ double s_B[kChainLdsMaxK], s_diag[kChainLdsMaxK], s_d[kChainLdsMaxK],
+      s_u[kChainLdsMaxK];
+  const int p = blockIdx.x, K = g.K, P = g.P, tid = threadIdx.x;
+  const int E = K * (K + 1) / 2;
+  const double* T = Ctri + (size_t)p * E;
+  for (int idx = tid; idx < K * K; idx += 1024) {
+    const int k = idx / K, j = idx - k * K;
+    const int a = min(k, j), b = max(k, j);
+    Cs[idx] = T[tri_off(a, K) + (b - a)];
+  }
   for (int k = tid; k < K; k += 1024) {
     s_B[k] = Bvec[(size_t)p * K + k];
-    s_diag[k] = diag[(size_t)p * K + k];
+    s_d[k] = (double)D[(size_t)k * P + p];
+  }
+  __syncthreads();
+  for (int k = tid; k < K; k += 1024) s_diag[k] = Cs[k * K + k];
+  // u_j = sum_k C[k][j] d_k: slice s of the k range per thread group
+  double* up = Cs + (size_t)K * K;               // [slices][K]
+  const int slices = 1024 / K, per = (K + slices - 1) / slices;
+  if (tid < slices * K) {
+    const int j = tid % K, sl = tid / K;
+    double acc = 0.0;
+    for (int k = sl * per; k < min(K, (sl + 1) * per); ++k) acc = fma(Cs[k * K + j], s_d[k], acc);
+    up[sl * K + j] = acc;
+  }
+  __syncthreads();
+  for (int j = tid; j < K; j += 1024) {
+    double u = 0.0;
+    for (int sl = 0; sl < slices; ++sl) u += up[sl * K + j];
+    s_u[j] = u;
   }
   __syncthreads();
   if (tid < kWave)
-    chain_run<KPL, 16>(g, p, tid, Cs, s_B, s_diag, x2p[p], scal, D, sumr2_p, key0, key1, stream);
+    chain_run<KPL, 16>(g, p, tid, Cs, s_B, s_diag, x2p[p], scal, D, sumr2_p, key0, key1, stream,
+                       s_u);
 }
 
 static DictPlanDev to_dev(const Geom& g, const DictPlan& plan) {
@@ -606,23 +658,33 @@ hipError_t launch_dict_chain(const Geom& g, const Buffers& b, const DictPlan& pl
   return hipGetLastError();
 }
 
-hipError_t launch_dict_chain_lds(const Geom& g, const Buffers& b, uint32_t key0, uint32_t key1,
-                                 uint32_t stream, hipStream_t st) {
-  if (g.K > kChainLdsMaxK) return hipErrorInvalidValue;
-  const size_t lds = (size_t)g.K * g.K * 8;
-  hipError_t e;
+size_t dict_chain_lds_bytes(int K) { return (size_t)K * K * 8 + (size_t)(1024 / K) * K * 8; }
+
+hipError_t launch_dict_reduce_chain_lds(const Geom& g, const Buffers& b, const DictPlan& plan,
+                                        uint32_t key0, uint32_t key1, uint32_t stream,
+                                        hipStream_t st) {
+  if (g.K > kChainLdsMaxK || plan.RG != 1) return hipErrorInvalidValue;
+  const DictPlanDev d = to_dev(g, plan);
+  const int E = g.K * (g.K + 1) / 2;
+  const int per_p = (E + g.K + 255) / 256;
+  // the packed triangles go where the full matrices would (P x K x K >= P x E)
+  dict_reduce_tri_kernel<<<g.P * per_p, 256, 0, st>>>(g, d, b.dpart, b.dx2, b.scal, b.Cfull,
+                                                       b.Bvec, b.x2p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = dict_chain_lds_bytes(g.K);
   if (g.K <= kWave) {
     e = hipFuncSetAttribute((const void*)dict_chain_lds_kernel<1>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    dict_chain_lds_kernel<1><<<g.P, 1024, lds, st>>>(g, b.Cfull, b.Bvec, b.diag, b.x2p, b.scal,
-                                                     b.D, b.sumr2_p, key0, key1, stream);
+    dict_chain_lds_kernel<1><<<g.P, 1024, lds, st>>>(g, b.Cfull, b.Bvec, b.x2p, b.scal, b.D,
+                                                     b.sumr2_p, key0, key1, stream);
   } else {
     e = hipFuncSetAttribute((const void*)dict_chain_lds_kernel<2>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    dict_chain_lds_kernel<2><<<g.P, 1024, lds, st>>>(g, b.Cfull, b.Bvec, b.diag, b.x2p, b.scal,
-                                                     b.D, b.sumr2_p, key0, key1, stream);
+    dict_chain_lds_kernel<2><<<g.P, 1024, lds, st>>>(g, b.Cfull, b.Bvec, b.x2p, b.scal, b.D,
+                                                     b.sumr2_p, key0, key1, stream);
   }
   return hipGetLastError();
 }
