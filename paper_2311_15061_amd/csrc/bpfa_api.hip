@@ -61,7 +61,7 @@ struct Layout {
   size_t sweep_lds = 0;
   DictPlan plan;
   // byte offsets
-  size_t image, mask, poff, pcoord, obs_bits, obs_count, perm, inv_perm, obs_idx, obs_val, block_J, sort_hist, sort_bin,
+  size_t image, mask, poff, pcoord, obs_bits, obs_count, perm, inv_perm, obs_idx, obs_val, block_J, wave_J, sort_hist, sort_bin,
       omega, omega_c, omega_blk, vpatch, omega_y, D, list0, list1, nact0, nact1, Ck, ell, scal, nk, sw_cnt, sw_part, dpart,
       dx2, Cfull, Bvec, diag, x2p, sumr2_p, Y, recon, total;
 };
@@ -166,8 +166,7 @@ Layout make_layout(const Geom& g) {
   L.KS = L.KT + 1;
   if (L.KS % 2 == 0) L.KS += 1;
   L.sweep_blocks = L.Npad / kSweepBlock;
-  // tile, then per-wave z counts (bytes)
-  L.sweep_lds = (size_t)P1 * L.KS * 4 + align_up((size_t)g.K * (kSweepBlock / kWave), 4);
+  L.sweep_lds = sweep_lds_bytes(g.P, L.KS, g.K);
   L.plan = make_dict_plan(g);
   long long rec_stride = 0;
   for (int r = 0; r < L.plan.RG; ++r) {
@@ -194,6 +193,7 @@ Layout make_layout(const Geom& g) {
   L.obs_idx = take(2 * (size_t)L.Jcap * Np);
   L.obs_val = take(4 * (size_t)L.Jcap * Np);
   L.block_J = take(4 * (Np / kSweepBlock));
+  L.wave_J = take(4 * (Np / kWave));
   L.sort_hist = take(4 * (P + 1) * ((N + kSortBlock - 1) / kSortBlock));
   L.sort_bin = take(4 * (P + 1));
   L.omega = take(4 * (size_t)g.Mtot);
@@ -493,6 +493,7 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
   b.obs_idx = (uint16_t*)(w + L.obs_idx);
   b.obs_val = (float*)(w + L.obs_val);
   b.block_J = (int32_t*)(w + L.block_J);
+  b.wave_J = (int32_t*)(w + L.wave_J);
   b.sort_hist = (int32_t*)(w + L.sort_hist);
   b.sort_bin = (int32_t*)(w + L.sort_bin);
   b.omega = (int32_t*)(w + L.omega);
@@ -608,6 +609,7 @@ bpfa_status bpfa_iterate(bpfa_t h, int32_t n_iters, uint32_t flags) {
     a.stream = stream_word(1, h->prm.problem_id);
     a.perm = b.perm;
     a.block_J = b.block_J;
+    a.wave_J = b.wave_J;
     a.obs_idx = b.obs_idx;
     a.obs_val = b.obs_val;
     a.D = b.D;

@@ -61,6 +61,7 @@ struct SweepArgs {
   uint32_t key0, key1, stream;   // Philox key and stream word (tag | problem_id << 8)
   const uint32_t* perm;          // slot -> patch
   const int32_t* block_J;        // per block of slots: largest |Obs|, rounded up to 4 (>= 4)
+  const int32_t* wave_J;         // per wavefront of slots: largest |Obs|, rounded up to 2 (>= 4)
   const uint16_t* obs_idx;       // [J][Npad] pixel offset p in the patch (P = padding)
   const float* obs_val;          // [J][Npad] observed value (0 = padding)
   const float* D;                // K x P
@@ -86,6 +87,7 @@ struct Buffers {
   uint16_t* obs_idx = nullptr;   // [Jcap][Npad]
   float* obs_val = nullptr;      // [Jcap][Npad]
   int32_t* block_J = nullptr;    // Npad / kSweepBlock
+  int32_t* wave_J = nullptr;     // Npad / kWave
   int32_t* sort_hist = nullptr;  // (P + 1) x sort blocks, bin-major
   int32_t* sort_bin = nullptr;   // P + 1: bin totals, then bin offsets
   int32_t* omega = nullptr;      // observed pixel indices, ascending (Mtot capacity)
@@ -128,6 +130,16 @@ struct DictPlan {
 // bytes of LDS of the statistics kernel
 inline size_t dict_stats_lds(int K, long long rec_stride, int chunk_visits) {
   return (size_t)(rec_stride + kWave) * 8 + (size_t)(K + 1) * 4 + (size_t)chunk_visits * 10;
+}
+
+// Sweep LDS: tile (P + 1) x KS floats | [wave][K] z counts (bytes) | per-wave
+// partials (4 waves x (2 doubles + 1 int64 + 1 float)), 8-byte aligned.
+__host__ __device__ inline size_t sweep_red_offset(int P, int KS, int K) {
+  const size_t off = (size_t)(P + 1) * KS * 4 + (size_t)K * (kSweepBlock / kWave);
+  return (off + 7) & ~(size_t)7;
+}
+inline size_t sweep_lds_bytes(int P, int KS, int K) {
+  return sweep_red_offset(P, KS, K) + (size_t)(kSweepBlock / kWave) * (8 + 8 + 8 + 4);
 }
 
 // First block of each sweep launch range (ranges of ascending J).

@@ -63,9 +63,13 @@ template <int J, bool GUARD>
 __device__ __forceinline__ void sweep_block(const SweepArgs& a, int blk, int Jrt) {
   extern __shared__ float lds[];
   uint8_t* cnt_lds = reinterpret_cast<uint8_t*>(lds + (a.P + 1) * a.KS);  // [wave][K] z counts
-  __shared__ double s_w2[kSweepBlock / kWave], s_r2[kSweepBlock / kWave];
-  __shared__ long long s_z[kSweepBlock / kWave];
-  __shared__ float s_wm[kSweepBlock / kWave];
+  // per-wave partials in the dynamic LDS, not in static __shared__ arrays:
+  // wavefronts of one block may run different instantiations of this body
+  char* red = reinterpret_cast<char*>(lds) + sweep_red_offset(a.P, a.KS, a.K);
+  double* s_w2 = reinterpret_cast<double*>(red);
+  double* s_r2 = s_w2 + kSweepBlock / kWave;
+  long long* s_z = reinterpret_cast<long long*>(s_r2 + kSweepBlock / kWave);
+  float* s_wm = reinterpret_cast<float*>(s_z + kSweepBlock / kWave);
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const int s = blk * kSweepBlock + tid;
@@ -249,12 +253,14 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int blk, int Jrt
   }
 }
 
-// per-block dispatch onto bodies compiled for exactly J = JLO, JLO+4, .., JHI
-template <int J, int JHI>
-__device__ __forceinline__ void dispatch_exact(const SweepArgs& a, int blk, int Jb) {
+// per-wavefront dispatch onto bodies compiled for exactly J = JLO, JLO+STEP, .., JHI
+// (the wavefronts of a block may run different bodies: every body passes the
+// same barriers)
+template <int J, int JHI, int STEP>
+__device__ __forceinline__ void dispatch_exact(const SweepArgs& a, int blk, int Jw) {
   if constexpr (J <= JHI) {
-    if (Jb <= J) sweep_block<J, false>(a, blk, J);
-    else dispatch_exact<J + 4, JHI>(a, blk, Jb);
+    if (Jw <= J) sweep_block<J, false>(a, blk, J);
+    else dispatch_exact<J + STEP, JHI, STEP>(a, blk, Jw);
   }
 }
 
@@ -265,7 +271,9 @@ template <int JLO, int JHI>
 __global__ __launch_bounds__(kSweepBlock) void sweep_exact_kernel(SweepArgs a, int block0) {
   if constexpr (JLO > 16) __builtin_amdgcn_s_setprio(JLO > 32 ? 3 : 2);
   const int blk = block0 + (int)blockIdx.x;
-  dispatch_exact<JLO, JHI>(a, blk, a.block_J[blk]);
+  const int Jw = __builtin_amdgcn_readfirstlane(
+      a.wave_J[(blk * kSweepBlock + (int)threadIdx.x) / kWave]);
+  dispatch_exact<JLO, JHI, (JHI <= 16 ? 2 : 4)>(a, blk, Jw);
 }
 
 template <int JMAX>
