@@ -387,11 +387,12 @@ bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask,
   }
   h->sweep_ranges.block0[kSweepRanges] = blk;
   if (blk != nblk) return fail(BPFA_EDEVICE, "slot blocks are not in ascending |Obs| order");
+  // the highest non-empty range goes on the handle's stream, which needs no
+  // event wait, so its few long blocks are dispatched before the bulk fills
+  // the CUs (started after the bulk they were stretched by ~80%)
   int best = 0;
-  for (int rr = 1; rr < kSweepRanges; ++rr)
-    if (h->sweep_ranges.block0[rr + 1] - h->sweep_ranges.block0[rr] >
-        h->sweep_ranges.block0[best + 1] - h->sweep_ranges.block0[best])
-      best = rr;
+  for (int rr = 0; rr < kSweepRanges; ++rr)
+    if (h->sweep_ranges.block0[rr + 1] > h->sweep_ranges.block0[rr]) best = rr;
   h->sweep_ranges.main_range = best;
   if (h->timing) {
     if ((r = record(h, &ev[1])) != BPFA_OK) return r;

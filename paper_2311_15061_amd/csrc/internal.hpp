@@ -145,7 +145,7 @@ inline size_t sweep_lds_bytes(int P, int KS, int K) {
 // First block of each sweep launch range (ranges of ascending J).
 struct SweepLaunch {
   int block0[kSweepRanges + 1];
-  int main_range;   // the range with the most blocks: it runs on the handle's stream
+  int main_range;   // the highest non-empty range: it runs on the handle's stream
 };
 
 // ---- launchers (each checks its own launch and returns the HIP status) ----
