@@ -56,12 +56,13 @@ struct DeviceGuard {
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-  int Npad = 0, Jcap = 0, KT = 0, KS = 0, sweep_blocks = 0;
+  int Npad = 0, Jcap = 0, KT = 0, KS = 0;
+  long long wave_cap = 0;       // capacity of the sweep's wavefront table
   long long rec_stride = 0;     // statistics partial record length (int64 entries)
   size_t sweep_lds = 0;
   DictPlan plan;
   // byte offsets
-  size_t image, mask, poff, pcoord, obs_bits, obs_count, perm, inv_perm, obs_idx, obs_val, block_J, wave_J, sort_hist, sort_bin,
+  size_t image, mask, poff, pcoord, obs_bits, obs_count, perm, inv_perm, obs_idx, obs_val, sweep_waves, sort_hist, sort_bin,
       omega, omega_c, omega_blk, vpatch, omega_y, D, list0, list1, nact0, nact1, Ck, ell, scal, nk, sw_cnt, sw_part, dpart,
       dx2, Cfull, Bvec, diag, x2p, sumr2_p, Y, recon, total;
 };
@@ -165,7 +166,7 @@ Layout make_layout(const Geom& g) {
   }
   L.KS = L.KT + 1;
   if (L.KS % 2 == 0) L.KS += 1;
-  L.sweep_blocks = L.Npad / kSweepBlock;
+  L.wave_cap = sweep_wave_capacity(g.N);
   L.sweep_lds = sweep_lds_bytes(g.P, L.KS, g.K);
   L.plan = make_dict_plan(g);
   long long rec_stride = 0;
@@ -192,8 +193,7 @@ Layout make_layout(const Geom& g) {
   L.inv_perm = take(4 * N);
   L.obs_idx = take(2 * (size_t)L.Jcap * Np);
   L.obs_val = take(4 * (size_t)L.Jcap * Np);
-  L.block_J = take(4 * (Np / kSweepBlock));
-  L.wave_J = take(4 * (Np / kWave));
+  L.sweep_waves = take(16 * (size_t)L.wave_cap);
   L.sort_hist = take(4 * (P + 1) * ((N + kSortBlock - 1) / kSortBlock));
   L.sort_bin = take(4 * (P + 1));
   L.omega = take(4 * (size_t)g.Mtot);
@@ -211,7 +211,7 @@ Layout make_layout(const Geom& g) {
   L.scal = take(sizeof(DevScalars));
   L.nk = take(8 * K);
   L.sw_cnt = take(4 * K);
-  L.sw_part = take(sizeof(SweepPart) * L.sweep_blocks);
+  L.sw_part = take(sizeof(SweepPart) * (size_t)((L.wave_cap + 3) / 4));
   L.dpart = take(8 * (size_t)P * L.plan.RG * L.plan.chunks * rec_stride);
   L.dx2 = take(8 * P * L.plan.chunks);
   L.Cfull = take(8 * P * K * K);
@@ -236,15 +236,15 @@ struct bpfa_problem {
   bool own_ws = false;
   hipStream_t st = nullptr;
   bool own_stream = false;
-  hipStream_t aux[kSweepRanges] = {};   // concurrent sweep ranges
-  hipEvent_t ev_fork = nullptr, ev_join[kSweepRanges] = {};
   int cur = 0;
   int precision = BPFA_FP32;    // contraction precision of the reconstruction
   int max_obs = 0, n_omega = 0;
   int dict_groups = 1;          // statistics partials per (p, row group) for this frame
   int dict_cv = 0;              // observed pixels per statistics chunk for this frame
   int n_cu = 256;               // compute units of the device
-  SweepLaunch sweep_ranges{};
+  int n_waves = 0;              // sweep wavefronts of this frame
+  int jpad = 4;                 // obs rows written per slot for this frame
+  std::vector<int4> wave_host;  // staging of the wavefront table
   uint32_t key0 = 0, key1 = 0;
   int64_t t_host = 1;
   // timing
@@ -339,7 +339,10 @@ bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask,
   }
   HIPCHK(launch_omega(g, h->b, h->st));
   DevScalars s;
+  std::vector<int32_t> bin_start((size_t)g.P + 1);   // first slot of each |Obs| value
   HIPCHK(hipMemcpyAsync(&s, h->b.scal, sizeof s, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipMemcpyAsync(bin_start.data(), h->b.sort_bin, 4 * ((size_t)g.P + 1),
+                        hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
   h->max_obs = s.max_obs;
   h->n_omega = s.n_omega;
@@ -372,28 +375,39 @@ bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask,
   if (h->max_obs > 256)
     return fail(BPFA_ESHAPE, "a patch has %d observed pixels; at most 256 are supported", h->max_obs);
   const int J4 = std::max(4, (h->max_obs + 3) & ~3);
+  h->jpad = J4;
   HIPCHK(launch_slots(g, h->b, h->L.Npad, J4, h->st));
   HIPCHK(launch_visit_table(g, h->b, h->n_omega, h->st));
-  // launch ranges of the sweep: blocks ascend in J
-  const int nblk = h->L.sweep_blocks;
-  std::vector<int32_t> bj(nblk);
-  HIPCHK(hipMemcpyAsync(bj.data(), h->b.block_J, 4 * (size_t)nblk, hipMemcpyDeviceToHost, h->st));
-  HIPCHK(hipStreamSynchronize(h->st));
-  static const int bound[kSweepRanges] = {16, 32, 64, 128, 256};
-  int blk = 0;
-  for (int rr = 0; rr < kSweepRanges; ++rr) {
-    h->sweep_ranges.block0[rr] = blk;
-    while (blk < nblk && bj[blk] <= bound[rr]) ++blk;
+  // wavefront table of the sweep: slots ascend in |Obs|; a wavefront takes
+  // consecutive slots of one lane count (sweep_lanes), 64 / lanes of them,
+  // and its register count J covers its last (largest) slot
+  {
+    auto count_of = [&](int slot) {   // |Obs| of a slot: the bin whose range holds it
+      return (int)(std::upper_bound(bin_start.begin(), bin_start.end(), slot) - bin_start.begin()) - 1;
+    };
+    auto first_above = [&](int c) {   // first slot with |Obs| > c
+      return c >= g.P ? g.N : bin_start[(size_t)c + 1];
+    };
+    h->wave_host.clear();
+    int slot = 0;
+    while (slot < g.N) {
+      const int lpp = sweep_lanes(count_of(slot));
+      const int climit = lpp == 1 ? 16 : lpp == 2 ? 32 : lpp == 4 ? 64 : lpp == 8 ? 128 : 256;
+      const int end = std::min({g.N, slot + kWave / lpp, first_above(climit)});
+      const int clast = count_of(end - 1);
+      int J = 16;
+      if (lpp == 1) J = std::max(4, (clast + 1) & ~1);
+      else if (lpp == 2 && clast <= 24) J = 12;
+      h->wave_host.push_back(make_int4(slot, end - slot, lpp, J));
+      slot = end;
+    }
+    if ((long long)h->wave_host.size() > h->L.wave_cap)
+      return fail(BPFA_EDEVICE, "sweep wavefront table overflow (%zu > %lld)", h->wave_host.size(),
+                  h->L.wave_cap);
+    h->n_waves = (int)h->wave_host.size();
+    HIPCHK(hipMemcpyAsync(h->b.sweep_waves, h->wave_host.data(), 16 * h->wave_host.size(),
+                          hipMemcpyHostToDevice, h->st));
   }
-  h->sweep_ranges.block0[kSweepRanges] = blk;
-  if (blk != nblk) return fail(BPFA_EDEVICE, "slot blocks are not in ascending |Obs| order");
-  // the highest non-empty range goes on the handle's stream, which needs no
-  // event wait, so its few long blocks are dispatched before the bulk fills
-  // the CUs (started after the bulk they were stretched by ~80%)
-  int best = 0;
-  for (int rr = 0; rr < kSweepRanges; ++rr)
-    if (h->sweep_ranges.block0[rr + 1] > h->sweep_ranges.block0[rr]) best = rr;
-  h->sweep_ranges.main_range = best;
   if (h->timing) {
     if ((r = record(h, &ev[1])) != BPFA_OK) return r;
     h->index_events.push_back(ev);
@@ -459,12 +473,6 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
       return bail(fail(BPFA_EDEVICE, "hipStreamCreate failed"));
     h->own_stream = true;
   }
-  for (int r = 0; r < kSweepRanges; ++r)
-    if (hipStreamCreateWithFlags(&h->aux[r], hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&h->ev_join[r], hipEventDisableTiming) != hipSuccess)
-      return bail(fail(BPFA_EDEVICE, "auxiliary stream creation failed"));
-  if (hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess)
-    return bail(fail(BPFA_EDEVICE, "event creation failed"));
   {
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, params->device) ==
@@ -493,8 +501,7 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
   b.inv_perm = (int32_t*)(w + L.inv_perm);
   b.obs_idx = (uint16_t*)(w + L.obs_idx);
   b.obs_val = (float*)(w + L.obs_val);
-  b.block_J = (int32_t*)(w + L.block_J);
-  b.wave_J = (int32_t*)(w + L.wave_J);
+  b.sweep_waves = (int4*)(w + L.sweep_waves);
   b.sort_hist = (int32_t*)(w + L.sort_hist);
   b.sort_bin = (int32_t*)(w + L.sort_bin);
   b.omega = (int32_t*)(w + L.omega);
@@ -609,8 +616,7 @@ bpfa_status bpfa_iterate(bpfa_t h, int32_t n_iters, uint32_t flags) {
     a.key1 = h->key1;
     a.stream = stream_word(1, h->prm.problem_id);
     a.perm = b.perm;
-    a.block_J = b.block_J;
-    a.wave_J = b.wave_J;
+    a.Jpad = h->jpad;
     a.obs_idx = b.obs_idx;
     a.obs_val = b.obs_val;
     a.D = b.D;
@@ -625,30 +631,9 @@ bpfa_status bpfa_iterate(bpfa_t h, int32_t n_iters, uint32_t flags) {
     std::array<hipEvent_t, 4> ev{};
     bpfa_status r;
     if (h->timing && (r = record(h, &ev[0])) != BPFA_OK) return r;
-    {
-      const SweepLaunch& sl = h->sweep_ranges;
-      hipStream_t streams[kSweepRanges];
-      bool side = false;
-      for (int rr = 0; rr < kSweepRanges; ++rr) {
-        streams[rr] = rr == sl.main_range ? h->st : h->aux[rr];
-        side = side || (rr != sl.main_range && sl.block0[rr + 1] > sl.block0[rr]);
-      }
-      if (side) {
-        HIPCHK(hipEventRecord(h->ev_fork, h->st));
-        for (int rr = 0; rr < kSweepRanges; ++rr)
-          if (rr != sl.main_range && sl.block0[rr + 1] > sl.block0[rr])
-            HIPCHK(hipStreamWaitEvent(h->aux[rr], h->ev_fork, 0));
-      }
-      HIPCHK(launch_sweep(sl, L.sweep_lds, a, streams));
-      if (side)
-        for (int rr = 0; rr < kSweepRanges; ++rr)
-          if (rr != sl.main_range && sl.block0[rr + 1] > sl.block0[rr]) {
-            HIPCHK(hipEventRecord(h->ev_join[rr], h->aux[rr]));
-            HIPCHK(hipStreamWaitEvent(h->st, h->ev_join[rr], 0));
-          }
-    }
+    HIPCHK(launch_sweep(b.sweep_waves, h->n_waves, L.sweep_lds, a, h->st));
     if (h->timing && (r = record(h, &ev[1])) != BPFA_OK) return r;
-    HIPCHK(launch_sweep_reduce(g, b, L.sweep_blocks, h->st));
+    HIPCHK(launch_sweep_reduce(g, b, (h->n_waves + 3) / 4, h->st));
     h->cur = 1 - h->cur;
     if (learn) {
       DictPlan plan = L.plan;
@@ -910,14 +895,6 @@ void bpfa_destroy(bpfa_t h) {
   (void)collect_timing(h);
   if (h->own_ws && h->ws) (void)hipFree(h->ws);
   if (h->own_stream && h->st) (void)hipStreamDestroy(h->st);
-  for (int r = 0; r < kSweepRanges; ++r) {
-    if (h->aux[r]) {
-      (void)hipStreamSynchronize(h->aux[r]);
-      (void)hipStreamDestroy(h->aux[r]);
-    }
-    if (h->ev_join[r]) (void)hipEventDestroy(h->ev_join[r]);
-  }
-  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   delete h;
 }
 

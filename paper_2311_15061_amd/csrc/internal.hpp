@@ -17,7 +17,6 @@ constexpr int kChainLdsMaxK = 128;  // largest K whose binary64 C_p (K x K) the 
 constexpr int kLdsBytes = 160 * 1024 - 1024;   // per block, leaving room for static arrays
 constexpr int kDictLdsEntries = 16384; // int64 accumulators per statistics block (128 KiB)
 constexpr int kSortBlock = 256;        // patches per block of the slot sort
-constexpr int kSweepRanges = 5;        // J <= 16, <= 32, <= 64 (exact bodies), <= 128, <= 256
 
 // Patch geometry (all sizes fit 32 bits; checked at create).
 struct Geom {
@@ -60,8 +59,7 @@ struct SweepArgs {
   int N, Npad, P, K, KT, KS;     // KT atoms per LDS tile, KS = KT + 1 (odd column stride)
   uint32_t key0, key1, stream;   // Philox key and stream word (tag | problem_id << 8)
   const uint32_t* perm;          // slot -> patch
-  const int32_t* block_J;        // per block of slots: largest |Obs|, rounded up to 4 (>= 4)
-  const int32_t* wave_J;         // per wavefront of slots: largest |Obs|, rounded up to 2 (>= 4)
+  int Jpad;                      // obs rows written per slot (padding rows hold P / 0)
   const uint16_t* obs_idx;       // [J][Npad] pixel offset p in the patch (P = padding)
   const float* obs_val;          // [J][Npad] observed value (0 = padding)
   const float* D;                // K x P
@@ -86,8 +84,7 @@ struct Buffers {
   int32_t* inv_perm = nullptr;   // N patch -> slot
   uint16_t* obs_idx = nullptr;   // [Jcap][Npad]
   float* obs_val = nullptr;      // [Jcap][Npad]
-  int32_t* block_J = nullptr;    // Npad / kSweepBlock
-  int32_t* wave_J = nullptr;     // Npad / kWave
+  int4* sweep_waves = nullptr;   // per-frame wavefront table (first slot, slots, lanes per slot, J)
   int32_t* sort_hist = nullptr;  // (P + 1) x sort blocks, bin-major
   int32_t* sort_bin = nullptr;   // P + 1: bin totals, then bin offsets
   int32_t* omega = nullptr;      // observed pixel indices, ascending (Mtot capacity)
@@ -142,11 +139,6 @@ inline size_t sweep_lds_bytes(int P, int KS, int K) {
   return sweep_red_offset(P, KS, K) + (size_t)(kSweepBlock / kWave) * (8 + 8 + 8 + 4);
 }
 
-// First block of each sweep launch range (ranges of ascending J).
-struct SweepLaunch {
-  int block0[kSweepRanges + 1];
-  int main_range;   // the highest non-empty range: it runs on the handle's stream
-};
 
 // ---- launchers (each checks its own launch and returns the HIP status) ----
 hipError_t launch_index(const Geom& g, const Buffers& b, int Npad, hipStream_t st);
@@ -155,8 +147,12 @@ hipError_t launch_omega(const Geom& g, const Buffers& b, hipStream_t st);
 hipError_t launch_visit_table(const Geom& g, const Buffers& b, int n_omega, hipStream_t st);
 hipError_t launch_init_dict(const Geom& g, const Buffers& b, uint32_t key0, uint32_t key1,
                             uint32_t stream, hipStream_t st);
-hipError_t launch_sweep(const SweepLaunch& sl, size_t lds, const SweepArgs& a,
-                        const hipStream_t* streams);
+hipError_t launch_sweep(const int4* waves, int nwaves, size_t lds, const SweepArgs& a,
+                        hipStream_t st);
+// lanes per patch of the sweep for a patch with c observed pixels
+inline int sweep_lanes(int c) { return c <= 16 ? 1 : c <= 32 ? 2 : c <= 64 ? 4 : c <= 128 ? 8 : 16; }
+// wavefronts the sweep table can need for N slots (slots per wave >= 4)
+inline long long sweep_wave_capacity(long long N) { return (N + 3) / 4 + 16; }
 hipError_t launch_sort(const Geom& g, const Buffers& b, int Npad, hipStream_t st);
 hipError_t launch_sweep_reduce(const Geom& g, const Buffers& b, int blocks, hipStream_t st);
 hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& plan, int cur,

@@ -11,8 +11,7 @@
 // slots_kernel   one thread per slot: the observed offsets p (ascending) and
 //                values of the slot's patch, stored [j][slot] so that a wave
 //                reads them coalesced; padding entries point at offset P,
-//                which the sweep keeps at zero.  Per block of slots the
-//                largest |Obs| (rounded up to 4) is the sweep's register count.
+//                which the sweep keeps at zero.
 // omega_*        ordered compaction of the observed pixels (the dictionary
 //                statistics visit patches through them).
 #include "internal.hpp"
@@ -95,8 +94,7 @@ __global__ __launch_bounds__(256) void slots_kernel(Geom g, const float* __restr
                                                     const uint32_t* __restrict__ perm,
                                                     uint16_t* __restrict__ obs_idx,
                                                     float* __restrict__ obs_val,
-                                                    int32_t* __restrict__ block_J,
-                                                    int32_t* __restrict__ wave_J, int Npad,
+                                                    int Npad,
                                                     int Jcap4) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;   // grid covers Npad exactly
   const bool valid = s < g.N;
@@ -122,13 +120,6 @@ __global__ __launch_bounds__(256) void slots_kernel(Geom g, const float* __restr
     obs_idx[(size_t)j * Npad + s] = (uint16_t)g.P;
     obs_val[(size_t)j * Npad + s] = 0.f;
   }
-  // slots ascend in |Obs|: the block's last valid slot has its largest count
-  const int blk = s / kSweepBlock;
-  const int last = min(g.N, (blk + 1) * kSweepBlock) - 1;
-  if (s == last || (s % kSweepBlock == 0 && last < s)) block_J[blk] = max(4, (cnt + 3) & ~3);
-  const int wv = s / kWave;
-  const int wlast = min(g.N, (wv + 1) * kWave) - 1;
-  if (s == wlast || (s % kWave == 0 && wlast < s)) wave_J[wv] = max(4, (cnt + 1) & ~1);
 }
 
 // exclusive scan in place of data[0 .. n) by one block of 1024 threads; returns the total
@@ -312,7 +303,7 @@ hipError_t launch_omega(const Geom& g, const Buffers& b, hipStream_t st) {
 
 hipError_t launch_slots(const Geom& g, const Buffers& b, int Npad, int Jcap4, hipStream_t st) {
   slots_kernel<<<Npad / 256, 256, 0, st>>>(g, b.image, b.poff, b.obs_bits, b.obs_count, b.perm,
-                                           b.obs_idx, b.obs_val, b.block_J, b.wave_J, Npad, Jcap4);
+                                           b.obs_idx, b.obs_val, Npad, Jcap4);
   return hipGetLastError();
 }
 

@@ -11,13 +11,22 @@
 // C_k = ell_k + ln(gamma_s) / 2 and q = (gamma_eps rho)^2 / (2 lam).
 //
 // Mapping onto gfx950:
-//  * one lane per patch, 64 patches per wavefront, 4 wavefronts per block
-//    sharing one LDS copy of the dictionary tile (three blocks fit a CU's
-//    LDS for 10 x 10 patches and 128 atoms);
-//  * slots are sorted by |Obs(i)| once per frame, so every block has one
-//    register count J (|Obs| of its last slot, rounded up to 4) and runs a
-//    body compiled for exactly that J: the residual on the observed pixels
-//    lives in J VGPRs for the whole atom loop, with no per-element guards;
+//  * slots (patches) are sorted by |Obs(i)| once per frame and cut into
+//    wavefronts by a per-frame table: a patch with |Obs| <= 16 gets one lane,
+//    larger ones 2, 4, 8 or 16 lanes (<= 32, 64, 128, 256 observed pixels),
+//    each lane holding at most 16 of the patch's observed pixels; every
+//    wavefront has one lane count and one register count J, and runs a body
+//    compiled for exactly that J: the residual on the observed pixels lives
+//    in J VGPRs for the whole atom loop, with no per-element guards.  One
+//    kernel covers every |Obs|, so the long patches run beside the bulk in
+//    the same launch instead of trailing it;
+//  * the lanes of one patch form an aligned group; their partial dot
+//    products are summed by a butterfly, so every lane of the group holds
+//    the same sums (addition is commutative at every level), draws the same
+//    numbers from the patch's Philox counters and takes the same decisions;
+//    only the group's first lane writes the patch's outputs;
+//  * 4 wavefronts per block share one LDS copy of the dictionary tile
+//    (three blocks fit a CU's LDS for 10 x 10 patches and 128 atoms);
 //  * the tile is pixel-major with an odd atom stride (d_kp at p * KS + k):
 //    a lane's gathers for its observed pixels hit different banks, and the
 //    values of atoms k and k+1 at one pixel are adjacent, so one ds_read2
@@ -58,13 +67,24 @@ __device__ __forceinline__ void load_tile(const SweepArgs& a, float* lds, int k0
   for (int kk = threadIdx.x; kk < a.KS; kk += kSweepBlock) lds[a.P * a.KS + kk] = 0.f;
 }
 
-// J registers of residual; GUARD: J is an upper bound and Jrt the real count
-template <int J, bool GUARD>
-__device__ __forceinline__ void sweep_block(const SweepArgs& a, int blk, int Jrt) {
+// sum over the LPP lanes of an aligned group, the same value in every lane
+template <int LPP>
+__device__ __forceinline__ float group_sum(float v) {
+  if constexpr (LPP >= 2) v += __shfl_xor(v, 1);
+  if constexpr (LPP >= 4) v += __shfl_xor(v, 2);
+  if constexpr (LPP >= 8) v += __shfl_xor(v, 4);
+  if constexpr (LPP >= 16) v += __shfl_xor(v, 8);
+  return v;
+}
+
+// One wavefront: slots wt.x .. wt.x + wt.y - 1, LPP lanes per slot, J
+// observed pixels per lane (lane `sub` of a group holds rows sub*J .. sub*J+J-1)
+template <int J, int LPP>
+__device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslots, int slot0) {
   extern __shared__ float lds[];
   uint8_t* cnt_lds = reinterpret_cast<uint8_t*>(lds + (a.P + 1) * a.KS);  // [wave][K] z counts
   // per-wave partials in the dynamic LDS, not in static __shared__ arrays:
-  // wavefronts of one block may run different instantiations of this body
+  // wavefronts of one block run different instantiations of this body
   char* red = reinterpret_cast<char*>(lds) + sweep_red_offset(a.P, a.KS, a.K);
   double* s_w2 = reinterpret_cast<double*>(red);
   double* s_r2 = s_w2 + kSweepBlock / kWave;
@@ -72,27 +92,30 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int blk, int Jrt
   float* s_wm = reinterpret_cast<float*>(s_z + kSweepBlock / kWave);
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-  const int s = blk * kSweepBlock + tid;
-  const bool valid = s < a.N;
+  const int grp = lane / LPP, sub = lane - grp * LPP;
+  const int s = slot0 + grp;
+  const bool valid = grp < nslots;
+  const bool lead = valid && sub == 0;
   const float gs = (float)a.scal->gamma_s;
   const float ge = (float)a.scal->gamma_eps;
   const uint32_t t = (uint32_t)a.scal->t;
-  const uint32_t ip = a.perm[s];
+  const uint32_t ip = valid ? a.perm[s] : 0u;
   const int K = a.K;
 
   lds_f* const L = (lds_f*)lds;
   lds_f* col[J];     // column p_j of the tile (p_j = P: the zero row)
-  float r[J];        // residual on observed pixel j
+  float r[J];        // residual on this lane's observed pixels
 #pragma unroll
-  for (int j = 0; j < J; ++j) {
+  for (int jj = 0; jj < J; ++jj) {
+    const int j = sub * J + jj;
     int p = a.P;
     float x = 0.f;
-    if (!GUARD || j < Jrt) {
+    if (valid && j < a.Jpad) {
       p = a.obs_idx[(size_t)j * a.Npad + s];
       x = a.obs_val[(size_t)j * a.Npad + s];
     }
-    col[j] = L + p * a.KS;
-    r[j] = x;
+    col[jj] = L + p * a.KS;
+    r[jj] = x;
   }
   uint8_t* const cnt_w = cnt_lds + wid * K;
   const float* __restrict__ Ck = a.Ck;
@@ -121,8 +144,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int blk, int Jrt
           const float w = __int_as_float(eb[u].y);
           const int ko = eb[u].x - k0;
 #pragma unroll
-          for (int j = 0; j < J; ++j)
-            if (!GUARD || (j & ~3) < Jrt) r[j] = fmaf(-col[j][ko], w, r[j]);
+          for (int j = 0; j < J; ++j) r[j] = fmaf(-col[j][ko], w, r[j]);
           used = u + 1;
         }
       }
@@ -160,12 +182,12 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int blk, int Jrt
     const float rhs = (1.f - uz) * __builtin_amdgcn_exp2f((Ck[k] + q) * kLog2e);
     const bool z = valid && (lhs < rhs);
     const float snew = z ? fmaf(n, rs, mean) : 0.f;
-    if (z) {
+    if (z && lead) {
       lout[nout++] = make_int2(k, __float_as_int(snew));
       sw2 = fmaf(snew, snew, sw2);
       wmx = fmaxf(wmx, fabsf(snew));
     }
-    const int nz = (int)__popcll(__ballot(z));
+    const int nz = (int)__popcll(__ballot(z && lead));
     if (lane == 0) cnt_w[k] = (uint8_t)nz;   // every (wave, atom) is visited exactly once
     return snew - wold;
   };
@@ -183,15 +205,18 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int blk, int Jrt
       float dl0 = 0.f, dl1 = 0.f, rh0 = 0.f, rh1 = 0.f, g01 = 0.f;
 #pragma unroll
       for (int j = 0; j < J; ++j) {
-        if (!GUARD || (j & ~3) < Jrt) {
-          const float x0 = col[j][ko], x1 = col[j][ko + 1];
-          dl0 = fmaf(x0, x0, dl0);
-          dl1 = fmaf(x1, x1, dl1);
-          rh0 = fmaf(x0, r[j], rh0);
-          rh1 = fmaf(x1, r[j], rh1);
-          g01 = fmaf(x0, x1, g01);
-        }
+        const float x0 = col[j][ko], x1 = col[j][ko + 1];
+        dl0 = fmaf(x0, x0, dl0);
+        dl1 = fmaf(x1, x1, dl1);
+        rh0 = fmaf(x0, r[j], rh0);
+        rh1 = fmaf(x1, r[j], rh1);
+        g01 = fmaf(x0, x1, g01);
       }
+      dl0 = group_sum<LPP>(dl0);
+      dl1 = group_sum<LPP>(dl1);
+      rh0 = group_sum<LPP>(rh0);
+      rh1 = group_sum<LPP>(rh1);
+      g01 = group_sum<LPP>(g01);
       const float u2 = u01f(rb.w2);
       const float rad = __builtin_amdgcn_sqrtf(-2.f * kLn2 * __builtin_amdgcn_logf(u2));
       const float ang = u01f(rb.w3);                 // revolutions
@@ -205,23 +230,22 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int blk, int Jrt
       if (dw0 != 0.f || dw1 != 0.f) {
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-          if (!GUARD || (j & ~3) < Jrt) {
-            const float x0 = col[j][ko], x1 = col[j][ko + 1];
-            r[j] = fmaf(-x1, dw1, fmaf(-x0, dw0, r[j]));
-          }
+          const float x0 = col[j][ko], x1 = col[j][ko + 1];
+          r[j] = fmaf(-x1, dw1, fmaf(-x0, dw0, r[j]));
         }
       }
     }
   }
 
-  if (valid) a.nact_out[ip] = nout;
+  if (lead) a.nact_out[ip] = nout;
   float r2 = 0.f;
 #pragma unroll
   for (int j = 0; j < J; ++j) r2 = fmaf(r[j], r[j], r2);
 
-  // deterministic block partials: fixed butterfly, then waves in order
+  // deterministic block partials: fixed butterfly, then waves in order (sw2,
+  // wmx and the z count come from the lead lanes only; r2 from every lane)
   double dw2 = (double)sw2, dr2 = (double)r2;
-  long long dz = nout;
+  long long dz = lead ? nout : 0;
   float dm = wmx;
   for (int o = kWave / 2; o > 0; o >>= 1) {
     dw2 += __shfl_xor(dw2, o);
@@ -253,68 +277,51 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int blk, int Jrt
   }
 }
 
-// per-wavefront dispatch onto bodies compiled for exactly J = JLO, JLO+STEP, .., JHI
-// (the wavefronts of a block may run different bodies: every body passes the
-// same barriers)
-template <int J, int JHI, int STEP>
-__device__ __forceinline__ void dispatch_exact(const SweepArgs& a, int blk, int Jw) {
-  if constexpr (J <= JHI) {
-    if (Jw <= J) sweep_block<J, false>(a, blk, J);
-    else dispatch_exact<J + STEP, JHI, STEP>(a, blk, Jw);
+// One kernel for every wavefront of the frame: wavefront w of the grid reads
+// its (first slot, slots, lanes per slot, J) from the table and runs the body
+// compiled for that pair; wavefronts past the table run with no valid lane
+// (every body passes the same barriers).
+__global__ __launch_bounds__(kSweepBlock) void sweep_kernel(SweepArgs a, const int4* __restrict__ waves,
+                                                            int nwaves) {
+  const int blk = blockIdx.x;
+  const int w = blk * (kSweepBlock / kWave) + (int)(threadIdx.x / kWave);
+  int4 wt = make_int4(0, 0, 1, 4);
+  if (w < nwaves) wt = waves[w];
+  const int slot0 = __builtin_amdgcn_readfirstlane(wt.x);
+  const int ns = __builtin_amdgcn_readfirstlane(wt.y);
+  const int lpp = __builtin_amdgcn_readfirstlane(wt.z);
+  const int J = __builtin_amdgcn_readfirstlane(wt.w);
+  switch (lpp) {
+    case 1:
+      switch (J) {
+        case 4: sweep_wave<4, 1>(a, blk, ns, slot0); break;
+        case 6: sweep_wave<6, 1>(a, blk, ns, slot0); break;
+        case 8: sweep_wave<8, 1>(a, blk, ns, slot0); break;
+        case 10: sweep_wave<10, 1>(a, blk, ns, slot0); break;
+        case 12: sweep_wave<12, 1>(a, blk, ns, slot0); break;
+        case 14: sweep_wave<14, 1>(a, blk, ns, slot0); break;
+        default: sweep_wave<16, 1>(a, blk, ns, slot0); break;
+      }
+      break;
+    case 2:
+      if (J <= 12) sweep_wave<12, 2>(a, blk, ns, slot0);
+      else sweep_wave<16, 2>(a, blk, ns, slot0);
+      break;
+    case 4: sweep_wave<16, 4>(a, blk, ns, slot0); break;
+    case 8: sweep_wave<16, 8>(a, blk, ns, slot0); break;
+    default: sweep_wave<16, 16>(a, blk, ns, slot0); break;
   }
 }
 
-// The few blocks of the higher-J ranges run beside the bulk range on the
-// same CUs; their atom loops are the sweep's critical path, so their waves
-// take a higher issue priority (s_setprio) and the bulk fills the gaps.
-template <int JLO, int JHI>
-__global__ __launch_bounds__(kSweepBlock) void sweep_exact_kernel(SweepArgs a, int block0) {
-  if constexpr (JLO > 16) __builtin_amdgcn_s_setprio(JLO > 32 ? 3 : 2);
-  const int blk = block0 + (int)blockIdx.x;
-  const int Jw = __builtin_amdgcn_readfirstlane(
-      a.wave_J[(blk * kSweepBlock + (int)threadIdx.x) / kWave]);
-  dispatch_exact<JLO, JHI, (JHI <= 16 ? 2 : 4)>(a, blk, Jw);
-}
-
-template <int JMAX>
-__global__ __launch_bounds__(kSweepBlock) void sweep_guarded_kernel(SweepArgs a, int block0) {
-  __builtin_amdgcn_s_setprio(3);
-  const int blk = block0 + (int)blockIdx.x;
-  sweep_block<JMAX, true>(a, blk, a.block_J[blk]);
-}
-
-template <typename F>
-static hipError_t launch_with_lds(F kernel, int blocks, size_t lds, const SweepArgs& a, int block0,
-                                  hipStream_t st) {
-  hipError_t e = hipFuncSetAttribute((const void*)kernel,
+hipError_t launch_sweep(const int4* waves, int nwaves, size_t lds, const SweepArgs& a,
+                        hipStream_t st) {
+  const int blocks = (nwaves + kSweepBlock / kWave - 1) / (kSweepBlock / kWave);
+  if (blocks <= 0) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)sweep_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  kernel<<<blocks, kSweepBlock, lds, st>>>(a, block0);
+  sweep_kernel<<<blocks, kSweepBlock, lds, st>>>(a, waves, nwaves);
   return hipGetLastError();
-}
-
-// Blocks are in ascending J.  Ranges: J <= 16, J <= 32, J <= 64 run exact
-// bodies (each range its own kernel, so its own register allocation); larger
-// J run guarded bodies (128 or 256 registers).  Every range goes to its own
-// stream and the ranges start in descending J: a block's atom loop is
-// sequential, so the few long high-J blocks must overlap the bulk instead of
-// trailing it.
-hipError_t launch_sweep(const SweepLaunch& sl, size_t lds, const SweepArgs& a,
-                        const hipStream_t* streams) {
-  hipError_t e = hipSuccess;
-  for (int r = kSweepRanges - 1; r >= 0 && e == hipSuccess; --r) {
-    const int b0 = sl.block0[r], nb = sl.block0[r + 1] - sl.block0[r];
-    if (nb <= 0) continue;
-    const hipStream_t st = streams[r];
-    switch (r) {
-      case 0: e = launch_with_lds(sweep_exact_kernel<4, 16>, nb, lds, a, b0, st); break;
-      case 1: e = launch_with_lds(sweep_exact_kernel<20, 32>, nb, lds, a, b0, st); break;
-      case 2: e = launch_with_lds(sweep_exact_kernel<36, 64>, nb, lds, a, b0, st); break;
-      case 3: e = launch_with_lds(sweep_guarded_kernel<128>, nb, lds, a, b0, st); break;
-      default: e = launch_with_lds(sweep_guarded_kernel<256>, nb, lds, a, b0, st); break;
-    }
-  }
-  return e;
 }
 
 // ---- reduction of the sweep's block partials (fixed order) ---------------

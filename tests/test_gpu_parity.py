@@ -146,9 +146,10 @@ def test_sparse_code_only_parity():
     ((40, 36), (6, 5), (1, 1), 20, 0.2),          # ragged grid, odd K
     ((30, 30), (10, 10), (1, 1), 200, 0.15),      # several LDS tiles, two statistics row groups
     ((20, 18, 8), (4, 4, 2), (1, 1, 2), 24, 0.25),  # 3-D video patches with a time stride
-    ((26, 26), (12, 12), (1, 1), 16, 0.35),       # |Obs| ~ 50: 36..64 register bodies
-    ((22, 22), (12, 12), (1, 1), 12, 0.65),       # |Obs| ~ 94: guarded 128-register bodies
-    ((28, 28), (12, 12), (1, 1), 20, 0.2),        # |Obs| spread over three ranges at once
+    ((26, 26), (12, 12), (1, 1), 16, 0.35),       # |Obs| ~ 50: 4 lanes per patch
+    ((22, 22), (12, 12), (1, 1), 12, 0.65),       # |Obs| ~ 94: 8 lanes per patch
+    ((28, 28), (12, 12), (1, 1), 20, 0.2),        # |Obs| spread over 1, 2 and 4 lanes per patch
+    ((20, 20), (12, 12), (1, 1), 8, 0.95),        # |Obs| ~ 137: 16 lanes per patch
     ((96, 96), (6, 6), (1, 1), 16, 0.95),         # 8 statistics chunks, one XCD per chunk
     ((400, 400), (4, 4), (1, 1), 8, 0.9),         # statistics blocks loop over several chunks
 ])
