@@ -202,8 +202,9 @@ Layout make_layout(const Geom& g) {
   L.vpatch = take(4 * P * (size_t)g.Mtot);
   L.omega_y = take(4 * (size_t)g.Mtot);
   L.D = take(4 * K * P);
-  L.list0 = take(8 * Np * K);
-  L.list1 = take(8 * Np * K);
+  // two entries of slack: the sweep reads up to two entries past a row
+  L.list0 = take(8 * Np * K + 16);
+  L.list1 = take(8 * Np * K + 16);
   L.nact0 = take(4 * Np);
   L.nact1 = take(4 * Np);
   L.Ck = take(4 * K);
@@ -211,7 +212,7 @@ Layout make_layout(const Geom& g) {
   L.scal = take(sizeof(DevScalars));
   L.nk = take(8 * K);
   L.sw_cnt = take(4 * K);
-  L.sw_part = take(sizeof(SweepPart) * (size_t)((L.wave_cap + 3) / 4));
+  L.sw_part = take(sizeof(SweepPart) * (size_t)((L.wave_cap + kSweepWaves - 1) / kSweepWaves));
   L.dpart = take(8 * (size_t)P * L.plan.RG * L.plan.chunks * rec_stride);
   L.dx2 = take(8 * P * L.plan.chunks);
   L.Cfull = take(8 * P * K * K);
@@ -633,7 +634,7 @@ bpfa_status bpfa_iterate(bpfa_t h, int32_t n_iters, uint32_t flags) {
     if (h->timing && (r = record(h, &ev[0])) != BPFA_OK) return r;
     HIPCHK(launch_sweep(b.sweep_waves, h->n_waves, L.sweep_lds, a, h->st));
     if (h->timing && (r = record(h, &ev[1])) != BPFA_OK) return r;
-    HIPCHK(launch_sweep_reduce(g, b, (h->n_waves + 3) / 4, h->st));
+    HIPCHK(launch_sweep_reduce(g, b, (h->n_waves + kSweepWaves - 1) / kSweepWaves, h->st));
     h->cur = 1 - h->cur;
     if (learn) {
       DictPlan plan = L.plan;

@@ -8,8 +8,12 @@ namespace bpfa {
 
 constexpr int kWave = 64;
 constexpr int kMaxDim = 4;
-constexpr int kSweepBlock = 256;      // 4 waves share one LDS copy of the dictionary tile
-constexpr int kSlotAlign = kSweepBlock;
+// 8 waves share one LDS copy of the dictionary tile; at <= 128 VGPRs (4 waves
+// per SIMD) two blocks fill a CU, so the LDS tile is not what caps residency
+constexpr int kSweepBlock = 512;
+constexpr int kSweepWaves = kSweepBlock / 64;
+constexpr int kSweepWavesPerSimd = 4;
+constexpr int kSlotAlign = 256;
 constexpr int kLdsTileBytes = 64 * 1024;
 constexpr int kDictBlock = 768;
 constexpr int kDictVpt = 8;       // visits per thread of one statistics chunk, held in registers
@@ -130,13 +134,13 @@ inline size_t dict_stats_lds(int K, long long rec_stride, int chunk_visits) {
 }
 
 // Sweep LDS: tile (P + 1) x KS floats | [wave][K] z counts (bytes) | per-wave
-// partials (4 waves x (2 doubles + 1 int64 + 1 float)), 8-byte aligned.
+// partials (per wave 2 doubles + 1 int64 + 1 float), 8-byte aligned.
 __host__ __device__ inline size_t sweep_red_offset(int P, int KS, int K) {
-  const size_t off = (size_t)(P + 1) * KS * 4 + (size_t)K * (kSweepBlock / kWave);
+  const size_t off = (size_t)(P + 1) * KS * 4 + (size_t)K * kSweepWaves;
   return (off + 7) & ~(size_t)7;
 }
 inline size_t sweep_lds_bytes(int P, int KS, int K) {
-  return sweep_red_offset(P, KS, K) + (size_t)(kSweepBlock / kWave) * (8 + 8 + 8 + 4);
+  return sweep_red_offset(P, KS, K) + (size_t)kSweepWaves * (8 + 8 + 8 + 4);
 }
 
 

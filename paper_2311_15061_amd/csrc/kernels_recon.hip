@@ -179,6 +179,7 @@ __global__ __launch_bounds__(256) void dense_to_lists_kernel(Geom g, const float
     if (z) L[na++] = make_int2(k, __float_as_int(w));
     else if (w != 0.f) atomicOr(bad, 1);
   }
+  if (na < g.K) L[na] = make_int2(-1, 0);   // end marker the sweep relies on
   nact[i] = na;
 }
 

@@ -25,8 +25,9 @@
 //    the same sums (addition is commutative at every level), draws the same
 //    numbers from the patch's Philox counters and takes the same decisions;
 //    only the group's first lane writes the patch's outputs;
-//  * 4 wavefronts per block share one LDS copy of the dictionary tile
-//    (three blocks fit a CU's LDS for 10 x 10 patches and 128 atoms);
+//  * 8 wavefronts per block share one LDS copy of the dictionary tile; the
+//    kernel is held to 128 VGPRs so two blocks (4 waves per SIMD) fit a CU,
+//    and a 512 x 512 frame's waves are all resident at once;
 //  * the tile is pixel-major with an odd atom stride (d_kp at p * KS + k):
 //    a lane's gathers for its observed pixels hit different banks, and the
 //    values of atoms k and k+1 at one pixel are adjacent, so one ds_read2
@@ -46,6 +47,7 @@
 namespace bpfa {
 
 typedef __attribute__((address_space(3))) float lds_f;
+typedef __attribute__((address_space(1))) uint64_t g_entry;   // one (atom, weight) list entry
 
 constexpr float kLn2 = 0.69314718055994531f;
 constexpr float kLog2e = 1.44269504088896341f;
@@ -87,9 +89,9 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslo
   // wavefronts of one block run different instantiations of this body
   char* red = reinterpret_cast<char*>(lds) + sweep_red_offset(a.P, a.KS, a.K);
   double* s_w2 = reinterpret_cast<double*>(red);
-  double* s_r2 = s_w2 + kSweepBlock / kWave;
-  long long* s_z = reinterpret_cast<long long*>(s_r2 + kSweepBlock / kWave);
-  float* s_wm = reinterpret_cast<float*>(s_z + kSweepBlock / kWave);
+  double* s_r2 = s_w2 + kSweepWaves;
+  long long* s_z = reinterpret_cast<long long*>(s_r2 + kSweepWaves);
+  float* s_wm = reinterpret_cast<float*>(s_z + kSweepWaves);
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const int grp = lane / LPP, sub = lane - grp * LPP;
@@ -153,25 +155,28 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslo
     }
   }
 
-  // pass 2: the sweep
+  // pass 2: the sweep.  e0, e1 are the next two unconsumed entries of the
+  // previous sample's list.  A row with na < K holds the marker atom -1 at
+  // position na, so an entry read past it is never taken: the marker is
+  // never matched, and what follows it is only promoted once the marker is
+  // taken.  Reads reach at most two entries past the row (the buffer has
+  // that slack); with na = K they happen after the last atom.
+  const int2 mark = make_int2(-1, 0);
   int cur = 0;
-  int2 e0 = make_int2(K, 0), e1 = make_int2(K, 0);
-  if (na > 0) e0 = lin[0];
-  if (na > 1) e1 = lin[1];
-  int nout = 0;
-  int2* __restrict__ lout = a.list_out + (size_t)ip * K;
-  float sw2 = 0.f, wmx = 0.f;
+  int2 e0 = na > 0 ? lin[0] : mark;
+  int2 e1 = na > 1 ? lin[1] : mark;
+  // (atom, weight bits) as one 64-bit word: atom in the low half, like int2
+  auto entry = [](int k, float w) -> uint64_t {
+    return (uint64_t)(uint32_t)k | ((uint64_t)__float_as_uint(w) << 32);
+  };
+  g_entry* const lout = (g_entry*)(a.list_out + (size_t)ip * K);
+  g_entry* lp = lout;
+  float sw2 = 0.f;
+  uint32_t wmb = 0u;
+  const uint64_t leads = __builtin_amdgcn_ballot_w64(lead);
 
   // one atom: decision and weight given its delta and rho (own term not yet added)
-  auto decide = [&](int k, float delta, float rho, float uz, float n) -> float {
-    float wold = 0.f;
-    if (e0.x == k) {
-      wold = __int_as_float(e0.y);
-      e0 = e1;
-      ++cur;
-      e1 = make_int2(K, 0);
-      if (cur + 1 < na) e1 = lin[cur + 1];
-    }
+  auto decide = [&](int k, float delta, float rho, float wold, float uz, float n) -> float {
     rho = fmaf(delta, wold, rho);
     const float lam = fmaf(ge, delta, gs);
     const float rs = __builtin_amdgcn_rsqf(lam);
@@ -180,15 +185,17 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslo
     const float q = 0.5f * ger * mean;
     const float lhs = uz * lam * rs;
     const float rhs = (1.f - uz) * __builtin_amdgcn_exp2f((Ck[k] + q) * kLog2e);
-    const bool z = valid && (lhs < rhs);
+    const bool cmp = lhs < rhs;
+    const bool z = valid && cmp;
     const float snew = z ? fmaf(n, rs, mean) : 0.f;
-    if (z && lead) {
-      lout[nout++] = make_int2(k, __float_as_int(snew));
-      sw2 = fmaf(snew, snew, sw2);
-      wmx = fmaxf(wmx, fabsf(snew));
-    }
-    const int nz = (int)__popcll(__ballot(z && lead));
+    // ballot of the compare itself (leads holds only valid lanes)
+    const int nz = (int)__popcll(__builtin_amdgcn_ballot_w64(cmp) & leads);
     if (lane == 0) cnt_w[k] = (uint8_t)nz;   // every (wave, atom) is visited exactly once
+    // snew = 0 unless z: the sums take exact zeros (only lead lanes count);
+    // |snew| as bits orders like its value
+    sw2 = fmaf(snew, snew, sw2);
+    wmb = max(wmb, __float_as_uint(snew) & 0x7FFFFFFFu);
+    if (z && lead) *lp++ = entry(k, snew);
     return snew - wold;
   };
 
@@ -200,7 +207,24 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslo
       __syncthreads();
     }
     for (int k = k0; k < k1; k += 2) {
-      const int ko = k - k0;
+      // the offset is hidden from loop strength reduction: each read address
+      // is then one add of this scalar to the column base, not a per-column
+      // induction register plus a copy
+      int ko = k - k0;
+      asm volatile("" : "+s"(ko));
+      // old weights of the pair; the next two entries are fetched now and
+      // first needed by the next pair
+      const bool c0 = e0.x == k;
+      const float wo0 = c0 ? __int_as_float(e0.y) : 0.f;
+      const int2 f = c0 ? e1 : e0;
+      const bool c1 = f.x == k + 1;
+      const float wo1 = c1 ? __int_as_float(f.y) : 0.f;
+      const int adv = (int)c0 + (int)c1;
+      if (adv != 0) {
+        cur += adv;
+        e0 = lin[cur];
+        e1 = lin[cur + 1];
+      }
       const Block4 rb = philox10(ip, (uint32_t)(k >> 1), t, a.stream, a.key0, a.key1);
       float dl0 = 0.f, dl1 = 0.f, rh0 = 0.f, rh1 = 0.f, g01 = 0.f;
 #pragma unroll
@@ -222,9 +246,9 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslo
       const float ang = u01f(rb.w3);                 // revolutions
       const float n0 = rad * __builtin_amdgcn_cosf(ang);
       const float n1 = rad * __builtin_amdgcn_sinf(ang);
-      const float dw0 = decide(k, dl0, rh0, u01f(rb.w0), n0);
+      const float dw0 = decide(k, dl0, rh0, wo0, u01f(rb.w0), n0);
       float dw1 = 0.f;
-      if (k + 1 < k1) dw1 = decide(k + 1, dl1, fmaf(-dw0, g01, rh1), u01f(rb.w1), n1);
+      if (k + 1 < k1) dw1 = decide(k + 1, dl1, fmaf(-dw0, g01, rh1), wo1, u01f(rb.w1), n1);
       // re-read the pair's columns rather than keep 2 J values live across the draws
       asm volatile("" ::: "memory");
       if (dw0 != 0.f || dw1 != 0.f) {
@@ -237,16 +261,21 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslo
     }
   }
 
-  if (lead) a.nact_out[ip] = nout;
+  const int nout = (int)(lp - lout);
+  if (lead) {
+    a.nact_out[ip] = nout;
+    if (nout < K) *lp = entry(-1, 0.f);
+  }
   float r2 = 0.f;
 #pragma unroll
   for (int j = 0; j < J; ++j) r2 = fmaf(r[j], r[j], r2);
 
-  // deterministic block partials: fixed butterfly, then waves in order (sw2,
-  // wmx and the z count come from the lead lanes only; r2 from every lane)
-  double dw2 = (double)sw2, dr2 = (double)r2;
+  // deterministic block partials: fixed butterfly, then waves in order (sw2
+  // and the z count from the lead lanes only, r2 from every lane; the lanes
+  // of a group hold the same max)
+  double dw2 = lead ? (double)sw2 : 0.0, dr2 = (double)r2;
   long long dz = lead ? nout : 0;
-  float dm = wmx;
+  float dm = __uint_as_float(wmb);
   for (int o = kWave / 2; o > 0; o >>= 1) {
     dw2 += __shfl_xor(dw2, o);
     dr2 += __shfl_xor(dr2, o);
@@ -262,7 +291,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslo
   __syncthreads();
   if (tid == 0) {
     SweepPart pt{0.0, 0.0, 0, 0.f, 0};
-    for (int w = 0; w < kSweepBlock / kWave; ++w) {
+    for (int w = 0; w < kSweepWaves; ++w) {
       pt.sum_w2 += s_w2[w];
       pt.sum_r2 += s_r2[w];
       pt.sum_z += s_z[w];
@@ -272,7 +301,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslo
   }
   for (int k = tid; k < K; k += kSweepBlock) {
     int c = 0;
-    for (int w = 0; w < kSweepBlock / kWave; ++w) c += cnt_lds[w * K + k];
+    for (int w = 0; w < kSweepWaves; ++w) c += cnt_lds[w * K + k];
     if (c) atomicAdd(&a.cnt[k], c);
   }
 }
@@ -281,10 +310,10 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslo
 // its (first slot, slots, lanes per slot, J) from the table and runs the body
 // compiled for that pair; wavefronts past the table run with no valid lane
 // (every body passes the same barriers).
-__global__ __launch_bounds__(kSweepBlock) void sweep_kernel(SweepArgs a, const int4* __restrict__ waves,
+__global__ __launch_bounds__(kSweepBlock, kSweepWavesPerSimd) void sweep_kernel(SweepArgs a, const int4* __restrict__ waves,
                                                             int nwaves) {
   const int blk = blockIdx.x;
-  const int w = blk * (kSweepBlock / kWave) + (int)(threadIdx.x / kWave);
+  const int w = blk * (kSweepWaves) + (int)(threadIdx.x / kWave);
   int4 wt = make_int4(0, 0, 1, 4);
   if (w < nwaves) wt = waves[w];
   const int slot0 = __builtin_amdgcn_readfirstlane(wt.x);
@@ -315,7 +344,7 @@ __global__ __launch_bounds__(kSweepBlock) void sweep_kernel(SweepArgs a, const i
 
 hipError_t launch_sweep(const int4* waves, int nwaves, size_t lds, const SweepArgs& a,
                         hipStream_t st) {
-  const int blocks = (nwaves + kSweepBlock / kWave - 1) / (kSweepBlock / kWave);
+  const int blocks = (nwaves + kSweepWaves - 1) / (kSweepWaves);
   if (blocks <= 0) return hipSuccess;
   hipError_t e = hipFuncSetAttribute((const void*)sweep_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
