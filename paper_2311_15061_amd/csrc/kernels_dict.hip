@@ -405,6 +405,7 @@ __device__ __forceinline__ void chain_run(const Geom& g, int p, int lane, const 
                                           double* __restrict__ sumr2_p, uint32_t key0,
                                           uint32_t key1, uint32_t stream,
                                           const double* u0 = nullptr) {
+  static_assert(kWave % PF == 0, "a ring slot keeps its row across register groups");
   const int K = g.K, P = g.P;
   const uint32_t t = (uint32_t)scal->t;
   const double ge = scal->gamma_eps;
@@ -454,44 +455,43 @@ __device__ __forceinline__ void chain_run(const Geom& g, int p, int lane, const 
       }
     }
   }
-  // the chain, rows of C_p (= columns, by symmetry) prefetched PF ahead
+  // the chain, rows of C_p (= columns, by symmetry) prefetched PF ahead.
+  // Loads are unconditional (row and column clamped into the matrix; rows
+  // past K are never consumed and lanes past K only feed u entries that are
+  // never read), so a refill lands in its ring slot with no select and is
+  // waited for only PF steps later.  The loop is split by register group m
+  // (steps 64 m .. 64 m + 63), so the readlanes and the d update name one
+  // register each.
   double ring[PF][KPL];
 #pragma unroll
   for (int u = 0; u < PF; ++u)
 #pragma unroll
-    for (int m = 0; m < KPL; ++m) {
-      const int j = lane + kWave * m;
-      ring[u][m] = (u < K && j < K) ? C[(size_t)u * K + j] : 0.0;
-    }
+    for (int m = 0; m < KPL; ++m)
+      ring[u][m] = C[(size_t)min(u, K - 1) * K + min(lane + kWave * m, K - 1)];
   bool bad = false;
-  for (int kb = 0; kb < K; kb += PF) {
 #pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const int k = kb + u;
-      if (k < K) {
-        double uk = 0.0, dk = 0.0, gk = 0.0, tk = 0.0;
+  for (int m = 0; m < KPL; ++m) {
+    const int kend = min(K, kWave * (m + 1));
+    for (int kb = kWave * m; kb < kend; kb += PF) {
 #pragma unroll
-        for (int m = 0; m < KPL; ++m)
-          if ((k >> 6) == m) {
-            const int kl = k & 63;
-            uk = readlane_d(ureg[m], kl);
-            dk = readlane_d(dreg[m], kl);
-            gk = readlane_d(greg[m], kl);
-            tk = readlane_d(treg[m], kl);
-          }
-        const double dn = fma(-gk, uk, tk);
-        bad = bad || !isfinite(dn);
-        const double delta = dn - dk;
+      for (int u = 0; u < PF; ++u) {
+        const int k = kb + u;
+        if (k < kend) {
+          const int kl = k - kWave * m;
+          const double uk = readlane_d(ureg[m], kl);
+          const double dk = readlane_d(dreg[m], kl);
+          const double gk = readlane_d(greg[m], kl);
+          const double tk = readlane_d(treg[m], kl);
+          const double dn = fma(-gk, uk, tk);
+          bad = bad || !isfinite(dn);
+          const double delta = dn - dk;
 #pragma unroll
-        for (int m = 0; m < KPL; ++m) {
-          ureg[m] = fma(ring[u][m], delta, ureg[m]);
-          if (k == lane + kWave * m) dreg[m] = dn;
-        }
-        const int kn = k + PF;
+          for (int mm = 0; mm < KPL; ++mm) ureg[mm] = fma(ring[u][mm], delta, ureg[mm]);
+          if (lane == kl) dreg[m] = dn;
+          const int kn = min(k + PF, K - 1);
 #pragma unroll
-        for (int m = 0; m < KPL; ++m) {
-          const int j = lane + kWave * m;
-          ring[u][m] = (kn < K && j < K) ? C[(size_t)kn * K + j] : 0.0;
+          for (int mm = 0; mm < KPL; ++mm)
+            ring[u][mm] = C[(size_t)kn * K + min(lane + kWave * mm, K - 1)];
         }
       }
     }
@@ -593,7 +593,9 @@ __global__ __launch_bounds__(1024) void dict_chain_lds_kernel(
   }
   __syncthreads();
   if (tid < kWave)
-    chain_run<KPL, 16>(g, p, tid, Cs, s_B, s_diag, x2p[p], scal, D, sumr2_p, key0, key1, stream,
+    // 8 row loads in flight: the LDS counter holds at most 15 outstanding,
+    // so a deeper ring makes every step wait for all of them
+    chain_run<KPL, 8 / KPL>(g, p, tid, Cs, s_B, s_diag, x2p[p], scal, D, sumr2_p, key0, key1, stream,
                        s_u);
 }
 
