@@ -285,3 +285,19 @@ def reconstruct(st, shape, patch, stride):
     """Overlap average of the patch models D^T w_i (last Gibbs sample)."""
     from . import patches
     return patches.overlap_average(st.W @ st.D, shape, patch, stride)
+
+
+def posterior_mean(states, shape, patch, stride):
+    """Posterior-mean reconstruction: the average over the kept Gibbs samples
+    (those after burn-in, in any order) of each sample's overlap-averaged
+    reconstruction -- the Monte Carlo estimate of E[x | y] from the sampler
+    of the BPFA section (reading: the paper names averaging samples for
+    frame interpolation of N-D data but gives no estimator; this is the plain
+    sample mean)."""
+    states = list(states)
+    if not states:
+        raise ValueError("posterior mean of no samples")
+    acc = np.zeros(shape, dtype=np.float64)
+    for st in states:
+        acc += reconstruct(st, shape, patch, stride)
+    return acc / len(states)
