@@ -328,6 +328,27 @@ def main():
         outs[prec] = o.cpu().numpy().astype(np.float64)
     prob.set_precision("fp32")
     res["reconstruct_ms"] = rec_ms
+    # posterior mean over the last half of a frame's iterations (after burn-in)
+    prob.reset_state()
+    prob.set_frame(y_d, m_d, reset_codes=True)
+    prob.iterate(iters - iters // 2, bpfa.LEARN_DICT)
+    for _ in range(iters // 2):
+        prob.iterate(1, bpfa.LEARN_DICT)
+        prob.mean_accumulate()
+    pm, n_kept = prob.posterior_mean()          # host copy: synchronises the handle's stream
+    # cost of one accumulation (a reconstruction plus the binary64 add), 20 in a row
+    prob.sync()
+    t_acc = time.perf_counter()
+    for _ in range(20):
+        prob.mean_accumulate()
+    prob.sync()
+    acc_ms = 1e3 * (time.perf_counter() - t_acc) / 20
+    prob.mean_reset()
+    res["posterior_mean"] = {"samples": n_kept, "burn_in": iters - iters // 2,
+                             "accumulate_ms": acc_ms}
+    if not args.no_quality:
+        res["posterior_mean"]["psnr_db"] = metrics.psnr(pm, g)
+        res["posterior_mean"]["ssim"] = metrics.ssim(pm, g)
     if not args.no_quality:
         x = out_d.cpu().numpy()
         res["psnr_db"] = metrics.psnr(x, g)

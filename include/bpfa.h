@@ -161,6 +161,22 @@ bpfa_status bpfa_iterate(bpfa_t h, int32_t n_iters, uint32_t flags);
  * prod(shape) floats of kind `mem`; host memory synchronises the stream. */
 bpfa_status bpfa_reconstruct(bpfa_t h, float* out, bpfa_mem mem);
 
+/* Posterior-mean reconstruction (the average of samples after burn-in; the
+ * N-dimensional inpainting section's averaging over samples, read as the
+ * plain Monte Carlo mean of the Gibbs samples' reconstructions).
+ * bpfa_mean_accumulate adds the current sample's overlap-averaged
+ * reconstruction (as bpfa_reconstruct computes it, in the precision form set
+ * by bpfa_set_precision) to a binary64 running sum in the workspace;
+ * stream-ordered, no host synchronisation.  bpfa_mean_get writes the mean of
+ * the accumulated samples, rounded to binary32, to out (prod(shape) floats of
+ * kind `mem`; host memory synchronises) and the sample count to *count when
+ * count is not NULL; ESTATE when no sample has been accumulated.
+ * bpfa_mean_reset starts a new mean; bpfa_set_frame and bpfa_reset_state do
+ * too. */
+bpfa_status bpfa_mean_reset(bpfa_t h);
+bpfa_status bpfa_mean_accumulate(bpfa_t h);
+bpfa_status bpfa_mean_get(bpfa_t h, float* out, bpfa_mem mem, int64_t* count);
+
 /* Precision form of the reconstruction's dense contraction y_i = D^T w_i
  * (every patch's model, before the overlap average).  BPFA_FP32 (default):
  * binary32 products and sums on the matrix cores.  BPFA_BF16: every operand

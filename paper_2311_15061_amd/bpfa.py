@@ -22,7 +22,8 @@ _NAMES = {EINVAL: "EINVAL", ESHAPE: "ESHAPE", ENOMEM: "ENOMEM", EDEVICE: "EDEVIC
           ESTATE: "ESTATE", ENUMERIC: "ENUMERIC", EBUSY: "EBUSY"}
 
 EXPORTED = ["bpfa_params_default", "bpfa_workspace_size", "bpfa_create", "bpfa_set_frame",
-            "bpfa_reset_state", "bpfa_iterate", "bpfa_reconstruct", "bpfa_set_precision",
+            "bpfa_reset_state", "bpfa_iterate", "bpfa_reconstruct", "bpfa_mean_reset",
+            "bpfa_mean_accumulate", "bpfa_mean_get", "bpfa_set_precision",
             "bpfa_transfer_dictionary", "bpfa_get_state",
             "bpfa_set_state", "bpfa_get_stats", "bpfa_set_timing", "bpfa_sync",
             "bpfa_get_patch_index", "bpfa_debug_philox", "bpfa_destroy", "bpfa_last_error"]
@@ -100,6 +101,9 @@ def _load():
         "bpfa_reset_state": (ctypes.c_int, [vp]),
         "bpfa_iterate": (ctypes.c_int, [vp, i32, u32]),
         "bpfa_reconstruct": (ctypes.c_int, [vp, vp, ctypes.c_int]),
+        "bpfa_mean_reset": (ctypes.c_int, [vp]),
+        "bpfa_mean_accumulate": (ctypes.c_int, [vp]),
+        "bpfa_mean_get": (ctypes.c_int, [vp, vp, ctypes.c_int, P(i64)]),
         "bpfa_set_precision": (ctypes.c_int, [vp, u32]),
         "bpfa_transfer_dictionary": (ctypes.c_int, [vp, vp, u32]),
         "bpfa_get_state": (ctypes.c_int, [vp, P(StateView)]),
@@ -259,6 +263,23 @@ class Problem:
         ptr, kind, keep = _buffer(out, np.float32)
         _check(lib.bpfa_reconstruct(self._h, ptr, kind))
         return out
+
+    def mean_reset(self):
+        """Start a new posterior mean (set_frame and reset_state do too)."""
+        _check(lib.bpfa_mean_reset(self._h))
+
+    def mean_accumulate(self):
+        """Add the current sample's reconstruction to the posterior-mean sum."""
+        _check(lib.bpfa_mean_accumulate(self._h))
+
+    def posterior_mean(self, out=None):
+        """Mean of the accumulated samples' reconstructions: (out, sample count)."""
+        if out is None:
+            out = np.empty(self.shape, np.float32)
+        ptr, kind, keep = _buffer(out, np.float32)
+        n = ctypes.c_int64(0)
+        _check(lib.bpfa_mean_get(self._h, ptr, kind, ctypes.byref(n)))
+        return out, int(n.value)
 
     def set_precision(self, precision):
         """'fp32' (binary32 contractions) or 'bf16' (BF16 matrix-core contractions with one

@@ -64,7 +64,7 @@ struct Layout {
   // byte offsets
   size_t image, mask, poff, pcoord, obs_bits, obs_count, perm, inv_perm, obs_idx, obs_val, sweep_waves, sort_hist, sort_bin,
       omega, omega_c, omega_blk, vpatch, omega_y, D, list0, list1, nact0, nact1, Ck, ell, scal, nk, sw_cnt, sw_part, dpart,
-      dx2, Cfull, Bvec, diag, x2p, sumr2_p, Y, recon, total;
+      dx2, Cfull, Bvec, diag, x2p, sumr2_p, Y, recon, mean, total;
 };
 
 bpfa_status make_geom(const bpfa_params* p, Geom* g) {
@@ -222,6 +222,7 @@ Layout make_layout(const Geom& g) {
   L.sumr2_p = take(8 * P);
   L.Y = take(4 * P * N);
   L.recon = take(4 * (size_t)g.Mtot);
+  L.mean = take(8 * (size_t)g.Mtot);   // posterior-mean running sum
   L.total = off;
   return L;
 }
@@ -248,6 +249,7 @@ struct bpfa_problem {
   std::vector<int4> wave_host;  // staging of the wavefront table
   uint32_t key0 = 0, key1 = 0;
   int64_t t_host = 1;
+  int64_t mean_count = 0;       // samples in the posterior-mean running sum
   // timing
   bool timing = false;
   std::vector<std::array<hipEvent_t, 4>> iter_events;
@@ -574,6 +576,7 @@ bpfa_status bpfa_set_frame(bpfa_t h, const float* image, const uint8_t* mask, bp
                            int reset_codes) {
   if (!h) return fail(BPFA_EINVAL, "NULL handle");
   DeviceGuard dg(h->prm.device);
+  h->mean_count = 0;
   return load_frame(h, image, mask, mem, reset_codes == 0);
 }
 
@@ -587,6 +590,7 @@ bpfa_status bpfa_reset_state(bpfa_t h) {
   HIPCHK(launch_init_dict(g, h->b, h->key0, h->key1, stream_word(7, h->prm.problem_id), h->st));
   HIPCHK(launch_ck(g, h->b, h->st));
   h->t_host = 1;
+  h->mean_count = 0;
   return clear_codes(h);
 }
 
@@ -674,6 +678,37 @@ bpfa_status bpfa_reconstruct(bpfa_t h, float* out, bpfa_mem mem) {
     if ((r = record(h, &ev[1])) != BPFA_OK) return r;
     h->recon_events.push_back(ev);
   }
+  if (mem == BPFA_HOST) {
+    HIPCHK(hipMemcpyAsync(out, dst, 4 * (size_t)h->g.Mtot, hipMemcpyDeviceToHost, h->st));
+    return check_status(h);
+  }
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_mean_reset(bpfa_t h) {
+  if (!h) return fail(BPFA_EINVAL, "NULL handle");
+  h->mean_count = 0;
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_mean_accumulate(bpfa_t h) {
+  if (!h) return fail(BPFA_EINVAL, "NULL handle");
+  DeviceGuard dg(h->prm.device);
+  float* x = (float*)(h->ws + h->L.recon);
+  HIPCHK(launch_recon(h->g, h->b, h->cur, h->L.Npad, x, h->precision == BPFA_BF16, h->st));
+  HIPCHK(launch_mean_add(h->g.Mtot, x, (double*)(h->ws + h->L.mean), h->mean_count == 0, h->st));
+  ++h->mean_count;
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_mean_get(bpfa_t h, float* out, bpfa_mem mem, int64_t* count) {
+  if (!h || !out) return fail(BPFA_EINVAL, "NULL handle or output");
+  if (h->mean_count == 0) return fail(BPFA_ESTATE, "no sample accumulated for the posterior mean");
+  DeviceGuard dg(h->prm.device);
+  float* dst = mem == BPFA_DEVICE ? out : (float*)(h->ws + h->L.recon);
+  HIPCHK(launch_mean_get(h->g.Mtot, (const double*)(h->ws + h->L.mean), (double)h->mean_count, dst,
+                         h->st));
+  if (count) *count = h->mean_count;
   if (mem == BPFA_HOST) {
     HIPCHK(hipMemcpyAsync(out, dst, 4 * (size_t)h->g.Mtot, hipMemcpyDeviceToHost, h->st));
     return check_status(h);

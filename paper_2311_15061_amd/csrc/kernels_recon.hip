@@ -114,6 +114,33 @@ __global__ __launch_bounds__(256) void recon_pixel_kernel(Geom g, const float* _
   out[q] = acc / (float)(cnt[0] * cnt[1] * cnt[2] * cnt[3]);
 }
 
+// Posterior mean over Gibbs samples: each sample's reconstruction is added to
+// a binary64 running sum (the first sample overwrites it), and the mean is
+// the sum divided by the sample count, rounded to binary32.
+__global__ __launch_bounds__(256) void mean_add_kernel(long long n, const float* __restrict__ x,
+                                                       double* __restrict__ sum, int first) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) sum[i] = first ? (double)x[i] : sum[i] + (double)x[i];
+}
+
+__global__ __launch_bounds__(256) void mean_get_kernel(long long n, const double* __restrict__ sum,
+                                                       double count, float* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)(sum[i] / count);
+}
+
+hipError_t launch_mean_add(long long n, const float* x, double* sum, bool first, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  mean_add_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, x, sum, first ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_mean_get(long long n, const double* sum, double count, float* out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  mean_get_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, sum, count, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_recon(const Geom& g, const Buffers& b, int cur, int Npad, float* out, bool bf16,
                         hipStream_t st) {
   (void)Npad;
