@@ -301,3 +301,18 @@ def posterior_mean(states, shape, patch, stride):
     for st in states:
         acc += reconstruct(st, shape, patch, stride)
     return acc / len(states)
+
+
+def posterior_variance(states, shape, patch, stride):
+    """Per-pixel unbiased sample variance of the kept samples' reconstructions,
+    (1 / (n - 1)) sum_s (x_s - mean)^2 -- the spread that on-the-fly targeted
+    signal selection (Feature summary) can steer acquisition by (reading:
+    the paper names strategic selection without a criterion)."""
+    states = list(states)
+    if len(states) < 2:
+        raise ValueError("posterior variance needs at least two samples")
+    mean = posterior_mean(states, shape, patch, stride)
+    acc = np.zeros(shape, dtype=np.float64)
+    for st in states:
+        acc += (reconstruct(st, shape, patch, stride) - mean) ** 2
+    return acc / (len(states) - 1)

@@ -67,3 +67,27 @@ def test_posterior_mean_is_linear_in_the_patch_models():
 def test_posterior_mean_needs_a_sample():
     with pytest.raises(ValueError):
         bpfa.posterior_mean([], (4, 4), (2, 2), (1, 1))
+
+
+def test_posterior_variance_two_samples_closed_form():
+    """n = 2: the unbiased variance is (a - b)^2 / 2 pixel by pixel."""
+    shape, patch, stride = (8, 7), (3, 2), (1, 1)
+    s1, s2 = _states(shape, patch, stride, K=4, S=2, seed=9)
+    a = bpfa.reconstruct(s1, shape, patch, stride)
+    b = bpfa.reconstruct(s2, shape, patch, stride)
+    assert np.allclose(bpfa.posterior_variance([s1, s2], shape, patch, stride), (a - b) ** 2 / 2,
+                       rtol=1e-12, atol=1e-15)
+
+
+def test_posterior_variance_matches_numpy_and_vanishes_on_repeats():
+    shape, patch, stride = (9, 6, 3), (3, 2, 3), (1, 1, 1)
+    states = _states(shape, patch, stride, K=5, S=5, seed=13)
+    stack = np.stack([_brute_force_mean([st], shape, patch, stride) for st in states])
+    assert np.allclose(bpfa.posterior_variance(states, shape, patch, stride),
+                       np.var(stack, axis=0, ddof=1), rtol=1e-10, atol=1e-14)
+    # repeated samples: zero up to the rounding of the mean
+    x = bpfa.reconstruct(states[0], shape, patch, stride)
+    v0 = bpfa.posterior_variance([states[0]] * 3, shape, patch, stride)
+    assert np.all(v0 <= 1e-30 * (1.0 + x * x))
+    with pytest.raises(ValueError):
+        bpfa.posterior_variance(states[:1], shape, patch, stride)
