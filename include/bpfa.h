@@ -177,6 +177,14 @@ bpfa_status bpfa_mean_reset(bpfa_t h);
 bpfa_status bpfa_mean_accumulate(bpfa_t h);
 bpfa_status bpfa_mean_get(bpfa_t h, float* out, bpfa_mem mem, int64_t* count);
 
+/* Per-pixel unbiased sample variance of the accumulated reconstructions,
+ * (S2 - S1^2 / n) / (n - 1) from the binary64 sums S1 = sum x and S2 =
+ * sum x^2 that bpfa_mean_accumulate keeps, rounded to binary32 (negative
+ * rounding residue clamped to 0): the spread that the Feature summary's
+ * on-the-fly strategic signal selection can steer acquisition by.  Same
+ * output convention as bpfa_mean_get; ESTATE with fewer than two samples. */
+bpfa_status bpfa_variance_get(bpfa_t h, float* out, bpfa_mem mem, int64_t* count);
+
 /* Precision form of the reconstruction's dense contraction y_i = D^T w_i
  * (every patch's model, before the overlap average).  BPFA_FP32 (default):
  * binary32 products and sums on the matrix cores.  BPFA_BF16: every operand

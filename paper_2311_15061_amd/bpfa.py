@@ -23,7 +23,7 @@ _NAMES = {EINVAL: "EINVAL", ESHAPE: "ESHAPE", ENOMEM: "ENOMEM", EDEVICE: "EDEVIC
 
 EXPORTED = ["bpfa_params_default", "bpfa_workspace_size", "bpfa_create", "bpfa_set_frame",
             "bpfa_reset_state", "bpfa_iterate", "bpfa_reconstruct", "bpfa_mean_reset",
-            "bpfa_mean_accumulate", "bpfa_mean_get", "bpfa_set_precision",
+            "bpfa_mean_accumulate", "bpfa_mean_get", "bpfa_variance_get", "bpfa_set_precision",
             "bpfa_transfer_dictionary", "bpfa_get_state",
             "bpfa_set_state", "bpfa_get_stats", "bpfa_set_timing", "bpfa_sync",
             "bpfa_get_patch_index", "bpfa_debug_philox", "bpfa_destroy", "bpfa_last_error"]
@@ -104,6 +104,7 @@ def _load():
         "bpfa_mean_reset": (ctypes.c_int, [vp]),
         "bpfa_mean_accumulate": (ctypes.c_int, [vp]),
         "bpfa_mean_get": (ctypes.c_int, [vp, vp, ctypes.c_int, P(i64)]),
+        "bpfa_variance_get": (ctypes.c_int, [vp, vp, ctypes.c_int, P(i64)]),
         "bpfa_set_precision": (ctypes.c_int, [vp, u32]),
         "bpfa_transfer_dictionary": (ctypes.c_int, [vp, vp, u32]),
         "bpfa_get_state": (ctypes.c_int, [vp, P(StateView)]),
@@ -279,6 +280,15 @@ class Problem:
         ptr, kind, keep = _buffer(out, np.float32)
         n = ctypes.c_int64(0)
         _check(lib.bpfa_mean_get(self._h, ptr, kind, ctypes.byref(n)))
+        return out, int(n.value)
+
+    def posterior_variance(self, out=None):
+        """Unbiased per-pixel variance of the accumulated samples: (out, sample count)."""
+        if out is None:
+            out = np.empty(self.shape, np.float32)
+        ptr, kind, keep = _buffer(out, np.float32)
+        n = ctypes.c_int64(0)
+        _check(lib.bpfa_variance_get(self._h, ptr, kind, ctypes.byref(n)))
         return out, int(n.value)
 
     def set_precision(self, precision):

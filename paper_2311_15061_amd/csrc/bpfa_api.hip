@@ -64,7 +64,7 @@ struct Layout {
   // byte offsets
   size_t image, mask, poff, pcoord, obs_bits, obs_count, perm, inv_perm, obs_idx, obs_val, sweep_waves, sort_hist, sort_bin,
       omega, omega_c, omega_blk, vpatch, omega_y, D, list0, list1, nact0, nact1, Ck, ell, scal, nk, sw_cnt, sw_part, dpart,
-      dx2, Cfull, Bvec, diag, x2p, sumr2_p, Y, recon, mean, total;
+      dx2, Cfull, Bvec, diag, x2p, sumr2_p, Y, recon, mean, mean2, total;
 };
 
 bpfa_status make_geom(const bpfa_params* p, Geom* g) {
@@ -222,7 +222,8 @@ Layout make_layout(const Geom& g) {
   L.sumr2_p = take(8 * P);
   L.Y = take(4 * P * N);
   L.recon = take(4 * (size_t)g.Mtot);
-  L.mean = take(8 * (size_t)g.Mtot);   // posterior-mean running sum
+  L.mean = take(8 * (size_t)g.Mtot);   // posterior-moment running sums
+  L.mean2 = take(8 * (size_t)g.Mtot);
   L.total = off;
   return L;
 }
@@ -696,7 +697,8 @@ bpfa_status bpfa_mean_accumulate(bpfa_t h) {
   DeviceGuard dg(h->prm.device);
   float* x = (float*)(h->ws + h->L.recon);
   HIPCHK(launch_recon(h->g, h->b, h->cur, h->L.Npad, x, h->precision == BPFA_BF16, h->st));
-  HIPCHK(launch_mean_add(h->g.Mtot, x, (double*)(h->ws + h->L.mean), h->mean_count == 0, h->st));
+  HIPCHK(launch_mean_add(h->g.Mtot, x, (double*)(h->ws + h->L.mean), (double*)(h->ws + h->L.mean2),
+                         h->mean_count == 0, h->st));
   ++h->mean_count;
   return BPFA_OK;
 }
@@ -708,6 +710,21 @@ bpfa_status bpfa_mean_get(bpfa_t h, float* out, bpfa_mem mem, int64_t* count) {
   float* dst = mem == BPFA_DEVICE ? out : (float*)(h->ws + h->L.recon);
   HIPCHK(launch_mean_get(h->g.Mtot, (const double*)(h->ws + h->L.mean), (double)h->mean_count, dst,
                          h->st));
+  if (count) *count = h->mean_count;
+  if (mem == BPFA_HOST) {
+    HIPCHK(hipMemcpyAsync(out, dst, 4 * (size_t)h->g.Mtot, hipMemcpyDeviceToHost, h->st));
+    return check_status(h);
+  }
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_variance_get(bpfa_t h, float* out, bpfa_mem mem, int64_t* count) {
+  if (!h || !out) return fail(BPFA_EINVAL, "NULL handle or output");
+  if (h->mean_count < 2) return fail(BPFA_ESTATE, "the variance needs two accumulated samples");
+  DeviceGuard dg(h->prm.device);
+  float* dst = mem == BPFA_DEVICE ? out : (float*)(h->ws + h->L.recon);
+  HIPCHK(launch_variance_get(h->g.Mtot, (const double*)(h->ws + h->L.mean),
+                             (const double*)(h->ws + h->L.mean2), (double)h->mean_count, dst, h->st));
   if (count) *count = h->mean_count;
   if (mem == BPFA_HOST) {
     HIPCHK(hipMemcpyAsync(out, dst, 4 * (size_t)h->g.Mtot, hipMemcpyDeviceToHost, h->st));

@@ -170,9 +170,13 @@ hipError_t launch_dict_chain(const Geom& g, const Buffers& b, const DictPlan& pl
                              uint32_t key0, uint32_t key1, uint32_t stream, hipStream_t st);
 hipError_t launch_scalars(const Geom& g, const Buffers& b, const double* hyper, int learn_dict,
                           uint32_t key0, uint32_t key1, uint32_t problem_id, hipStream_t st);
-// posterior mean: sum = x (first) or sum += x; out = sum / count
-hipError_t launch_mean_add(long long n, const float* x, double* sum, bool first, hipStream_t st);
+// posterior moments: (sum, sum2) = (x, x^2) (first) or += (x, x^2);
+// mean = sum / count; variance = (sum2 - sum^2 / count) / (count - 1)
+hipError_t launch_mean_add(long long n, const float* x, double* sum, double* sum2, bool first,
+                           hipStream_t st);
 hipError_t launch_mean_get(long long n, const double* sum, double count, float* out, hipStream_t st);
+hipError_t launch_variance_get(long long n, const double* sum, const double* sum2, double count,
+                               float* out, hipStream_t st);
 hipError_t launch_recon(const Geom& g, const Buffers& b, int cur, int Npad, float* out, bool bf16,
                         hipStream_t st);
 hipError_t launch_recon_patches_mfma(const Geom& g, const Buffers& b, int cur, hipStream_t st);

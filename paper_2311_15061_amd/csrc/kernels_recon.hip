@@ -114,13 +114,36 @@ __global__ __launch_bounds__(256) void recon_pixel_kernel(Geom g, const float* _
   out[q] = acc / (float)(cnt[0] * cnt[1] * cnt[2] * cnt[3]);
 }
 
-// Posterior mean over Gibbs samples: each sample's reconstruction is added to
-// a binary64 running sum (the first sample overwrites it), and the mean is
-// the sum divided by the sample count, rounded to binary32.
+// Posterior moments over Gibbs samples: each sample's reconstruction and its
+// square are added to binary64 running sums (the first sample overwrites
+// them); the mean is the sum divided by the sample count, rounded to
+// binary32.  x^2 of a binary32 x is exact in binary64.
 __global__ __launch_bounds__(256) void mean_add_kernel(long long n, const float* __restrict__ x,
-                                                       double* __restrict__ sum, int first) {
+                                                       double* __restrict__ sum,
+                                                       double* __restrict__ sum2, int first) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) sum[i] = first ? (double)x[i] : sum[i] + (double)x[i];
+  if (i < n) {
+    const double v = (double)x[i];
+    sum[i] = first ? v : sum[i] + v;
+    sum2[i] = first ? v * v : sum2[i] + v * v;
+  }
+}
+
+__global__ __launch_bounds__(256) void variance_get_kernel(long long n, const double* __restrict__ sum,
+                                                           const double* __restrict__ sum2,
+                                                           double count, float* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double s = sum[i];
+    out[i] = (float)fmax(0.0, (sum2[i] - s * s / count) / (count - 1.0));
+  }
+}
+
+hipError_t launch_variance_get(long long n, const double* sum, const double* sum2, double count,
+                               float* out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  variance_get_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, sum, sum2, count, out);
+  return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void mean_get_kernel(long long n, const double* __restrict__ sum,
@@ -129,9 +152,10 @@ __global__ __launch_bounds__(256) void mean_get_kernel(long long n, const double
   if (i < n) out[i] = (float)(sum[i] / count);
 }
 
-hipError_t launch_mean_add(long long n, const float* x, double* sum, bool first, hipStream_t st) {
+hipError_t launch_mean_add(long long n, const float* x, double* sum, double* sum2, bool first,
+                           hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  mean_add_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, x, sum, first ? 1 : 0);
+  mean_add_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, x, sum, sum2, first ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -147,6 +147,8 @@ def test_sparse_code_only_parity():
     ((30, 30), (10, 10), (1, 1), 200, 0.15),      # several LDS tiles, two statistics row groups
     ((20, 18, 8), (4, 4, 2), (1, 1, 2), 24, 0.25),  # 3-D video patches with a time stride
     ((10, 9, 6, 5), (3, 3, 2, 2), (1, 1, 2, 1), 12, 0.3),  # 4-D patches spanning two frames
+    ((24, 22, 3), (6, 6, 3), (1, 1, 1), 16, 0.3),  # full-depth patches (B_2 = M_2, e.g. RGB)
+    ((20, 20, 3), (5, 5, 1), (1, 1, 1), 16, 0.3),  # one single-channel dictionary across layers
     ((26, 26), (12, 12), (1, 1), 16, 0.35),       # |Obs| ~ 50: 4 lanes per patch
     ((22, 22), (12, 12), (1, 1), 12, 0.65),       # |Obs| ~ 94: 8 lanes per patch
     ((28, 28), (12, 12), (1, 1), 20, 0.2),        # |Obs| spread over 1, 2 and 4 lanes per patch

@@ -75,3 +75,46 @@ def test_posterior_mean_reset_and_errors():
     with pytest.raises(bpfa.BpfaError):
         prob.posterior_mean()
     prob.close()
+
+
+@pytest.mark.parametrize("shape,patch,stride,K,rho", [
+    ((64, 64), (8, 8), (1, 1), 32, 0.25),
+    ((20, 20, 3), (5, 5, 1), (1, 1, 1), 16, 0.3),   # one single-channel dictionary across layers
+])
+def test_posterior_variance_parity(shape, patch, stride, K, rho):
+    y, m, g = case(shape, patch, stride, K, rho, seed=K + 2)
+    prob, kept = _run(y, m, patch, stride, K, 0xBEEF + K, iters=7, burn_in=2)
+    var, n = prob.posterior_variance()
+    assert n == len(kept) == 5
+    ref = ob.posterior_variance(kept, shape, patch, stride)
+    e = assert_close(var, ref, FP32_TOL, "posterior variance")
+    assert np.all(var >= 0)
+    print("posterior variance error %.2e over %d samples" % (e, n))
+    prob.close()
+
+
+def test_targeted_selection_follows_the_variance():
+    """On-the-fly strategic selection: new acquisitions drawn by posterior
+    variance land where the variance is high, and the frame continues from the
+    kept codes with the refined mask."""
+    from paper_2311_15061_amd import sampling
+    wl = synth.workload("lattice64")
+    y, m0, g = synth.make_frame(wl)
+    m = sampling.uniform_mask(wl.shape, 0.10, seed=5)
+    prob = bpfa.Problem(np.asarray(y, np.float32), m, wl.patch, wl.stride, K=wl.K, seed=wl.method_seed)
+    prob.iterate(6)
+    for _ in range(4):
+        prob.iterate(1)
+        prob.mean_accumulate()
+    var, n = prob.posterior_variance()
+    assert n == 4 and np.all(var >= 0)
+    m2 = sampling.targeted_mask(var, 0.20, seed=6, base=m)
+    assert m2.sum() == round(0.20 * m2.size) and np.all(m2[m != 0] == 1)
+    new = (m2 != 0) & (m == 0)
+    unobserved = m == 0
+    assert var[new].mean() > 1.5 * var[unobserved].mean()
+    prob.set_frame(np.asarray(y, np.float32), m2, reset_codes=False)
+    prob.iterate(3)
+    xh = prob.reconstruct()
+    assert np.all(np.isfinite(xh))
+    prob.close()
