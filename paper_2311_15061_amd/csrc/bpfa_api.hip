@@ -247,7 +247,11 @@ struct bpfa_problem {
   int n_cu = 256;               // compute units of the device
   int n_waves = 0;              // sweep wavefronts of this frame
   int jpad = 4;                 // obs rows written per slot for this frame
-  std::vector<int4> wave_host;  // staging of the wavefront table
+  // pinned host staging (hipHostMalloc): the frame load's readback of the
+  // scalars and |Obs| bin starts, and the wavefront table it uploads, so the
+  // copies run as DMA without a pageable bounce
+  char* stage = nullptr;
+  size_t stage_bytes = 0;
   uint32_t key0 = 0, key1 = 0;
   int64_t t_host = 1;
   int64_t mean_count = 0;       // samples in the posterior-mean running sum
@@ -342,12 +346,16 @@ bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask,
     HIPCHK(hipMemsetAsync(h->b.nact[1], 0, 4 * (size_t)h->L.Npad, h->st));
   }
   HIPCHK(launch_omega(g, h->b, h->st));
-  DevScalars s;
-  std::vector<int32_t> bin_start((size_t)g.P + 1);   // first slot of each |Obs| value
-  HIPCHK(hipMemcpyAsync(&s, h->b.scal, sizeof s, hipMemcpyDeviceToHost, h->st));
-  HIPCHK(hipMemcpyAsync(bin_start.data(), h->b.sort_bin, 4 * ((size_t)g.P + 1),
-                        hipMemcpyDeviceToHost, h->st));
+  // (the synchronisation also retires the previous frame's table upload
+  // before its staging is rewritten)
+  DevScalars* sp = reinterpret_cast<DevScalars*>(h->stage);
+  int32_t* bin_start = reinterpret_cast<int32_t*>(h->stage + align_up(sizeof(DevScalars), 16));
+  int4* wave_stage = reinterpret_cast<int4*>(h->stage + align_up(sizeof(DevScalars), 16) +
+                                             align_up(4 * ((size_t)g.P + 1), 16));
+  HIPCHK(hipMemcpyAsync(sp, h->b.scal, sizeof(DevScalars), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipMemcpyAsync(bin_start, h->b.sort_bin, 4 * ((size_t)g.P + 1), hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
+  const DevScalars s = *sp;   // bin_start[c]: first slot of each |Obs| value c
   h->max_obs = s.max_obs;
   h->n_omega = s.n_omega;
   {
@@ -386,13 +394,17 @@ bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask,
   // consecutive slots of one lane count (sweep_lanes), 64 / lanes of them,
   // and its register count J covers its last (largest) slot
   {
+    // one pass: the |Obs| queries come in ascending slot order, so the bin is
+    // found by a pointer that only moves forward
+    int bin = 0;
     auto count_of = [&](int slot) {   // |Obs| of a slot: the bin whose range holds it
-      return (int)(std::upper_bound(bin_start.begin(), bin_start.end(), slot) - bin_start.begin()) - 1;
+      while (bin < g.P && bin_start[bin + 1] <= slot) ++bin;
+      return bin;
     };
     auto first_above = [&](int c) {   // first slot with |Obs| > c
       return c >= g.P ? g.N : bin_start[(size_t)c + 1];
     };
-    h->wave_host.clear();
+    long long n = 0;
     int slot = 0;
     while (slot < g.N) {
       const int lpp = sweep_lanes(count_of(slot));
@@ -402,15 +414,13 @@ bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask,
       int J = 16;
       if (lpp == 1) J = std::max(4, (clast + 1) & ~1);
       else if (lpp == 2 && clast <= 24) J = 12;
-      h->wave_host.push_back(make_int4(slot, end - slot, lpp, J));
+      if (n >= h->L.wave_cap)
+        return fail(BPFA_EDEVICE, "sweep wavefront table overflow (> %lld)", h->L.wave_cap);
+      wave_stage[n++] = make_int4(slot, end - slot, lpp, J);
       slot = end;
     }
-    if ((long long)h->wave_host.size() > h->L.wave_cap)
-      return fail(BPFA_EDEVICE, "sweep wavefront table overflow (%zu > %lld)", h->wave_host.size(),
-                  h->L.wave_cap);
-    h->n_waves = (int)h->wave_host.size();
-    HIPCHK(hipMemcpyAsync(h->b.sweep_waves, h->wave_host.data(), 16 * h->wave_host.size(),
-                          hipMemcpyHostToDevice, h->st));
+    h->n_waves = (int)n;
+    HIPCHK(hipMemcpyAsync(h->b.sweep_waves, wave_stage, 16 * (size_t)n, hipMemcpyHostToDevice, h->st));
   }
   if (h->timing) {
     if ((r = record(h, &ev[1])) != BPFA_OK) return r;
@@ -477,6 +487,10 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
       return bail(fail(BPFA_EDEVICE, "hipStreamCreate failed"));
     h->own_stream = true;
   }
+  h->stage_bytes = align_up(sizeof(DevScalars), 16) + align_up(4 * ((size_t)g.P + 1), 16) +
+                   16 * (size_t)h->L.wave_cap;
+  if (hipHostMalloc((void**)&h->stage, h->stage_bytes, hipHostMallocDefault) != hipSuccess)
+    return bail(fail(BPFA_ENOMEM, "hipHostMalloc of %zu staging bytes failed", h->stage_bytes));
   {
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, params->device) ==
@@ -948,6 +962,7 @@ void bpfa_destroy(bpfa_t h) {
   (void)collect_timing(h);
   if (h->own_ws && h->ws) (void)hipFree(h->ws);
   if (h->own_stream && h->st) (void)hipStreamDestroy(h->st);
+  if (h->stage) (void)hipHostFree(h->stage);
   delete h;
 }
 
