@@ -49,14 +49,17 @@ __global__ __launch_bounds__(256) void index_kernel(Geom g, const uint8_t* __res
   if (i < g.N) {
     const int org = patch_origin(g, i);
     for (int w = 0; w < g.PW; ++w) {
-      uint32_t word = 0;
+      // the word's 32 mask bytes are loaded together (a load-test loop waits
+      // out one memory latency per pixel); positions past P read pixel 0
       const int pe = min(32, g.P - 32 * w);
-      for (int b = 0; b < pe; ++b) {
-        if (mask[org + poff[32 * w + b]]) {
-          word |= 1u << b;
-          ++cnt;
-        }
-      }
+      uint8_t v[32];
+#pragma unroll
+      for (int b = 0; b < 32; ++b) v[b] = mask[org + poff[min(32 * w + b, g.P - 1)]];
+      uint32_t word = 0;
+#pragma unroll
+      for (int b = 0; b < 32; ++b)
+        if (b < pe && v[b]) word |= 1u << b;
+      cnt += __popc(word);
       bits[(size_t)i * g.PW + w] = word;
     }
     count[i] = cnt;
@@ -106,13 +109,28 @@ __global__ __launch_bounds__(256) void slots_kernel(Geom g, const float* __restr
     int j = 0;
     for (int w = 0; w < g.PW; ++w) {
       uint32_t word = bits[(size_t)i * g.PW + w];
+      // observed pixels in batches of 8 whose image loads issue together
+      // (an empty batch entry reads pixel 0 of the patch and is not stored)
       while (word) {
-        const int b = __builtin_ctz(word);
-        word &= word - 1;
-        const int p = 32 * w + b;
-        obs_idx[(size_t)j * Npad + s] = (uint16_t)p;
-        obs_val[(size_t)j * Npad + s] = image[org + poff[p]];
-        ++j;
+        int pb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          pb[u] = -1;
+          if (word) {
+            pb[u] = 32 * w + __builtin_ctz(word);
+            word &= word - 1;
+          }
+        }
+        float vb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) vb[u] = image[org + poff[max(pb[u], 0)]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (pb[u] >= 0) {
+            obs_idx[(size_t)j * Npad + s] = (uint16_t)pb[u];
+            obs_val[(size_t)j * Npad + s] = vb[u];
+            ++j;
+          }
       }
     }
   }
