@@ -31,7 +31,7 @@ PEAK_HBM = 8.0e12
 
 
 def sweep_ops_per_update(obs_per_patch):
-    """Algorithmic lane-op cost of one patch-atom update (see DESIGN.md).
+    """Algorithmic lane-op cost of one patch-atom update.
 
     Philox4x32-10, one block per two updates: 10 rounds x (2 wide products at
     4 + 2 three-way xors) = 100 -> 50.  Uniform transforms: 4.  Box-Muller per
@@ -286,7 +286,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(--gpus %d, WORLD_SIZE %d requested)" % (args.gpus, world), file=sys.stderr)
         sys.exit(2)
 

@@ -62,7 +62,7 @@ typedef enum { BPFA_HOST = 0, BPFA_DEVICE = 1 } bpfa_mem;
 enum {
   BPFA_LEARN_DICT = 1u,       /* sparse coding + dictionary learning (the default iteration) */
   BPFA_SPARSE_CODE_ONLY = 2u, /* keep D fixed; z, s, pi, gamma_s, gamma_eps are still drawn */
-  BPFA_PRECISION_BF16 = 4u    /* reserved for the BF16 precision form; rejected (EINVAL) */
+  BPFA_PRECISION_BF16 = 4u    /* reserved; rejected (EINVAL): the precision form is set by bpfa_set_precision */
 };
 
 /* contraction precision of a handle (bpfa_set_precision) */

@@ -617,7 +617,7 @@ bpfa_status bpfa_iterate(bpfa_t h, int32_t n_iters, uint32_t flags) {
   if ((flags & BPFA_LEARN_DICT) && (flags & BPFA_SPARSE_CODE_ONLY))
     return fail(BPFA_EINVAL, "LEARN_DICT and SPARSE_CODE_ONLY are exclusive");
   if (flags & BPFA_PRECISION_BF16)
-    return fail(BPFA_EINVAL, "the BF16 precision form is not available in this build");
+    return fail(BPFA_EINVAL, "the precision form is chosen with bpfa_set_precision, not an iterate flag");
   const int learn = (flags & BPFA_SPARSE_CODE_ONLY) ? 0 : 1;
   DeviceGuard dg(h->prm.device);
   const Geom& g = h->g;
