@@ -488,11 +488,14 @@ __device__ __forceinline__ void chain_run(const Geom& g, int p, int lane, const 
 #pragma unroll
           for (int mm = 0; mm < KPL; ++mm) ureg[mm] = fma(ring[u][mm], delta, ureg[mm]);
           if (lane == kl) dreg[m] = dn;
-          const int kn = min(k + PF, K - 1);
-#pragma unroll
-          for (int mm = 0; mm < KPL; ++mm)
-            ring[u][mm] = C[(size_t)kn * K + min(lane + kWave * mm, K - 1)];
         }
+        // the refill is issued on every step, taken or not, so each trip
+        // issues the same loads and a slot's wait counts only the loads
+        // issued after it, not every load in flight
+        const int kn = min(k + PF, K - 1);
+#pragma unroll
+        for (int mm = 0; mm < KPL; ++mm)
+          ring[u][mm] = C[(size_t)kn * K + min(lane + kWave * mm, K - 1)];
       }
     }
   }
