@@ -568,10 +568,23 @@ __global__ __launch_bounds__(1024) void dict_chain_lds_kernel(
   const int p = blockIdx.x, K = g.K, P = g.P, tid = threadIdx.x;
   const int E = K * (K + 1) / 2;
   const double* T = Ctri + (size_t)p * E;
-  for (int idx = tid; idx < K * K; idx += 1024) {
-    const int k = idx / K, j = idx - k * K;
-    const int a = min(k, j), b = max(k, j);
-    Cs[idx] = T[tri_off(a, K) + (b - a)];
+  // the symmetric expansion, 16 loads per thread in flight before their
+  // stores (a load-store loop waits out one memory latency per element)
+  constexpr int kExp = 16;
+  for (int base = 0; base < K * K; base += 1024 * kExp) {
+    double v[kExp];
+#pragma unroll
+    for (int u = 0; u < kExp; ++u) {
+      const int idx = min(base + tid + 1024 * u, K * K - 1);   // clamped: stays in the triangle
+      const int k = idx / K, j = idx - k * K;
+      const int a = min(k, j), b = max(k, j);
+      v[u] = T[tri_off(a, K) + (b - a)];
+    }
+#pragma unroll
+    for (int u = 0; u < kExp; ++u) {
+      const int idx = base + tid + 1024 * u;
+      if (idx < K * K) Cs[idx] = v[u];
+    }
   }
   for (int k = tid; k < K; k += 1024) {
     s_B[k] = Bvec[(size_t)p * K + k];
