@@ -1,0 +1,103 @@
+"""GPU parity on the degenerate and extreme inputs of the sampler.
+
+Each case runs the HIP library and the binary64 oracle on the same Philox
+streams in follow mode (as in the iteration parity tests) and compares the
+state after every iteration and the final reconstruction to the binary32
+bar.  Cases: a mask with no observed pixel (every patch empty: the
+dictionary is drawn from its prior, the noise precision from its prior
+updated by nothing), a sparse mask where many patches are empty, a fully
+observed mask at the largest supported |Obs(i)| (256), a single atom, a
+single patch covering the whole image, the largest supported dictionary
+(K = 1024), and the rejection of a patch with more than 256 observed pixels.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import bpfa as ob  # noqa: E402
+from oracle import patches  # noqa: E402
+from parity_util import FP32_TOL, assert_close, case, oracle_problem  # noqa: E402
+
+from paper_2311_15061_amd import bpfa  # noqa: E402
+from test_gpu_parity import gpu_problem, run_follow  # noqa: E402
+
+
+def _run(shape, patch, stride, K, rho, iters=3, mask=None, **hyper):
+    y, m, g = case(shape, patch, stride, K, rho, seed=K)
+    if mask is not None:
+        m = np.full(shape, mask, np.uint8)
+    prob, st, ties, errs = run_follow(y, m, patch, stride, K, 0x5150 + K, iters, **hyper)
+    xh = prob.reconstruct()
+    ref = ob.reconstruct(st, shape, patch, stride)
+    assert_close(xh, ref, FP32_TOL, "reconstruction")
+    stats = prob.stats()
+    prob.close()
+    return m, st, stats
+
+
+def test_empty_mask():
+    """No observed pixel: n_obs = 0, the statistics are empty, D and gamma_eps
+    come from their priors (gamma_eps with e = f = 1, so that its draw stays
+    away from binary64 underflow)."""
+    m, st, stats = _run((12, 12), (3, 3), (1, 1), 6, 0.3, mask=0, e=1.0, f=1.0)
+    assert stats["n_obs"] == 0 and stats["max_obs"] == 0
+    assert st.gamma_eps > 0
+
+
+def test_sparse_mask_with_many_empty_patches():
+    shape, patch = (30, 30), (3, 3)
+    m, st, stats = _run(shape, patch, (1, 1), 8, 0.1)
+    X, Mk = patches.extract(np.zeros(shape, np.float32), m, patch, (1, 1))
+    empty = int((Mk.sum(axis=1) == 0).sum())
+    assert empty > Mk.shape[0] // 5, empty
+
+
+def test_full_mask_at_the_largest_observed_count():
+    """16 x 16 patches of a fully observed image: |Obs(i)| = 256 for every patch."""
+    m, st, stats = _run((24, 24), (16, 16), (1, 1), 12, 1.0, mask=1)
+    assert stats["max_obs"] == 256 and stats["n_obs"] == 256 * 81
+
+
+def test_single_atom():
+    _run((16, 16), (3, 3), (1, 1), 1, 0.4)
+
+
+def test_single_patch_covering_the_image():
+    m, st, stats = _run((7, 9), (7, 9), (1, 1), 6, 0.5)
+    assert stats["N"] == 1
+
+
+def test_largest_dictionary():
+    """K = 1024, the largest the library takes (many statistics row groups,
+    two sweep tiles, 16 register groups in the dictionary chain)."""
+    _run((20, 20), (4, 4), (1, 1), 1024, 0.5, iters=2)
+
+
+def test_more_than_256_observed_pixels_is_rejected():
+    y, m, g = case((20, 20), (17, 17), (1, 1), 4, 1.0, seed=1)
+    m = np.ones((20, 20), np.uint8)
+    with pytest.raises(bpfa.BpfaError) as ei:
+        gpu_problem(y, m, (17, 17), (1, 1), 4, 1)
+    assert ei.value.status == bpfa.ESHAPE
+    # 16 x 16 of the same image is accepted
+    prob = gpu_problem(y, m, (16, 16), (1, 1), 4, 1)
+    prob.close()
+
+
+def test_empty_mask_with_the_vague_noise_prior_reports_underflow():
+    """With no observed pixel and the default Ga(1e-6, 1e-6) prior the
+    gamma_eps draw underflows to 0 in binary64 (the oracle's too); the library
+    flags it and the next synchronising call reports ENUMERIC."""
+    shape, patch, K, seed = (12, 12), (3, 3), 6, 0x77
+    y, m, g = case(shape, patch, (1, 1), K, 0.3, seed=K)
+    m = np.zeros(shape, np.uint8)
+    prm, X, Mk = oracle_problem(y, m, patch, (1, 1), K, seed)
+    st, _ = ob.iterate(prm, X, Mk, ob.init_state(prm, X.shape[0], X.shape[1]))
+    assert st.gamma_eps == 0.0
+    prob = gpu_problem(y, m, patch, (1, 1), K, seed)
+    prob.iterate(1)
+    with pytest.raises(bpfa.BpfaError) as ei:
+        prob.sync()
+    assert ei.value.status == bpfa.ENUMERIC
+    prob.close()

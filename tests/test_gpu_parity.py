@@ -143,7 +143,7 @@ def test_sparse_code_only_parity():
 
 
 @pytest.mark.parametrize("shape,patch,stride,K,rho", [
-    ((40, 36), (6, 5), (1, 1), 20, 0.2),          # ragged grid, odd K
+    ((40, 36), (6, 5), (1, 1), 21, 0.2),          # ragged grid, odd K
     ((30, 30), (10, 10), (1, 1), 200, 0.15),      # several LDS tiles, two statistics row groups
     ((20, 18, 8), (4, 4, 2), (1, 1, 2), 24, 0.25),  # 3-D video patches with a time stride
     ((10, 9, 6, 5), (3, 3, 2, 2), (1, 1, 2, 1), 12, 0.3),  # 4-D patches spanning two frames
