@@ -300,28 +300,67 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
       case 8: stats_pairs<16>(sr, kk, ww); break;
       default: break;
     }
-    // entries beyond the register stage (rare): pairs (a, b), a <= b, b >= kStatsCap
-    for (int b = kStatsCap; b < wmax; ++b) {
-      int2 eb = make_int2(-1, 0);
-      if (b < na) eb = L[b];
-      const bool inb = b < na;
-      const double wb = inb ? (double)__int_as_float(eb.y) : 0.0;
-      const bool inbr = inb && eb.x >= r0 && eb.x < r1;
-      atomicAdd((unsigned long long*)(inbr ? acc + E + (eb.x - r0) : sink),
-                to_fixed((inbr ? wb : 0.0) * ysb));
+    if (wmax > kStatsCap) {
+      // lists longer than the register stage.  (1) every later entry b, one
+      // at a time, with the first-stage entries a < kStatsCap
+      for (int b = kStatsCap; b < wmax; ++b) {
+        int2 eb = make_int2(-1, 0);
+        if (b < na) eb = L[b];
+        const bool inb = b < na;
+        const double wb = inb ? (double)__int_as_float(eb.y) : 0.0;
 #pragma unroll
-      for (int a = 0; a < kStatsCap; ++a) {
-        const bool ok = inb && kk[a] >= r0 && kk[a] < r1;
-        long long* pc = ok ? acc + (sr.row_off(kk[a]) + eb.x) : sink;
-        atomicAdd((unsigned long long*)pc, to_fixed(ok ? ww[a] * sc * wb : 0.0));
+        for (int a = 0; a < kStatsCap; ++a) {
+          const bool ok = inb && kk[a] >= r0 && kk[a] < r1;
+          long long* pc = ok ? acc + (sr.row_off(kk[a]) + eb.x) : sink;
+          atomicAdd((unsigned long long*)pc, to_fixed(ok ? ww[a] * sc * wb : 0.0));
+        }
       }
-      for (int a = kStatsCap; a <= b; ++a) {
-        int2 ea = make_int2(-1, 0);
-        if (a < na) ea = L[a];
-        const bool ok = inb && a < na && ea.x >= r0 && ea.x < r1;
-        long long* pc = ok ? acc + (sr.row_off(ea.x) + eb.x) : sink;
-        atomicAdd((unsigned long long*)pc,
-                  to_fixed(ok ? (double)__int_as_float(ea.y) * sc * wb : 0.0));
+      // (2) entries kStatsCap .. 2 kStatsCap - 1 replace the first stage in
+      // registers (loaded together; the bound is the wave's): their B
+      // entries and the pairs among them, by the same bodies
+      const int n2 = min(wmax, 2 * kStatsCap) - kStatsCap;
+#pragma unroll
+      for (int u = 0; u < kStatsCap; ++u) {
+        int2 e = make_int2(-1, 0);
+        if (u < n2) e = L[min(kStatsCap + u, K - 1)];
+        const bool in = kStatsCap + u < na;
+        kk[u] = in ? e.x : -1;
+        ww[u] = in ? (double)__int_as_float(e.y) : 0.0;
+      }
+      switch ((n2 + 1) >> 1) {
+        case 1: stats_pairs<2>(sr, kk, ww); break;
+        case 2: stats_pairs<4>(sr, kk, ww); break;
+        case 3: stats_pairs<6>(sr, kk, ww); break;
+        case 4: stats_pairs<8>(sr, kk, ww); break;
+        case 5: stats_pairs<10>(sr, kk, ww); break;
+        case 6: stats_pairs<12>(sr, kk, ww); break;
+        case 7: stats_pairs<14>(sr, kk, ww); break;
+        default: stats_pairs<16>(sr, kk, ww); break;
+      }
+      // (3) entries past both stages (rare): B entries, pairs with the second
+      // stage, and pairs among themselves from memory
+      for (int b = 2 * kStatsCap; b < wmax; ++b) {
+        int2 eb = make_int2(-1, 0);
+        if (b < na) eb = L[b];
+        const bool inb = b < na;
+        const double wb = inb ? (double)__int_as_float(eb.y) : 0.0;
+        const bool inbr = inb && eb.x >= r0 && eb.x < r1;
+        atomicAdd((unsigned long long*)(inbr ? acc + E + (eb.x - r0) : sink),
+                  to_fixed((inbr ? wb : 0.0) * ysb));
+#pragma unroll
+        for (int a = 0; a < kStatsCap; ++a) {
+          const bool ok = inb && kk[a] >= r0 && kk[a] < r1;
+          long long* pc = ok ? acc + (sr.row_off(kk[a]) + eb.x) : sink;
+          atomicAdd((unsigned long long*)pc, to_fixed(ok ? ww[a] * sc * wb : 0.0));
+        }
+        for (int a = 2 * kStatsCap; a <= b; ++a) {
+          int2 ea = make_int2(-1, 0);
+          if (a < na) ea = L[a];
+          const bool ok = inb && a < na && ea.x >= r0 && ea.x < r1;
+          long long* pc = ok ? acc + (sr.row_off(ea.x) + eb.x) : sink;
+          atomicAdd((unsigned long long*)pc,
+                    to_fixed(ok ? (double)__int_as_float(ea.y) * sc * wb : 0.0));
+        }
       }
     }
 #pragma unroll

@@ -101,3 +101,25 @@ def test_empty_mask_with_the_vague_noise_prior_reports_underflow():
         prob.sync()
     assert ei.value.status == bpfa.ENUMERIC
     prob.close()
+
+
+@pytest.mark.parametrize("ell,density", [(0.5, 0.6), (4.0, 0.8)])
+def test_long_active_lists(ell, density):
+    """Dense codes from an injected state (logit pi = ell): lists of 12-34
+    entries (0.5), or 33-40 (4.0), so the dictionary statistics take the
+    paths past their first (16) and second (32) register stage."""
+    shape, patch, K, seed = (24, 24), (6, 6), 40, 0x10C
+    y, m, g = case(shape, patch, (1, 1), K, 0.5, seed=K)
+    prm, X, Mk = oracle_problem(y, m, patch, (1, 1), K, seed)
+    st = ob.init_state(prm, X.shape[0], X.shape[1])
+    rng = np.random.default_rng(5)
+    Z = rng.random((X.shape[0], K)) < density
+    st.Z = Z
+    st.W = np.where(Z, rng.standard_normal(Z.shape) * 0.3, 0.0).astype(np.float32).astype(np.float64)
+    st.D = st.D.astype(np.float32).astype(np.float64)
+    st.ell = np.full(K, ell)
+    prob, st, ties, errs = run_follow(y, m, patch, (1, 1), K, seed, 2, state=st)
+    na = st.Z.sum(axis=1)
+    assert (na > 16).mean() > 0.5, (na.min(), na.max())
+    assert_close(prob.reconstruct(), ob.reconstruct(st, shape, patch, (1, 1)), FP32_TOL, "reconstruction")
+    prob.close()
