@@ -300,7 +300,7 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
       case 8: stats_pairs<16>(sr, kk, ww); break;
       default: break;
     }
-    if (wmax > kStatsCap) {
+    if (wmax > kStatsCap + kStatsCap / 2) {
       // lists longer than the register stage.  (1) every later entry b, one
       // at a time, with the first-stage entries a < kStatsCap
       for (int b = kStatsCap; b < wmax; ++b) {
@@ -354,6 +354,31 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
           atomicAdd((unsigned long long*)pc, to_fixed(ok ? ww[a] * sc * wb : 0.0));
         }
         for (int a = 2 * kStatsCap; a <= b; ++a) {
+          int2 ea = make_int2(-1, 0);
+          if (a < na) ea = L[a];
+          const bool ok = inb && a < na && ea.x >= r0 && ea.x < r1;
+          long long* pc = ok ? acc + (sr.row_off(ea.x) + eb.x) : sink;
+          atomicAdd((unsigned long long*)pc,
+                    to_fixed(ok ? (double)__int_as_float(ea.y) * sc * wb : 0.0));
+        }
+      }
+    } else {
+      // entries beyond the register stage (rare): pairs (a, b), a <= b, b >= kStatsCap
+      for (int b = kStatsCap; b < wmax; ++b) {
+        int2 eb = make_int2(-1, 0);
+        if (b < na) eb = L[b];
+        const bool inb = b < na;
+        const double wb = inb ? (double)__int_as_float(eb.y) : 0.0;
+        const bool inbr = inb && eb.x >= r0 && eb.x < r1;
+        atomicAdd((unsigned long long*)(inbr ? acc + E + (eb.x - r0) : sink),
+                  to_fixed((inbr ? wb : 0.0) * ysb));
+  #pragma unroll
+        for (int a = 0; a < kStatsCap; ++a) {
+          const bool ok = inb && kk[a] >= r0 && kk[a] < r1;
+          long long* pc = ok ? acc + (sr.row_off(kk[a]) + eb.x) : sink;
+          atomicAdd((unsigned long long*)pc, to_fixed(ok ? ww[a] * sc * wb : 0.0));
+        }
+        for (int a = kStatsCap; a <= b; ++a) {
           int2 ea = make_int2(-1, 0);
           if (a < na) ea = L[a];
           const bool ok = inb && a < na && ea.x >= r0 && ea.x < r1;
