@@ -95,12 +95,16 @@ struct StatsRow {
   __device__ __forceinline__ int row_off(int k) const { return (int)(tri_off(k, K) - e0) - k; }
 };
 
-template <int NB>
+// SKIP: with three or more row groups a row no lane of the wave holds in
+// this block's group (it adds only to the sinks) is skipped whole by a
+// uniform branch; with fewer groups the test costs more than it saves
+template <int NB, bool SKIP>
 __device__ __forceinline__ void stats_pairs(const StatsRow& sr, const int (&kk)[kStatsCap],
                                             const double (&ww)[kStatsCap]) {
 #pragma unroll
   for (int a = 0; a < NB; ++a) {
     const bool ina = kk[a] >= sr.r0 && kk[a] < sr.r1;   // kk = -1 past n_a
+    if (SKIP && __builtin_amdgcn_ballot_w64(ina) == 0) continue;
     const double wa = ina ? ww[a] : 0.0;
     atomicAdd((unsigned long long*)(ina ? sr.acc + sr.E + (kk[a] - sr.r0) : sr.sink),
               to_fixed(wa * sr.ysb));
@@ -144,6 +148,7 @@ hipError_t launch_visit_table(const Geom& g, const Buffers& b, int n_omega, hipS
 // LDS: rec int64 accumulators | 64 per-lane sinks | K + 1 int bin starts | chunk visits (patch
 // int32, y float, n_a uint16).  Visits are bucketed by n_a inside the block so
 // each wavefront's pair loop runs to a bound its lanes share.
+template <bool SKIP>
 __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
     Geom g, DictPlanDev pl, int nom, const int32_t* __restrict__ vpatch,
     const float* __restrict__ omega_y, const int2* __restrict__ list,
@@ -290,14 +295,14 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
     long long* const sink = acc + pl.rec_stride + lane;
     const StatsRow sr{acc, sink, r0, r1, e0, E, K, sc, ysb};
     switch ((min(wmax, kStatsCap) + 1) >> 1) {
-      case 1: stats_pairs<2>(sr, kk, ww); break;
-      case 2: stats_pairs<4>(sr, kk, ww); break;
-      case 3: stats_pairs<6>(sr, kk, ww); break;
-      case 4: stats_pairs<8>(sr, kk, ww); break;
-      case 5: stats_pairs<10>(sr, kk, ww); break;
-      case 6: stats_pairs<12>(sr, kk, ww); break;
-      case 7: stats_pairs<14>(sr, kk, ww); break;
-      case 8: stats_pairs<16>(sr, kk, ww); break;
+      case 1: stats_pairs<2, SKIP>(sr, kk, ww); break;
+      case 2: stats_pairs<4, SKIP>(sr, kk, ww); break;
+      case 3: stats_pairs<6, SKIP>(sr, kk, ww); break;
+      case 4: stats_pairs<8, SKIP>(sr, kk, ww); break;
+      case 5: stats_pairs<10, SKIP>(sr, kk, ww); break;
+      case 6: stats_pairs<12, SKIP>(sr, kk, ww); break;
+      case 7: stats_pairs<14, SKIP>(sr, kk, ww); break;
+      case 8: stats_pairs<16, SKIP>(sr, kk, ww); break;
       default: break;
     }
     if (wmax > kStatsCap + kStatsCap / 2) {
@@ -328,14 +333,14 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
         ww[u] = in ? (double)__int_as_float(e.y) : 0.0;
       }
       switch ((n2 + 1) >> 1) {
-        case 1: stats_pairs<2>(sr, kk, ww); break;
-        case 2: stats_pairs<4>(sr, kk, ww); break;
-        case 3: stats_pairs<6>(sr, kk, ww); break;
-        case 4: stats_pairs<8>(sr, kk, ww); break;
-        case 5: stats_pairs<10>(sr, kk, ww); break;
-        case 6: stats_pairs<12>(sr, kk, ww); break;
-        case 7: stats_pairs<14>(sr, kk, ww); break;
-        default: stats_pairs<16>(sr, kk, ww); break;
+        case 1: stats_pairs<2, SKIP>(sr, kk, ww); break;
+        case 2: stats_pairs<4, SKIP>(sr, kk, ww); break;
+        case 3: stats_pairs<6, SKIP>(sr, kk, ww); break;
+        case 4: stats_pairs<8, SKIP>(sr, kk, ww); break;
+        case 5: stats_pairs<10, SKIP>(sr, kk, ww); break;
+        case 6: stats_pairs<12, SKIP>(sr, kk, ww); break;
+        case 7: stats_pairs<14, SKIP>(sr, kk, ww); break;
+        default: stats_pairs<16, SKIP>(sr, kk, ww); break;
       }
       // (3) entries past both stages (rare): B entries, pairs with the second
       // stage, and pairs among themselves from memory
@@ -705,12 +710,17 @@ hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& pl
   const int blocks = g.P * plan.RG * plan.chunks;
   // the LDS holds visit records for the largest chunk the plan allows
   const size_t lds = dict_stats_lds(g.K, d.rec_stride, plan.chunk_visits);
-  hipError_t e = hipFuncSetAttribute((const void*)dict_stats_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const bool skip = plan.RG >= 3;
+  hipError_t e = hipFuncSetAttribute(
+      skip ? (const void*)dict_stats_kernel<true> : (const void*)dict_stats_kernel<false>,
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  dict_stats_kernel<<<blocks, kDictBlock, lds, st>>>(g, d, n_omega, b.vpatch, b.omega_y,
-                                                     b.list[cur], b.nact[cur], b.scal, b.dpart,
-                                                     b.dx2);
+  if (skip)
+    dict_stats_kernel<true><<<blocks, kDictBlock, lds, st>>>(
+        g, d, n_omega, b.vpatch, b.omega_y, b.list[cur], b.nact[cur], b.scal, b.dpart, b.dx2);
+  else
+    dict_stats_kernel<false><<<blocks, kDictBlock, lds, st>>>(
+        g, d, n_omega, b.vpatch, b.omega_y, b.list[cur], b.nact[cur], b.scal, b.dpart, b.dx2);
   return hipGetLastError();
 }
 
