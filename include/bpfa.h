@@ -51,7 +51,7 @@ typedef enum {
                          transfer between different P or K */
   BPFA_ENOMEM = -3,   /* workspace too small, or a device allocation failed */
   BPFA_EDEVICE = -4,  /* a HIP runtime call failed (message has the HIP error) */
-  BPFA_ESTATE = -5,   /* a state view does not match the handle */
+  BPFA_ESTATE = -5,   /* a state view does not match the handle, or no valid frame */
   BPFA_ENUMERIC = -6, /* non-finite gamma / residual sum, or a gamma draw that did not accept */
   BPFA_EBUSY = -7     /* reserved */
 } bpfa_status;
@@ -131,14 +131,20 @@ bpfa_status bpfa_workspace_size(const bpfa_params* params, size_t* bytes);
  * The state is initialised from the prior: d_kp = n / sqrt(P) (Philox INIT
  * stream), no active atoms, logit pi_k = ln(a / (b (K-1))), gamma_s0,
  * gamma_eps0, t = 1.  Index construction (masked patch extraction) runs on
- * the stream.  ESHAPE for a bad geometry or an uncovered pixel, ENOMEM for a
- * short workspace, EDEVICE on a HIP failure. */
+ * the stream.  ESHAPE for a bad geometry, an uncovered pixel or a patch with
+ * more than 256 observed pixels, ENOMEM for a short workspace, EDEVICE on a
+ * HIP failure.  A mask with no observed pixel is accepted: the dictionary
+ * statistics are then empty and D and gamma_eps are drawn from their priors
+ * (under a vague gamma_eps prior that draw can underflow to 0 in binary64,
+ * which the next synchronising call reports as ENUMERIC). */
 bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_bytes,
                         const float* image, const uint8_t* mask, bpfa_mem mem, bpfa_t* out);
 
 /* Replace the frame (image and mask of the same shape) and rebuild the patch
  * index.  reset_codes != 0 clears W and Z (D, pi and the gammas are kept:
- * the live-feed use of the feature summary); 0 keeps the codes. */
+ * the live-feed use of the feature summary); 0 keeps the codes.  ESHAPE for a
+ * patch with more than 256 observed pixels; after a failed frame load
+ * bpfa_iterate returns ESTATE until a frame loads. */
 bpfa_status bpfa_set_frame(bpfa_t h, const float* image, const uint8_t* mask, bpfa_mem mem,
                            int reset_codes);
 
@@ -153,7 +159,8 @@ bpfa_status bpfa_reset_state(bpfa_t h);
  * dictionary update (atoms in ascending order), pi_k, gamma_s, gamma_eps.
  * Asynchronous on the handle's stream; a numeric failure is reported by the
  * next synchronising call (bpfa_sync, bpfa_get_state, bpfa_get_stats,
- * bpfa_reconstruct to host).  EINVAL for n_iters < 0 or unknown flags. */
+ * bpfa_reconstruct to host).  EINVAL for n_iters < 0 or unknown flags;
+ * ESTATE when the last frame load failed. */
 bpfa_status bpfa_iterate(bpfa_t h, int32_t n_iters, uint32_t flags);
 
 /* Overlap-averaged reconstruction from the current sample: every pixel is the

@@ -255,6 +255,7 @@ struct bpfa_problem {
   uint32_t key0 = 0, key1 = 0;
   int64_t t_host = 1;
   int64_t mean_count = 0;       // samples in the posterior-mean running sum
+  bool frame_ok = false;        // the last frame load completed (the index is whole)
   // timing
   bool timing = false;
   std::vector<std::array<hipEvent_t, 4>> iter_events;
@@ -333,6 +334,7 @@ bpfa_status check_status(bpfa_problem* h) {
 bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask, bpfa_mem mem,
                        bool keep_codes) {
   const Geom& g = h->g;
+  h->frame_ok = false;   // until every table of the new frame is built
   bpfa_status r = upload(h, h->b.image, image, 4 * (size_t)g.Mtot, mem);
   if (r != BPFA_OK) return r;
   r = upload(h, h->b.mask, mask, (size_t)g.Mtot, mem);
@@ -426,6 +428,7 @@ bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask,
     if ((r = record(h, &ev[1])) != BPFA_OK) return r;
     h->index_events.push_back(ev);
   }
+  h->frame_ok = true;
   return BPFA_OK;
 }
 
@@ -618,6 +621,8 @@ bpfa_status bpfa_iterate(bpfa_t h, int32_t n_iters, uint32_t flags) {
     return fail(BPFA_EINVAL, "LEARN_DICT and SPARSE_CODE_ONLY are exclusive");
   if (flags & BPFA_PRECISION_BF16)
     return fail(BPFA_EINVAL, "the precision form is chosen with bpfa_set_precision, not an iterate flag");
+  if (!h->frame_ok)
+    return fail(BPFA_ESTATE, "the last frame load failed; set a valid frame before iterating");
   const int learn = (flags & BPFA_SPARSE_CODE_ONLY) ? 0 : 1;
   DeviceGuard dg(h->prm.device);
   const Geom& g = h->g;

@@ -123,3 +123,22 @@ def test_long_active_lists(ell, density):
     assert (na > 16).mean() > 0.5, (na.min(), na.max())
     assert_close(prob.reconstruct(), ob.reconstruct(st, shape, patch, (1, 1)), FP32_TOL, "reconstruction")
     prob.close()
+
+
+def test_failed_frame_load_blocks_iteration():
+    """A frame with a patch of more than 256 observed pixels is refused by
+    set_frame (ESHAPE); iterate then returns ESTATE until a valid frame loads."""
+    y, m, g = case((20, 20), (17, 17), (1, 1), 4, 0.5, seed=2)
+    prob = gpu_problem(y, m, (17, 17), (1, 1), 4, 1)
+    prob.iterate(1)
+    prob.sync()
+    with pytest.raises(bpfa.BpfaError) as ei:
+        prob.set_frame(y, np.ones((20, 20), np.uint8))
+    assert ei.value.status == bpfa.ESHAPE
+    with pytest.raises(bpfa.BpfaError) as ei:
+        prob.iterate(1)
+    assert ei.value.status == bpfa.ESTATE
+    prob.set_frame(y, m)
+    prob.iterate(1)
+    prob.sync()
+    prob.close()
