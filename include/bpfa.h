@@ -192,14 +192,16 @@ bpfa_status bpfa_mean_get(bpfa_t h, float* out, bpfa_mem mem, int64_t* count);
  * output convention as bpfa_mean_get; ESTATE with fewer than two samples. */
 bpfa_status bpfa_variance_get(bpfa_t h, float* out, bpfa_mem mem, int64_t* count);
 
-/* Precision form of the reconstruction's dense contraction y_i = D^T w_i
- * (every patch's model, before the overlap average).  BPFA_FP32 (default):
- * binary32 products and sums on the matrix cores.  BPFA_BF16: every operand
- * is split into a BF16 head and a BF16 tail; the head product runs on the
- * BF16 matrix cores with binary32 accumulation and one correction pass adds
- * the head-tail cross products, so the error stays near 2^-16 of |d||w|.
- * The sampler (z, s, D, pi, gammas) is binary32 / binary64 in both forms.
- * Takes effect at the next bpfa_reconstruct.  EINVAL for another value. */
+/* Precision form of the reconstruction's contraction y_i = D^T w_i (every
+ * patch's model, before the overlap average).  BPFA_FP32 (default): binary32
+ * products and sums on the vector ALUs over each patch's active atoms only
+ * (the sparse form).  BPFA_BF16: the dense contraction on the BF16 matrix
+ * cores; every operand is split into a BF16 head and a BF16 tail, the head
+ * product accumulates in binary32 and one correction pass adds the head-tail
+ * cross products, so the error stays near 2^-16 of |d||w|.  The sampler (z,
+ * s, D, pi, gammas) is binary32 / binary64 in both forms.  Takes effect at
+ * the next bpfa_reconstruct.  EINVAL for another value; ESHAPE for BPFA_BF16
+ * when P > 256 (the matrix-core tiles hold at most 256 patch pixels). */
 bpfa_status bpfa_set_precision(bpfa_t h, uint32_t precision);
 
 /* Dictionary transfer between sources (feature summary): copy D (and, as

@@ -50,10 +50,12 @@ typedef struct {
 
 /* Defaults: 2-D 10 x 10 patches stride 1, K = 128, priors as bpfa_params_default,
  * 4 streams, 5 sparse-coding iterations, dictionary every 10 frames, 4 slots,
- * 16 GiB budget, device 0, BF16 precision form. */
+ * 16 GiB budget, device 0, binary32 reconstruction (BPFA_FP32; the BF16 form
+ * is selectable and is slower on these sparse codes). */
 void bpfa_server_params_default(bpfa_server_params* p);
 
-/* Start a server.  EINVAL / ESHAPE for bad parameters, EDEVICE on HIP errors. */
+/* Start a server.  EINVAL / ESHAPE for bad parameters (ESHAPE also for
+ * BPFA_BF16 with patches of more than 256 pixels), EDEVICE on HIP errors. */
 bpfa_status bpfa_server_create(const bpfa_server_params* p, bpfa_server_t* out);
 
 /* Dictionary transfer (feature summary) into stream `stream`: copies D,
@@ -72,6 +74,10 @@ bpfa_status bpfa_server_submit(bpfa_server_t s, int32_t stream, const int64_t* s
                                const float* image, const uint8_t* mask, float* out,
                                uint64_t* ticket);
 
+/* A frame that fails (status != BPFA_OK, e.g. ENUMERIC when one of its
+ * draws failed) leaves its stream's dictionary state and iteration counter
+ * as the last successful frame left them: the next frame of the stream
+ * starts from there. */
 typedef struct {
   uint64_t ticket;
   int32_t stream;

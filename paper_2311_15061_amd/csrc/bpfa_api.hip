@@ -755,6 +755,8 @@ bpfa_status bpfa_variance_get(bpfa_t h, float* out, bpfa_mem mem, int64_t* count
 bpfa_status bpfa_set_precision(bpfa_t h, uint32_t precision) {
   if (!h) return fail(BPFA_EINVAL, "NULL handle");
   if (precision != BPFA_FP32 && precision != BPFA_BF16) return fail(BPFA_EINVAL, "unknown precision");
+  if (precision == BPFA_BF16 && h->g.P > 256)
+    return fail(BPFA_ESHAPE, "the BF16 form takes patches of at most 256 pixels (P = %d)", h->g.P);
   h->precision = (int)precision;
   return BPFA_OK;
 }

@@ -49,6 +49,7 @@ struct Frame {
 struct Slot {
   std::vector<int64_t> shape;
   bpfa_t h = nullptr;
+  void* staging = nullptr;    // device blob the frame's state is saved into before it is known good
   size_t bytes = 0;
   bool busy = false;
   bool stop = false;
@@ -127,7 +128,10 @@ void finish(bpfa_server* s, Frame* f, int status, bool learned) {
   delete f;
 }
 
-// one frame on a slot (called by the slot's worker without the server lock)
+// one frame on a slot (called by the slot's worker without the server lock).
+// The updated state goes to the slot's staging blob; the caller swaps it in as
+// the stream's state only when the frame succeeded, so a frame whose draws
+// failed (ENUMERIC) leaves the stream at its last good state and iteration.
 int run_frame(bpfa_server* s, Slot* sl, Frame* f, StreamState* ss) {
   const bpfa_server_params& p = s->prm;
   bpfa_t h = sl->h;
@@ -138,9 +142,11 @@ int run_frame(bpfa_server* s, Slot* sl, Frame* f, StreamState* ss) {
   st = bpfa_iterate(h, p.sc_iters, BPFA_SPARSE_CODE_ONLY);
   if (st == BPFA_OK && f->learn) st = bpfa_iterate(h, 1, BPFA_LEARN_DICT);
   if (st != BPFA_OK) return st;
-  st = bpfa::problem_export_dict(h, ss->blob);
+  st = bpfa::problem_export_dict(h, sl->staging);
   if (st != BPFA_OK) return st;
-  return bpfa_reconstruct(h, f->out, BPFA_HOST);   // synchronises the slot's stream
+  // synchronises the slot's stream and reports a numeric failure of any
+  // iteration of this frame
+  return bpfa_reconstruct(h, f->out, BPFA_HOST);
 }
 
 void worker_loop(bpfa_server* s, Slot* sl) {
@@ -155,6 +161,7 @@ void worker_loop(bpfa_server* s, Slot* sl) {
     lk.lock();
     const bool learned = f->learn;
     if (st == BPFA_OK) {
+      std::swap(ss->blob, sl->staging);   // the frame's state becomes the stream's
       ss->t = f->t0 + s->prm.sc_iters + (learned ? 1 : 0);
     }
     ss->busy = false;
@@ -170,6 +177,7 @@ void worker_loop(bpfa_server* s, Slot* sl) {
 void destroy_slot(Slot* sl) {
   if (sl->worker.joinable()) sl->worker.join();
   if (sl->h) bpfa_destroy(sl->h);
+  if (sl->staging) (void)hipFree(sl->staging);
   delete sl;
 }
 
@@ -182,6 +190,21 @@ Slot* acquire_slot(bpfa_server* s, const std::vector<int64_t>& shape, size_t nee
   if (*fail_status != BPFA_OK) return nullptr;
   for (Slot* sl : s->slots)
     if (!sl->busy && sl->shape == shape) return sl;
+  // evict only when that makes room: the idle slots of other shapes together
+  // must free enough bytes and slot count, or nothing is evicted and the frame
+  // waits (the dispatcher then tries other streams' frames)
+  {
+    int64_t idle_bytes = 0;
+    int idle_n = 0;
+    for (Slot* x : s->slots)
+      if (!x->busy && x->shape != shape) {
+        idle_bytes += (int64_t)x->bytes;
+        ++idle_n;
+      }
+    if ((uint64_t)(s->slot_bytes - idle_bytes) + need > s->prm.hbm_budget ||
+        (int)s->slots.size() - idle_n >= s->prm.max_slots)
+      return nullptr;
+  }
   // make room: evict idle slots of other shapes until the new one fits
   while ((uint64_t)s->slot_bytes + need > s->prm.hbm_budget ||
          (int)s->slots.size() >= s->prm.max_slots) {
@@ -214,8 +237,13 @@ Slot* acquire_slot(bpfa_server* s, const std::vector<int64_t>& shape, size_t nee
   std::vector<float> zimg((size_t)px, 0.f);
   std::vector<uint8_t> zmask((size_t)px, 0);
   bpfa_t h = nullptr;
+  void* staging = nullptr;
   int st = bpfa_create(&fp, nullptr, 0, zimg.data(), zmask.data(), BPFA_HOST, &h);
   if (st == BPFA_OK) st = bpfa_set_precision(h, (uint32_t)s->prm.precision);
+  if (st == BPFA_OK && hipMalloc(&staging, bpfa::dict_blob_bytes(s->K, s->P)) != hipSuccess) {
+    staging = nullptr;
+    st = BPFA_ENOMEM;
+  }
   if (st != BPFA_OK && h) {
     bpfa_destroy(h);
     h = nullptr;
@@ -229,6 +257,7 @@ Slot* acquire_slot(bpfa_server* s, const std::vector<int64_t>& shape, size_t nee
     return nullptr;
   }
   sl->h = h;
+  sl->staging = staging;
   sl->busy = false;
   sl->worker = std::thread(worker_loop, s, sl);
   return sl;
@@ -240,27 +269,39 @@ void dispatcher_loop(bpfa_server* s) {
     bool progress = true;
     while (progress) {
       progress = false;
-      // oldest head-of-stream frame first
-      Frame* best = nullptr;
+      // head-of-stream frames of idle streams, oldest first; a frame that
+      // must wait for a slot does not hold back the younger ones behind it
+      std::vector<Frame*> heads;
       for (auto& ss : s->streams)
-        if (!ss.busy && !ss.fifo.empty() && (!best || ss.fifo.front()->ticket < best->ticket))
-          best = ss.fifo.front();
-      if (!best) break;
-      StreamState& ss = s->streams[best->stream];
-      bpfa_params fp = frame_params(s->prm, best->shape);
-      size_t need = 0;
-      if (bpfa_workspace_size(&fp, &need) != BPFA_OK) need = (size_t)-1;
-      int fail_status = BPFA_OK;
-      Slot* sl = acquire_slot(s, best->shape, need, lk, &fail_status);
-      if (fail_status != BPFA_OK) {
-        ss.fifo.pop_front();
-        --s->queued;
-        finish(s, best, fail_status, false);
-        s->cv_done.notify_all();
-        progress = true;
-        continue;
+        if (!ss.busy && !ss.fifo.empty()) heads.push_back(ss.fifo.front());
+      std::sort(heads.begin(), heads.end(),
+                [](const Frame* a, const Frame* b) { return a->ticket < b->ticket; });
+      Frame* best = nullptr;
+      Slot* sl = nullptr;
+      for (Frame* cand : heads) {
+        bpfa_params fp = frame_params(s->prm, cand->shape);
+        size_t need = 0;
+        if (bpfa_workspace_size(&fp, &need) != BPFA_OK) need = (size_t)-1;
+        int fail_status = BPFA_OK;
+        Slot* got = acquire_slot(s, cand->shape, need, lk, &fail_status);
+        if (fail_status != BPFA_OK) {
+          StreamState& fs = s->streams[cand->stream];
+          fs.fifo.pop_front();
+          --s->queued;
+          finish(s, cand, fail_status, false);
+          s->cv_done.notify_all();
+          progress = true;
+          break;   // the lock may have been released: rescan
+        }
+        if (got) {
+          best = cand;
+          sl = got;
+          break;
+        }
       }
-      if (!sl) break;   // wait for a slot
+      if (progress) continue;
+      if (!best) break;   // every candidate waits for a slot
+      StreamState& ss = s->streams[best->stream];
       ss.fifo.pop_front();
       --s->queued;
       ss.busy = true;
@@ -307,7 +348,7 @@ void bpfa_server_params_default(bpfa_server_params* p) {
   p->dict_every = 10;
   p->max_slots = 4;
   p->hbm_budget = 16ull << 30;
-  p->precision = BPFA_BF16;
+  p->precision = BPFA_FP32;
 }
 
 bpfa_status bpfa_server_create(const bpfa_server_params* p, bpfa_server_t* out) {
@@ -317,6 +358,11 @@ bpfa_status bpfa_server_create(const bpfa_server_params* p, bpfa_server_t* out) 
       p->max_slots < 1 || p->hbm_budget == 0 ||
       (p->precision != BPFA_FP32 && p->precision != BPFA_BF16))
     return BPFA_EINVAL;
+  {
+    int64_t P = 1;
+    for (int d = 0; d < p->ndim && d < 4; ++d) P *= p->patch[d];
+    if (p->precision == BPFA_BF16 && P > 256) return BPFA_ESHAPE;   // matrix-core tiles hold 256 pixels
+  }
   // validate the patch geometry and priors on the smallest frame that holds one patch
   std::vector<int64_t> probe(4, 1);
   for (int d = 0; d < p->ndim && d < 4; ++d) probe[d] = p->patch[d];

@@ -68,7 +68,7 @@ class Server:
     """Live-feed server: per-stream dictionaries resident on the GPU, frames of any size."""
 
     def __init__(self, patch=(10, 10), stride=None, K=128, n_streams=4, sc_iters=5, dict_every=10,
-                 max_slots=4, hbm_budget=16 << 30, seed=0, device=0, precision="bf16", **hyper):
+                 max_slots=4, hbm_budget=16 << 30, seed=0, device=0, precision="fp32", **hyper):
         p = ServerParams()
         lib.bpfa_server_params_default(ctypes.byref(p))
         p.ndim = len(patch)

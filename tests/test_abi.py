@@ -108,3 +108,18 @@ def test_bad_ndim_and_null_pointers(bpfa):
     assert bpfa.lib.bpfa_sync(None) == bpfa.EINVAL
     assert bpfa.lib.bpfa_set_precision(None, bpfa.BF16) == bpfa.EINVAL
     bpfa.lib.bpfa_destroy(None)
+
+
+def test_server_rejects_bf16_for_patches_over_256_pixels(bpfa):
+    """The BF16 reconstruction's matrix-core tiles hold at most 256 patch pixels;
+    a server asking for it with 17 x 17 patches is refused before any device work."""
+    import ctypes as ct
+    from paper_2311_15061_amd import serve
+    p = serve.ServerParams()
+    serve.lib.bpfa_server_params_default(ct.byref(p))
+    assert p.precision == bpfa.FP32
+    p.patch[0], p.patch[1] = 17, 17
+    p.precision = bpfa.BF16
+    h = ct.c_void_p()
+    assert serve.lib.bpfa_server_create(ct.byref(p), ct.byref(h)) == bpfa.ESHAPE
+    assert not h.value

@@ -1,8 +1,8 @@
 """GPU parity of the reconstruction's contraction in both precision forms.
 
-The patch models y_i = D^T w_i run on the matrix cores: binary32 products
-(BPFA_FP32) or BF16 head products plus one binary32 correction pass
-(BPFA_BF16).  States are injected (binary32-representable D and W), so the
+The patch models y_i = D^T w_i run either in binary32 on the vector ALUs
+over each patch's active atoms (BPFA_FP32), or densely on the BF16 matrix
+cores as head products plus one binary32 correction pass (BPFA_BF16).  States are injected (binary32-representable D and W), so the
 oracle's binary64 overlap average of the same state is the reference:
 
 * FP32 form: within 1e-6 (binary32 rounding of short sums).
@@ -106,4 +106,20 @@ def test_bf16_trajectory_and_psnr_lattice64():
     print("bf16 reconstruction: error vs binary64 %.3e, PSNR %.4f dB vs oracle %.4f dB"
           % (e, p_gpu, p_ref), flush=True)
     assert abs(p_gpu - p_ref) <= 0.1
+    prob.close()
+
+
+def test_bf16_rejected_for_patches_over_256_pixels():
+    """The matrix-core tiles hold at most 256 patch pixels: asking a handle with
+    17 x 17 patches for the BF16 form fails at once (ESHAPE), and the handle
+    keeps reconstructing in binary32."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    img = rng.random((24, 24)).astype(np.float32)
+    mask = (rng.random((24, 24)) < 0.3).astype(np.uint8)
+    prob = bpfa.Problem(img, mask, (17, 17), K=8, seed=3)
+    with pytest.raises(bpfa.BpfaError) as ei:
+        prob.set_precision("bf16")
+    assert ei.value.status == bpfa.ESHAPE
+    prob.iterate(1)
+    assert np.all(np.isfinite(prob.reconstruct()))
     prob.close()

@@ -160,3 +160,22 @@ def test_admission_by_hbm_budget():
     assert stats["completed"] == 4 and stats["failed"] == 0
     assert stats["peak_slot_bytes"] <= budget
     assert stats["slot_evictions"] >= 1
+
+
+def test_failed_frame_leaves_stream_state():
+    """A frame whose noise-precision draw underflows (no observed pixel under the
+    vague Ga(1e-6, 1e-6) prior: ENUMERIC) is reported failed and leaves its
+    stream's dictionary state and Philox iteration counter untouched: the next
+    frame equals a direct run that skips the failed frame."""
+    good = frames_for(3, 2)
+    side = good[0][0].shape[0]
+    empty = (good[0][0], np.zeros((side, side), np.uint8))
+    seq = [good[0], empty, good[1]]
+    outs, stats = run_server({3: seq}, n_streams=4, dict_every=0, precision="fp32")
+    assert outs[(3, 0)][0] == bpfa.OK
+    assert outs[(3, 1)][0] == bpfa.ENUMERIC
+    assert outs[(3, 2)][0] == bpfa.OK
+    assert stats["failed"] == 1 and stats["completed"] == 2
+    ref = direct_sequence(good, stream=3, dict_every=0, precision="fp32")
+    assert np.array_equal(outs[(3, 0)][1], ref[0])
+    assert np.array_equal(outs[(3, 2)][1], ref[1]), "frame after the failure"
