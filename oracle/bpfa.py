@@ -25,6 +25,16 @@ One iteration, in this order:
   3. pi_k from its Beta conditional, as ell_k = ln G_A - ln G_B;
   4. gamma_s; 5. gamma_eps (residual after step 2); 6. t <- t + 1.
 
+Mini-batch epochs (the Time-to-solution section trains for "complete
+epochs"; the paper gives no schedule, so this is a reading): the patches are
+dealt into B batches, patch i to batch i mod B; an epoch takes the batches in
+ascending order, and each batch step is one iteration of steps 1-6 in which
+the sweep visits only that batch's patches and the global draws (2-5) use
+the batch's statistics scaled by s = N / n_b, i.e. the conditionals given a
+data set made of s copies of the batch.  Every batch step is an iteration
+number of its own (t advances per step), so each step draws fresh numbers.
+With B = 1 a batch step is exactly the full iteration.
+
 Random numbers come from oracle.philox under the stream contract described
 there; a GPU implementation that follows the same contract draws the same
 uniforms, so the two can be compared draw by draw.
@@ -210,14 +220,15 @@ def sweep(params, X, Mk, st, follow_z=None, tie_tol=1e-4, patch_ids=None):
     return W, Z, R, rep
 
 
-def dictionary_update(params, Mk, st, W, R, positions=None, prior_P=None):
+def dictionary_update(params, Mk, st, W, R, positions=None, prior_P=None, scale=1.0):
     """Step 2: atoms in order; every position p of d_k from its conditional.
 
     R is the residual of the current dictionary and W; both the returned D and
     the residual reflect the new atoms.  Positions are independent given W, so
     the columns of a subset of positions can be updated on their own: pass the
     column subsets of Mk, R and st.D, their position indices and the full
-    patch dimension P (the prior precision).
+    patch dimension P (the prior precision).  scale multiplies the data
+    statistics A and b (a mini-batch step's N / n_b); the prior is not scaled.
     """
     K, P = st.D.shape
     D = st.D.copy()
@@ -230,8 +241,8 @@ def dictionary_update(params, Mk, st, W, R, positions=None, prior_P=None):
         w = W[:, k]
         rows = np.nonzero(w)[0]
         mw = Mf[rows] * w[rows, None]                       # m_ip w_ik
-        A = (mw * w[rows, None]).sum(axis=0)
-        b = (mw * (R[rows] + D[k][None, :] * w[rows, None])).sum(axis=0)
+        A = scale * (mw * w[rows, None]).sum(axis=0)
+        b = scale * (mw * (R[rows] + D[k][None, :] * w[rows, None])).sum(axis=0)
         mean, lam = dict_conditional(P, ge, A, b)
         d_new = mean + dict_normal(params, pp, k, st.t) / np.sqrt(lam)
         R[rows] -= mw * (d_new - D[k])[None, :]
@@ -239,32 +250,37 @@ def dictionary_update(params, Mk, st, W, R, positions=None, prior_P=None):
     return D, R
 
 
-def pi_update(params, Z, t):
-    """Step 3: pi_k | Z ~ Beta(a/K + n_k, b(K-1)/K + N - n_k), kept as its logit."""
+def pi_update(params, Z, t, scale=1.0):
+    """Step 3: pi_k | Z ~ Beta(a/K + n_k, b(K-1)/K + N - n_k), kept as its logit.
+
+    With scale s (a mini-batch step over the N rows of Z) the counts are
+    s n_k and s N: the Beta conditional given s copies of the batch."""
     N, K = Z.shape
     nk = Z.sum(axis=0)
     ell = np.empty(K)
     for k in range(K):
-        la = _gamma.log_gamma_draw(params.a / K + nk[k], params.seed, params.problem_id,
+        la = _gamma.log_gamma_draw(params.a / K + scale * nk[k], params.seed, params.problem_id,
                                    philox.TAG_PI_A, k, t)
-        lb = _gamma.log_gamma_draw(params.b * (K - 1) / K + N - nk[k], params.seed,
+        lb = _gamma.log_gamma_draw(params.b * (K - 1) / K + scale * N - scale * nk[k], params.seed,
                                    params.problem_id, philox.TAG_PI_B, k, t)
         ell[k] = la - lb
     return ell
 
 
-def gamma_s_update(params, Z, W, t):
-    """Step 4: gamma_s ~ Ga(c + sum(z)/2, d + sum(w^2)/2) over active weights."""
-    shape = params.c + 0.5 * float(Z.sum())
-    rate = params.d + 0.5 * float((W * W).sum())
+def gamma_s_update(params, Z, W, t, scale=1.0):
+    """Step 4: gamma_s ~ Ga(c + sum(z)/2, d + sum(w^2)/2) over active weights
+    (both sums multiplied by scale in a mini-batch step)."""
+    shape = params.c + 0.5 * (scale * float(Z.sum()))
+    rate = params.d + 0.5 * (scale * float((W * W).sum()))
     lg = _gamma.log_gamma_draw(shape, params.seed, params.problem_id, philox.TAG_GS, 0, t)
     return math.exp(lg) / rate
 
 
-def gamma_eps_update(params, Mk, R, t):
-    """Step 5: gamma_eps ~ Ga(e + |Obs|/2, f + sum_{Obs} r^2 / 2)."""
-    shape = params.e + 0.5 * float(Mk.sum())
-    rate = params.f + 0.5 * float((R * R).sum())
+def gamma_eps_update(params, Mk, R, t, scale=1.0):
+    """Step 5: gamma_eps ~ Ga(e + |Obs|/2, f + sum_{Obs} r^2 / 2) (both sums
+    multiplied by scale in a mini-batch step)."""
+    shape = params.e + 0.5 * (scale * float(Mk.sum()))
+    rate = params.f + 0.5 * (scale * float((R * R).sum()))
     lg = _gamma.log_gamma_draw(shape, params.seed, params.problem_id, philox.TAG_GE, 0, t)
     return math.exp(lg) / rate
 
@@ -279,6 +295,48 @@ def iterate(params, X, Mk, st, learn_dict=True, follow_z=None, tie_tol=1e-4):
     gs = gamma_s_update(params, Z, W, st.t)
     ge = gamma_eps_update(params, Mk, R, st.t)
     return State(D=D, W=W, Z=Z, ell=ell, gamma_s=gs, gamma_eps=ge, t=st.t + 1), rep
+
+
+def batch_rows(N, n_batches, batch):
+    """Patches of mini-batch `batch`: every patch i with i mod n_batches == batch."""
+    return np.arange(batch, N, n_batches)
+
+
+def minibatch_step(params, X, Mk, st, n_batches, batch, learn_dict=True, follow_z=None,
+                   tie_tol=1e-4):
+    """One mini-batch step, iteration number st.t: the sweep visits the n_b
+    patches of `batch` only (the others keep their codes), then the dictionary,
+    pi, gamma_s and gamma_eps are drawn from the conditionals given the batch
+    with its statistics scaled by s = N / n_b.  follow_z (N x K) is consulted
+    on the batch's rows.  Returns (new state, sweep report of the batch)."""
+    N = X.shape[0]
+    rows = batch_rows(N, n_batches, batch)
+    scale = N / rows.size
+    sub = State(D=st.D, W=st.W[rows], Z=st.Z[rows], ell=st.ell, gamma_s=st.gamma_s,
+                gamma_eps=st.gamma_eps, t=st.t)
+    fz = None if follow_z is None else np.asarray(follow_z)[rows]
+    Wb, Zb, Rb, rep = sweep(params, X[rows], Mk[rows], sub, follow_z=fz, tie_tol=tie_tol,
+                            patch_ids=rows)
+    D = st.D
+    if learn_dict:
+        D, Rb = dictionary_update(params, Mk[rows], sub, Wb, Rb, scale=scale)
+    ell = pi_update(params, Zb, st.t, scale=scale)
+    gs = gamma_s_update(params, Zb, Wb, st.t, scale=scale)
+    ge = gamma_eps_update(params, Mk[rows], Rb, st.t, scale=scale)
+    W = st.W.copy()
+    Z = st.Z.copy()
+    W[rows] = Wb
+    Z[rows] = Zb
+    return State(D=D, W=W, Z=Z, ell=ell, gamma_s=gs, gamma_eps=ge, t=st.t + 1), rep
+
+
+def epochs(params, X, Mk, st, n_epochs, n_batches, learn_dict=True):
+    """n_epochs passes over all patches, each the n_batches mini-batch steps in
+    ascending batch order (n_epochs * n_batches iteration numbers)."""
+    for _ in range(n_epochs):
+        for b in range(n_batches):
+            st, _ = minibatch_step(params, X, Mk, st, n_batches, b, learn_dict=learn_dict)
+    return st
 
 
 def reconstruct(st, shape, patch, stride):
