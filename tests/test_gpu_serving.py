@@ -115,7 +115,8 @@ def test_transferred_dictionary():
     teacher = bpfa.Problem(y.astype(np.float32), m, PATCH, K=K, seed=77)
     teacher.iterate(4)
     frames = frames_for(2, 2)
-    srv = serve.Server(patch=PATCH, K=K, n_streams=3, sc_iters=2, dict_every=0, seed=SEED)
+    srv = serve.Server(patch=PATCH, K=K, n_streams=3, sc_iters=2, dict_every=0, seed=SEED,
+                       precision="bf16")
     srv.set_dictionary(2, teacher)
     for y2, m2 in frames:
         srv.submit(2, y2, m2)
