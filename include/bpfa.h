@@ -163,6 +163,28 @@ bpfa_status bpfa_reset_state(bpfa_t h);
  * ESTATE when the last frame load failed. */
 bpfa_status bpfa_iterate(bpfa_t h, int32_t n_iters, uint32_t flags);
 
+/* Mini-batch epochs (Time-to-solution section: a dictionary trained for a
+ * number of complete epochs; the paper gives no schedule, so this is a
+ * reading).  The patches are dealt into n_batches mini-batches, patch i to
+ * batch i mod n_batches, and one call runs n_steps mini-batch steps; step j
+ * works on batch (c + j) mod n_batches, where c is the handle's batch cursor
+ * (0 after bpfa_create, bpfa_set_frame, bpfa_reset_state, bpfa_set_state or a
+ * change of n_batches), so n_batches steps from c = 0 make one epoch in which
+ * every patch is swept once.  A step is one iteration with an iteration
+ * number t of its own: the z/s sweep over the batch's patches only (the other
+ * patches keep their codes), then, unless BPFA_SPARSE_CODE_ONLY, the
+ * dictionary, then pi, gamma_s and gamma_eps, each drawn from its conditional
+ * given the batch with every data statistic (the dictionary update's sums,
+ * the usage counts and the patch count of pi, sum z and sum w^2 of gamma_s,
+ * |Obs| and the residual sum of squares of gamma_eps) multiplied by
+ * N / n_b (n_b = patches in the batch): the conditional given N / n_b copies
+ * of the batch.  n_batches = 1 is bpfa_iterate.  Changing n_batches re-orders
+ * the frame's slots by (batch, |Obs|), with one host synchronisation, and may
+ * grow the handle's pinned staging buffer; otherwise asynchronous on the
+ * handle's stream.  Errors as bpfa_iterate, and EINVAL for n_batches outside
+ * 1 .. min(256, N) or n_steps < 0. */
+bpfa_status bpfa_minibatch(bpfa_t h, int32_t n_batches, int32_t n_steps, uint32_t flags);
+
 /* Overlap-averaged reconstruction from the current sample: every pixel is the
  * mean of the values D^T w_i that the patches covering it give it.  out holds
  * prod(shape) floats of kind `mem`; host memory synchronises the stream. */

@@ -22,7 +22,7 @@ _NAMES = {EINVAL: "EINVAL", ESHAPE: "ESHAPE", ENOMEM: "ENOMEM", EDEVICE: "EDEVIC
           ESTATE: "ESTATE", ENUMERIC: "ENUMERIC", EBUSY: "EBUSY"}
 
 EXPORTED = ["bpfa_params_default", "bpfa_workspace_size", "bpfa_create", "bpfa_set_frame",
-            "bpfa_reset_state", "bpfa_iterate", "bpfa_reconstruct", "bpfa_mean_reset",
+            "bpfa_reset_state", "bpfa_iterate", "bpfa_minibatch", "bpfa_reconstruct", "bpfa_mean_reset",
             "bpfa_mean_accumulate", "bpfa_mean_get", "bpfa_variance_get", "bpfa_set_precision",
             "bpfa_transfer_dictionary", "bpfa_get_state",
             "bpfa_set_state", "bpfa_get_stats", "bpfa_set_timing", "bpfa_sync",
@@ -100,6 +100,7 @@ def _load():
         "bpfa_set_frame": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, ctypes.c_int]),
         "bpfa_reset_state": (ctypes.c_int, [vp]),
         "bpfa_iterate": (ctypes.c_int, [vp, i32, u32]),
+        "bpfa_minibatch": (ctypes.c_int, [vp, i32, i32, u32]),
         "bpfa_reconstruct": (ctypes.c_int, [vp, vp, ctypes.c_int]),
         "bpfa_mean_reset": (ctypes.c_int, [vp]),
         "bpfa_mean_accumulate": (ctypes.c_int, [vp]),
@@ -257,6 +258,14 @@ class Problem:
 
     def iterate(self, n=1, flags=LEARN_DICT):
         _check(lib.bpfa_iterate(self._h, int(n), int(flags)))
+
+    def minibatch(self, n_batches, n_steps=1, flags=LEARN_DICT):
+        """n_steps mini-batch steps of a partition into n_batches batches."""
+        _check(lib.bpfa_minibatch(self._h, int(n_batches), int(n_steps), int(flags)))
+
+    def epochs(self, n_epochs, n_batches, flags=LEARN_DICT):
+        """n_epochs complete epochs: n_epochs * n_batches mini-batch steps."""
+        self.minibatch(n_batches, int(n_epochs) * int(n_batches), flags)
 
     def reconstruct(self, out=None):
         if out is None:

@@ -194,8 +194,10 @@ Layout make_layout(const Geom& g) {
   L.obs_idx = take(2 * (size_t)L.Jcap * Np);
   L.obs_val = take(4 * (size_t)L.Jcap * Np);
   L.sweep_waves = take(16 * (size_t)L.wave_cap);
-  L.sort_hist = take(4 * (P + 1) * ((N + kSortBlock - 1) / kSortBlock));
-  L.sort_bin = take(4 * (P + 1));
+  // the sort's histogram for up to kMaxBatches batches: each batch's sort
+  // blocks hold ceil(N / B / 256) <= ceil(N / 256 / B) + 1 blocks' worth
+  L.sort_hist = take(4 * (P + 1) * ((N + kSortBlock - 1) / kSortBlock + kMaxBatches));
+  L.sort_bin = take(4 * (P + 1) * (size_t)kMaxBatches);
   L.omega = take(4 * (size_t)g.Mtot);
   L.omega_c = take(16 * (size_t)g.Mtot);
   L.omega_blk = take(4 * (((size_t)g.Mtot + 255) / 256 + 1));
@@ -252,6 +254,12 @@ struct bpfa_problem {
   // copies run as DMA without a pageable bounce
   char* stage = nullptr;
   size_t stage_bytes = 0;
+  // mini-batch partition of the slot order (patch i in batch i mod n_batches)
+  int n_batches = 1;
+  int batch_cursor = 0;            // batch of the next mini-batch step
+  std::vector<int> batch_slot0;    // n_batches + 1: first slot of each batch
+  std::vector<int> batch_wave0;    // n_batches + 1: first wavefront of each batch
+  std::vector<long long> batch_nobs;  // observed pixels of each batch
   uint32_t key0 = 0, key1 = 0;
   int64_t t_host = 1;
   int64_t mean_count = 0;       // samples in the posterior-mean running sum
@@ -329,38 +337,54 @@ bpfa_status check_status(bpfa_problem* h) {
   return BPFA_OK;
 }
 
-// Upload a frame and rebuild the patch index.  keep_codes: the active lists
-// (stored by patch, not by slot) stay as they are; otherwise they are cleared.
-bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask, bpfa_mem mem,
-                       bool keep_codes) {
+// Pinned staging of the frame load: the device scalars, the slot sort's key
+// offsets for `batches` batches, and the wavefront table.
+size_t stage_size(const Geom& g, const Layout& L, int batches) {
+  return align_up(sizeof(DevScalars), 16) + align_up(4 * ((size_t)g.P + 1) * batches, 16) +
+         16 * (size_t)L.wave_cap;
+}
+
+bpfa_status ensure_stage(bpfa_problem* h, int batches) {
+  const size_t need = stage_size(h->g, h->L, batches);
+  if (need <= h->stage_bytes) return BPFA_OK;
+  HIPCHK(hipStreamSynchronize(h->st));   // a pending upload may still read the old staging
+  if (h->stage) (void)hipHostFree(h->stage);
+  h->stage = nullptr;
+  h->stage_bytes = 0;
+  if (hipHostMalloc((void**)&h->stage, need, hipHostMallocDefault) != hipSuccess)
+    return fail(BPFA_ENOMEM, "hipHostMalloc of %zu staging bytes failed", need);
+  h->stage_bytes = need;
+  return BPFA_OK;
+}
+
+// Slot order of the current frame for a partition into n_batches
+// mini-batches: sort by (batch, |Obs|), read the key offsets back (one host
+// synchronisation), fill the per-slot observed tables and build the sweep's
+// wavefront table, whose wavefronts never straddle two batches.  with_plan:
+// also size the dictionary-statistics launch from the frame's observed
+// pixels (a new frame).
+bpfa_status order_slots(bpfa_problem* h, int n_batches, bool with_plan) {
   const Geom& g = h->g;
-  h->frame_ok = false;   // until every table of the new frame is built
-  bpfa_status r = upload(h, h->b.image, image, 4 * (size_t)g.Mtot, mem);
+  bpfa_status r = ensure_stage(h, n_batches);
   if (r != BPFA_OK) return r;
-  r = upload(h, h->b.mask, mask, (size_t)g.Mtot, mem);
-  if (r != BPFA_OK) return r;
-  std::array<hipEvent_t, 2> ev{};
-  if (h->timing && (r = record(h, &ev[0])) != BPFA_OK) return r;
-  HIPCHK(launch_index(g, h->b, h->L.Npad, h->st));
-  HIPCHK(launch_sort(g, h->b, h->L.Npad, h->st));
-  if (!keep_codes) {
-    HIPCHK(hipMemsetAsync(h->b.nact[0], 0, 4 * (size_t)h->L.Npad, h->st));
-    HIPCHK(hipMemsetAsync(h->b.nact[1], 0, 4 * (size_t)h->L.Npad, h->st));
-  }
-  HIPCHK(launch_omega(g, h->b, h->st));
-  // (the synchronisation also retires the previous frame's table upload
-  // before its staging is rewritten)
+  if (sort_hist_entries(g, n_batches) >
+      (size_t)(g.P + 1) * ((g.N + kSortBlock - 1) / kSortBlock + kMaxBatches))
+    return fail(BPFA_EINVAL, "sort histogram too small for %d batches", n_batches);
+  HIPCHK(launch_sort(g, h->b, n_batches, h->st));
+  // (the synchronisation also retires the previous table upload before its
+  // staging is rewritten)
   DevScalars* sp = reinterpret_cast<DevScalars*>(h->stage);
   int32_t* bin_start = reinterpret_cast<int32_t*>(h->stage + align_up(sizeof(DevScalars), 16));
   int4* wave_stage = reinterpret_cast<int4*>(h->stage + align_up(sizeof(DevScalars), 16) +
-                                             align_up(4 * ((size_t)g.P + 1), 16));
+                                             align_up(4 * ((size_t)g.P + 1) * n_batches, 16));
+  const size_t nkeys = (size_t)(g.P + 1) * n_batches;
   HIPCHK(hipMemcpyAsync(sp, h->b.scal, sizeof(DevScalars), hipMemcpyDeviceToHost, h->st));
-  HIPCHK(hipMemcpyAsync(bin_start, h->b.sort_bin, 4 * ((size_t)g.P + 1), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipMemcpyAsync(bin_start, h->b.sort_bin, 4 * nkeys, hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
-  const DevScalars s = *sp;   // bin_start[c]: first slot of each |Obs| value c
+  const DevScalars s = *sp;   // bin_start[b (P + 1) + c]: first slot of batch b's |Obs| = c
   h->max_obs = s.max_obs;
   h->n_omega = s.n_omega;
-  {
+  if (with_plan) {
     // The statistics blocks run in rounds of (CUs x blocks per CU): pick the
     // chunk count c >= need that minimises rounds(c) / c, the time per visit,
     // so that the last round is not a near-empty tail (ties: the smaller c,
@@ -391,27 +415,37 @@ bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask,
   const int J4 = std::max(4, (h->max_obs + 3) & ~3);
   h->jpad = J4;
   HIPCHK(launch_slots(g, h->b, h->L.Npad, J4, h->st));
-  HIPCHK(launch_visit_table(g, h->b, h->n_omega, h->st));
-  // wavefront table of the sweep: slots ascend in |Obs|; a wavefront takes
-  // consecutive slots of one lane count (sweep_lanes), 64 / lanes of them,
-  // and its register count J covers its last (largest) slot
-  {
-    // one pass: the |Obs| queries come in ascending slot order, so the bin is
-    // found by a pointer that only moves forward
+  // wavefront table of the sweep: within a batch, slots ascend in |Obs|; a
+  // wavefront takes consecutive slots of one batch and one lane count
+  // (sweep_lanes), 64 / lanes of them, and its register count J covers its
+  // last (largest) slot
+  h->batch_slot0.assign(n_batches + 1, g.N);
+  h->batch_wave0.assign(n_batches + 1, 0);
+  h->batch_nobs.assign(n_batches, 0);
+  long long n = 0;
+  for (int bt = 0; bt < n_batches; ++bt) {
+    const int32_t* bs = bin_start + (size_t)bt * (g.P + 1);
+    const int send = bt + 1 < n_batches ? bin_start[(size_t)(bt + 1) * (g.P + 1)] : g.N;
+    // end of |Obs| bin c of this batch
+    auto bin_end = [&](int c) { return c >= g.P ? send : bs[c + 1]; };
+    h->batch_slot0[bt] = bs[0];
+    h->batch_wave0[bt] = (int)n;
+    long long nobs = 0;
+    for (int c = 1; c <= g.P; ++c) nobs += (long long)c * (bin_end(c) - bs[c]);
+    h->batch_nobs[bt] = nobs;
+    // the |Obs| queries come in ascending slot order, so the bin is found by
+    // a pointer that only moves forward
     int bin = 0;
-    auto count_of = [&](int slot) {   // |Obs| of a slot: the bin whose range holds it
-      while (bin < g.P && bin_start[bin + 1] <= slot) ++bin;
+    auto count_of = [&](int slot) {
+      while (bin < g.P && bin_end(bin) <= slot) ++bin;
       return bin;
     };
-    auto first_above = [&](int c) {   // first slot with |Obs| > c
-      return c >= g.P ? g.N : bin_start[(size_t)c + 1];
-    };
-    long long n = 0;
-    int slot = 0;
-    while (slot < g.N) {
+    auto first_above = [&](int c) { return c >= g.P ? send : bs[c + 1]; };
+    int slot = bs[0];
+    while (slot < send) {
       const int lpp = sweep_lanes(count_of(slot));
       const int climit = lpp == 1 ? 16 : lpp == 2 ? 32 : lpp == 4 ? 64 : lpp == 8 ? 128 : 256;
-      const int end = std::min({g.N, slot + kWave / lpp, first_above(climit)});
+      const int end = std::min({send, slot + kWave / lpp, first_above(climit)});
       const int clast = count_of(end - 1);
       int J = 16;
       if (lpp == 1) J = std::max(4, (clast + 1) & ~1);
@@ -421,9 +455,36 @@ bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask,
       wave_stage[n++] = make_int4(slot, end - slot, lpp, J);
       slot = end;
     }
-    h->n_waves = (int)n;
-    HIPCHK(hipMemcpyAsync(h->b.sweep_waves, wave_stage, 16 * (size_t)n, hipMemcpyHostToDevice, h->st));
   }
+  h->batch_slot0[n_batches] = g.N;
+  h->batch_wave0[n_batches] = (int)n;
+  h->n_waves = (int)n;
+  HIPCHK(hipMemcpyAsync(h->b.sweep_waves, wave_stage, 16 * (size_t)n, hipMemcpyHostToDevice, h->st));
+  h->n_batches = n_batches;
+  h->batch_cursor = 0;
+  return BPFA_OK;
+}
+
+// Upload a frame and rebuild the patch index.  keep_codes: the active lists
+// (stored by patch, not by slot) stay as they are; otherwise they are cleared.
+bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask, bpfa_mem mem,
+                       bool keep_codes) {
+  const Geom& g = h->g;
+  h->frame_ok = false;   // until every table of the new frame is built
+  bpfa_status r = upload(h, h->b.image, image, 4 * (size_t)g.Mtot, mem);
+  if (r != BPFA_OK) return r;
+  r = upload(h, h->b.mask, mask, (size_t)g.Mtot, mem);
+  if (r != BPFA_OK) return r;
+  std::array<hipEvent_t, 2> ev{};
+  if (h->timing && (r = record(h, &ev[0])) != BPFA_OK) return r;
+  HIPCHK(launch_index(g, h->b, h->L.Npad, h->st));
+  if (!keep_codes) {
+    HIPCHK(hipMemsetAsync(h->b.nact[0], 0, 4 * (size_t)h->L.Npad, h->st));
+    HIPCHK(hipMemsetAsync(h->b.nact[1], 0, 4 * (size_t)h->L.Npad, h->st));
+  }
+  HIPCHK(launch_omega(g, h->b, h->st));
+  if ((r = order_slots(h, h->n_batches, true)) != BPFA_OK) return r;
+  HIPCHK(launch_visit_table(g, h->b, h->n_omega, h->st));
   if (h->timing) {
     if ((r = record(h, &ev[1])) != BPFA_OK) return r;
     h->index_events.push_back(ev);
@@ -435,6 +496,99 @@ bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask,
 bpfa_status clear_codes(bpfa_problem* h) {
   HIPCHK(hipMemsetAsync(h->b.nact[0], 0, 4 * (size_t)h->L.Npad, h->st));
   HIPCHK(hipMemsetAsync(h->b.nact[1], 0, 4 * (size_t)h->L.Npad, h->st));
+  return BPFA_OK;
+}
+
+bpfa_status check_iter_flags(bpfa_t h, uint32_t flags) {
+  if (flags & ~(uint32_t)(BPFA_LEARN_DICT | BPFA_SPARSE_CODE_ONLY | BPFA_PRECISION_BF16))
+    return fail(BPFA_EINVAL, "unknown flags 0x%x", flags);
+  if ((flags & BPFA_LEARN_DICT) && (flags & BPFA_SPARSE_CODE_ONLY))
+    return fail(BPFA_EINVAL, "LEARN_DICT and SPARSE_CODE_ONLY are exclusive");
+  if (flags & BPFA_PRECISION_BF16)
+    return fail(BPFA_EINVAL, "the precision form is chosen with bpfa_set_precision, not an iterate flag");
+  if (!h->frame_ok)
+    return fail(BPFA_ESTATE, "the last frame load failed; set a valid frame before iterating");
+  return BPFA_OK;
+}
+
+// One Gibbs step on the handle's stream: batch < 0 is a full iteration over
+// every patch; batch >= 0 a mini-batch step over that batch of the current
+// partition, its statistics scaled by N / n_b.
+bpfa_status run_step(bpfa_t h, int learn, int batch) {
+  const Geom& g = h->g;
+  const Layout& L = h->L;
+  Buffers& b = h->b;
+  const double hyper[6] = {h->prm.a, h->prm.b, h->prm.c, h->prm.d, h->prm.e, h->prm.f};
+  int w0 = 0, w1 = h->n_waves, nbat = 1, bsel = 0;
+  StepBatch sb{g.N, -1, 1.0};
+  if (batch >= 0) {
+    w0 = h->batch_wave0[batch];
+    w1 = h->batch_wave0[batch + 1];
+    nbat = h->n_batches;
+    bsel = batch;
+    sb.n_b = h->batch_slot0[batch + 1] - h->batch_slot0[batch];
+    sb.n_obs_b = h->batch_nobs[batch];
+    sb.scale = (double)g.N / (double)sb.n_b;
+  }
+  SweepArgs a{};
+  a.N = g.N;
+  a.Npad = L.Npad;
+  a.P = g.P;
+  a.K = g.K;
+  a.KT = L.KT;
+  a.KS = L.KS;
+  a.key0 = h->key0;
+  a.key1 = h->key1;
+  a.stream = stream_word(1, h->prm.problem_id);
+  a.perm = b.perm;
+  a.Jpad = h->jpad;
+  a.obs_idx = b.obs_idx;
+  a.obs_val = b.obs_val;
+  a.D = b.D;
+  a.Ck = b.Ck;
+  a.scal = b.scal;
+  a.list_in = b.list[h->cur];
+  a.nact_in = b.nact[h->cur];
+  a.list_out = b.list[1 - h->cur];
+  a.nact_out = b.nact[1 - h->cur];
+  a.cnt = b.sw_cnt;
+  a.part = b.sw_part;
+  std::array<hipEvent_t, 4> ev{};
+  bpfa_status r;
+  if (h->timing && (r = record(h, &ev[0])) != BPFA_OK) return r;
+  HIPCHK(launch_sweep(b.sweep_waves + w0, w1 - w0, L.sweep_lds, a, h->st));
+  if (h->timing && (r = record(h, &ev[1])) != BPFA_OK) return r;
+  HIPCHK(launch_sweep_reduce(g, b, (w1 - w0 + kSweepWaves - 1) / kSweepWaves, h->st));
+  if (batch < 0) {
+    h->cur = 1 - h->cur;
+  } else {
+    // the batch's new lists go back into the current buffer, which keeps
+    // every other patch's codes
+    const int s0 = h->batch_slot0[batch];
+    HIPCHK(launch_list_copy(g, b, 1 - h->cur, s0, h->batch_slot0[batch + 1] - s0, h->st));
+  }
+  if (learn) {
+    DictPlan plan = L.plan;
+    plan.chunks = h->dict_groups;
+    plan.chunk_visits = h->dict_cv;
+    plan.xcd = plan.chunks % 8 == 0;
+    HIPCHK(launch_dict_stats(g, b, plan, h->cur, h->n_omega, nbat, bsel, h->st));
+    if (g.K <= kChainLdsMaxK && plan.RG == 1) {
+      HIPCHK(launch_dict_reduce_chain_lds(g, b, plan, sb.scale, h->key0, h->key1,
+                                          stream_word(2, h->prm.problem_id), h->st));
+    } else {
+      HIPCHK(launch_dict_reduce(g, b, plan, h->st));
+      HIPCHK(launch_dict_chain(g, b, L.plan, sb.scale, h->key0, h->key1,
+                               stream_word(2, h->prm.problem_id), h->st));
+    }
+  }
+  if (h->timing && (r = record(h, &ev[2])) != BPFA_OK) return r;
+  HIPCHK(launch_scalars(g, b, hyper, learn, sb, h->key0, h->key1, h->prm.problem_id, h->st));
+  if (h->timing) {
+    if ((r = record(h, &ev[3])) != BPFA_OK) return r;
+    h->iter_events.push_back(ev);
+  }
+  ++h->t_host;
   return BPFA_OK;
 }
 
@@ -490,8 +644,7 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
       return bail(fail(BPFA_EDEVICE, "hipStreamCreate failed"));
     h->own_stream = true;
   }
-  h->stage_bytes = align_up(sizeof(DevScalars), 16) + align_up(4 * ((size_t)g.P + 1), 16) +
-                   16 * (size_t)h->L.wave_cap;
+  h->stage_bytes = stage_size(g, h->L, 1);
   if (hipHostMalloc((void**)&h->stage, h->stage_bytes, hipHostMallocDefault) != hipSuccess)
     return bail(fail(BPFA_ENOMEM, "hipHostMalloc of %zu staging bytes failed", h->stage_bytes));
   {
@@ -609,79 +762,40 @@ bpfa_status bpfa_reset_state(bpfa_t h) {
   HIPCHK(launch_ck(g, h->b, h->st));
   h->t_host = 1;
   h->mean_count = 0;
+  h->batch_cursor = 0;
   return clear_codes(h);
 }
 
 bpfa_status bpfa_iterate(bpfa_t h, int32_t n_iters, uint32_t flags) {
   if (!h) return fail(BPFA_EINVAL, "NULL handle");
   if (n_iters < 0) return fail(BPFA_EINVAL, "n_iters < 0");
-  if (flags & ~(uint32_t)(BPFA_LEARN_DICT | BPFA_SPARSE_CODE_ONLY | BPFA_PRECISION_BF16))
-    return fail(BPFA_EINVAL, "unknown flags 0x%x", flags);
-  if ((flags & BPFA_LEARN_DICT) && (flags & BPFA_SPARSE_CODE_ONLY))
-    return fail(BPFA_EINVAL, "LEARN_DICT and SPARSE_CODE_ONLY are exclusive");
-  if (flags & BPFA_PRECISION_BF16)
-    return fail(BPFA_EINVAL, "the precision form is chosen with bpfa_set_precision, not an iterate flag");
-  if (!h->frame_ok)
-    return fail(BPFA_ESTATE, "the last frame load failed; set a valid frame before iterating");
+  bpfa_status r = check_iter_flags(h, flags);
+  if (r != BPFA_OK) return r;
   const int learn = (flags & BPFA_SPARSE_CODE_ONLY) ? 0 : 1;
   DeviceGuard dg(h->prm.device);
-  const Geom& g = h->g;
-  const Layout& L = h->L;
-  Buffers& b = h->b;
-  const double hyper[6] = {h->prm.a, h->prm.b, h->prm.c, h->prm.d, h->prm.e, h->prm.f};
-  for (int it = 0; it < n_iters; ++it) {
-    SweepArgs a{};
-    a.N = g.N;
-    a.Npad = L.Npad;
-    a.P = g.P;
-    a.K = g.K;
-    a.KT = L.KT;
-    a.KS = L.KS;
-    a.key0 = h->key0;
-    a.key1 = h->key1;
-    a.stream = stream_word(1, h->prm.problem_id);
-    a.perm = b.perm;
-    a.Jpad = h->jpad;
-    a.obs_idx = b.obs_idx;
-    a.obs_val = b.obs_val;
-    a.D = b.D;
-    a.Ck = b.Ck;
-    a.scal = b.scal;
-    a.list_in = b.list[h->cur];
-    a.nact_in = b.nact[h->cur];
-    a.list_out = b.list[1 - h->cur];
-    a.nact_out = b.nact[1 - h->cur];
-    a.cnt = b.sw_cnt;
-    a.part = b.sw_part;
-    std::array<hipEvent_t, 4> ev{};
-    bpfa_status r;
-    if (h->timing && (r = record(h, &ev[0])) != BPFA_OK) return r;
-    HIPCHK(launch_sweep(b.sweep_waves, h->n_waves, L.sweep_lds, a, h->st));
-    if (h->timing && (r = record(h, &ev[1])) != BPFA_OK) return r;
-    HIPCHK(launch_sweep_reduce(g, b, (h->n_waves + kSweepWaves - 1) / kSweepWaves, h->st));
-    h->cur = 1 - h->cur;
-    if (learn) {
-      DictPlan plan = L.plan;
-      plan.chunks = h->dict_groups;
-      plan.chunk_visits = h->dict_cv;
-      plan.xcd = plan.chunks % 8 == 0;
-      HIPCHK(launch_dict_stats(g, b, plan, h->cur, h->n_omega, h->st));
-      if (g.K <= kChainLdsMaxK && plan.RG == 1) {
-        HIPCHK(launch_dict_reduce_chain_lds(g, b, plan, h->key0, h->key1,
-                                            stream_word(2, h->prm.problem_id), h->st));
-      } else {
-        HIPCHK(launch_dict_reduce(g, b, plan, h->st));
-        HIPCHK(launch_dict_chain(g, b, L.plan, h->key0, h->key1,
-                                 stream_word(2, h->prm.problem_id), h->st));
-      }
-    }
-    if (h->timing && (r = record(h, &ev[2])) != BPFA_OK) return r;
-    HIPCHK(launch_scalars(g, b, hyper, learn, h->key0, h->key1, h->prm.problem_id, h->st));
-    if (h->timing) {
-      if ((r = record(h, &ev[3])) != BPFA_OK) return r;
-      h->iter_events.push_back(ev);
-    }
-    ++h->t_host;
+  for (int it = 0; it < n_iters; ++it)
+    if ((r = run_step(h, learn, -1)) != BPFA_OK) return r;
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_minibatch(bpfa_t h, int32_t n_batches, int32_t n_steps, uint32_t flags) {
+  if (!h) return fail(BPFA_EINVAL, "NULL handle");
+  if (n_steps < 0) return fail(BPFA_EINVAL, "n_steps < 0");
+  if (n_batches < 1 || n_batches > kMaxBatches || n_batches > h->g.N)
+    return fail(BPFA_EINVAL, "n_batches must be 1..min(%d, N = %d), got %d", kMaxBatches, h->g.N,
+                n_batches);
+  bpfa_status r = check_iter_flags(h, flags);
+  if (r != BPFA_OK) return r;
+  const int learn = (flags & BPFA_SPARSE_CODE_ONLY) ? 0 : 1;
+  DeviceGuard dg(h->prm.device);
+  if (n_batches != h->n_batches) {
+    h->frame_ok = false;   // until the new slot order is whole
+    if ((r = order_slots(h, n_batches, false)) != BPFA_OK) return r;
+    h->frame_ok = true;
+  }
+  for (int st = 0; st < n_steps; ++st) {
+    if ((r = run_step(h, learn, h->batch_cursor)) != BPFA_OK) return r;
+    h->batch_cursor = (h->batch_cursor + 1) % h->n_batches;
   }
   return BPFA_OK;
 }
@@ -868,6 +982,7 @@ bpfa_status bpfa_set_state(bpfa_t h, const bpfa_state_view* v) {
   HIPCHK(launch_ck(g, h->b, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
   h->t_host = v->t;
+  h->batch_cursor = 0;
   if (bad) return fail(BPFA_ESTATE, "W is non-zero where Z is 0");
   return BPFA_OK;
 }

@@ -21,6 +21,7 @@ constexpr int kChainLdsMaxK = 128;  // largest K whose binary64 C_p (K x K) the 
 constexpr int kLdsBytes = 160 * 1024 - 1024;   // per block, leaving room for static arrays
 constexpr int kDictLdsEntries = 16384; // int64 accumulators per statistics block (128 KiB)
 constexpr int kSortBlock = 256;        // patches per block of the slot sort
+constexpr int kMaxBatches = 256;       // mini-batches of the epoch schedule, at most
 
 // Patch geometry (all sizes fit 32 bits; checked at create).
 struct Geom {
@@ -89,8 +90,8 @@ struct Buffers {
   uint16_t* obs_idx = nullptr;   // [Jcap][Npad]
   float* obs_val = nullptr;      // [Jcap][Npad]
   int4* sweep_waves = nullptr;   // per-frame wavefront table (first slot, slots, lanes per slot, J)
-  int32_t* sort_hist = nullptr;  // (P + 1) x sort blocks, bin-major
-  int32_t* sort_bin = nullptr;   // P + 1: bin totals, then bin offsets
+  int32_t* sort_hist = nullptr;  // [batch][P + 1][sort blocks of the batch]
+  int32_t* sort_bin = nullptr;   // [batch][P + 1]: key totals, then key offsets
   int32_t* omega = nullptr;      // observed pixel indices, ascending (Mtot capacity)
   int4* omega_c = nullptr;       // their coordinates (unused dimensions 0)
   int32_t* omega_blk = nullptr;  // per-block counts / offsets of the compaction
@@ -155,21 +156,38 @@ hipError_t launch_sweep(const int4* waves, int nwaves, size_t lds, const SweepAr
                         hipStream_t st);
 // lanes per patch of the sweep for a patch with c observed pixels
 inline int sweep_lanes(int c) { return c <= 16 ? 1 : c <= 32 ? 2 : c <= 64 ? 4 : c <= 128 ? 8 : 16; }
-// wavefronts the sweep table can need for N slots (slots per wave >= 4)
-inline long long sweep_wave_capacity(long long N) { return (N + 3) / 4 + 16; }
-hipError_t launch_sort(const Geom& g, const Buffers& b, int Npad, hipStream_t st);
+// wavefronts the sweep table can need for N slots: at least 4 slots per wave
+// except the last wave of each (batch, lanes per slot) run
+inline long long sweep_wave_capacity(long long N) { return (N + 3) / 4 + 8LL * kMaxBatches + 16; }
+hipError_t launch_sort(const Geom& g, const Buffers& b, int n_batches, hipStream_t st);
+// histogram entries of the slot sort for n_batches mini-batches
+size_t sort_hist_entries(const Geom& g, int n_batches);
+// copy the new lists of slots slot0 .. slot0 + nslots - 1 from buffer `from` to the other
+hipError_t launch_list_copy(const Geom& g, const Buffers& b, int from, int slot0, int nslots,
+                            hipStream_t st);
 hipError_t launch_sweep_reduce(const Geom& g, const Buffers& b, int blocks, hipStream_t st);
+// statistics over the visits of patches i with i mod n_batches == batch
 hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& plan, int cur,
-                             int n_omega, hipStream_t st);
+                             int n_omega, int n_batches, int batch, hipStream_t st);
 hipError_t launch_dict_reduce(const Geom& g, const Buffers& b, const DictPlan& plan,
                               hipStream_t st);
+// the chain draws with the data statistics multiplied by `scale` (a
+// mini-batch step's N / n_b; 1 for a full iteration)
 hipError_t launch_dict_reduce_chain_lds(const Geom& g, const Buffers& b, const DictPlan& plan,
-                                        uint32_t key0, uint32_t key1, uint32_t stream,
-                                        hipStream_t st);
-hipError_t launch_dict_chain(const Geom& g, const Buffers& b, const DictPlan& plan,
+                                        double scale, uint32_t key0, uint32_t key1,
+                                        uint32_t stream, hipStream_t st);
+hipError_t launch_dict_chain(const Geom& g, const Buffers& b, const DictPlan& plan, double scale,
                              uint32_t key0, uint32_t key1, uint32_t stream, hipStream_t st);
+// Batch of a step: n_b patches with n_obs_b observed pixels and its statistics
+// scaled by `scale`; a full iteration is {N, -1 (the frame's count), 1}.
+struct StepBatch {
+  long long n_b;
+  long long n_obs_b;
+  double scale;
+};
 hipError_t launch_scalars(const Geom& g, const Buffers& b, const double* hyper, int learn_dict,
-                          uint32_t key0, uint32_t key1, uint32_t problem_id, hipStream_t st);
+                          const StepBatch& sb, uint32_t key0, uint32_t key1, uint32_t problem_id,
+                          hipStream_t st);
 // posterior moments: (sum, sum2) = (x, x^2) (first) or += (x, x^2);
 // mean = sum / count; variance = (sum2 - sum^2 / count) / (count - 1)
 hipError_t launch_mean_add(long long n, const float* x, double* sum, double* sum2, bool first,

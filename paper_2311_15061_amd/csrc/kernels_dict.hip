@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
     Geom g, DictPlanDev pl, int nom, const int32_t* __restrict__ vpatch,
     const float* __restrict__ omega_y, const int2* __restrict__ list,
     const int32_t* __restrict__ nact, const DevScalars* __restrict__ scal,
-    long long* __restrict__ dpart, double* __restrict__ dx2) {
+    long long* __restrict__ dpart, double* __restrict__ dx2, int n_batches, int batch) {
   extern __shared__ long long acc[];
   __shared__ double s_x2[kDictBlock / kWave];
   __shared__ int s_total;
@@ -205,6 +205,8 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
     if (v < v1) {
       r_pat[u] = vs[v];
       r_y[u] = omega_y[v];
+      // a mini-batch step counts only the visits of its batch's patches
+      if (n_batches > 1 && r_pat[u] >= 0 && r_pat[u] % n_batches != batch) r_pat[u] = -1;
     }
   }
 #pragma unroll
@@ -467,17 +469,20 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 // to its u_j: no reduction per step, and at the end d.u = d^T C_p d.
 // C: C_p (K x K, symmetric) in global memory or LDS; Bp, diagp: B_p and the
 // diagonal of C_p; x2: X2_p.
+// scale: the data statistics enter the conditional multiplied by it (a
+// mini-batch step's N / n_b), i.e. gamma_eps scale in place of gamma_eps in
+// lam and g; the residual sum of squares stays the batch's own.
 template <int KPL, int PF>
 __device__ __forceinline__ void chain_run(const Geom& g, int p, int lane, const double* C,
                                           const double* Bp, const double* diagp, double x2,
                                           DevScalars* scal, float* __restrict__ D,
-                                          double* __restrict__ sumr2_p, uint32_t key0,
-                                          uint32_t key1, uint32_t stream,
+                                          double* __restrict__ sumr2_p, double scale,
+                                          uint32_t key0, uint32_t key1, uint32_t stream,
                                           const double* u0 = nullptr) {
   static_assert(kWave % PF == 0, "a ring slot keeps its row across register groups");
   const int K = g.K, P = g.P;
   const uint32_t t = (uint32_t)scal->t;
-  const double ge = scal->gamma_eps;
+  const double ge = scal->gamma_eps * scale;
   double dreg[KPL], ureg[KPL], greg[KPL], treg[KPL], breg[KPL];
 #pragma unroll
   for (int m = 0; m < KPL; ++m) {
@@ -591,11 +596,11 @@ template <int KPL, int PF>
 __global__ __launch_bounds__(kWave) void dict_chain_kernel(
     Geom g, const double* __restrict__ Cfull, const double* __restrict__ Bvec,
     const double* __restrict__ diag, const double* __restrict__ x2p, DevScalars* scal,
-    float* __restrict__ D, double* __restrict__ sumr2_p, uint32_t key0, uint32_t key1,
-    uint32_t stream) {
+    float* __restrict__ D, double* __restrict__ sumr2_p, double scale, uint32_t key0,
+    uint32_t key1, uint32_t stream) {
   const int p = blockIdx.x, K = g.K;
   chain_run<KPL, PF>(g, p, threadIdx.x, Cfull + (size_t)p * K * K, Bvec + (size_t)p * K,
-                     diag + (size_t)p * K, x2p[p], scal, D, sumr2_p, key0, key1, stream);
+                     diag + (size_t)p * K, x2p[p], scal, D, sumr2_p, scale, key0, key1, stream);
 }
 
 // K <= kChainLdsMaxK (one row group): the chunk partials are summed into the
@@ -630,7 +635,7 @@ template <int KPL>
 __global__ __launch_bounds__(1024) void dict_chain_lds_kernel(
     Geom g, const double* __restrict__ Ctri, const double* __restrict__ Bvec,
     const double* __restrict__ x2p, DevScalars* scal, float* __restrict__ D,
-    double* __restrict__ sumr2_p, uint32_t key0, uint32_t key1, uint32_t stream) {
+    double* __restrict__ sumr2_p, double scale, uint32_t key0, uint32_t key1, uint32_t stream) {
   extern __shared__ double Cs[];                 // K x K, then the u partials
   __shared__ double s_B[kChainLdsMaxK], s_diag[kChainLdsMaxK], s_d[kChainLdsMaxK],
       s_u[kChainLdsMaxK];
@@ -680,8 +685,8 @@ __global__ __launch_bounds__(1024) void dict_chain_lds_kernel(
   if (tid < kWave)
     // 8 row loads in flight: the LDS counter holds at most 15 outstanding,
     // so a deeper ring makes every step wait for all of them
-    chain_run<KPL, 8 / KPL>(g, p, tid, Cs, s_B, s_diag, x2p[p], scal, D, sumr2_p, key0, key1, stream,
-                       s_u);
+    chain_run<KPL, 8 / KPL>(g, p, tid, Cs, s_B, s_diag, x2p[p], scal, D, sumr2_p, scale, key0, key1,
+                            stream, s_u);
 }
 
 static DictPlanDev to_dev(const Geom& g, const DictPlan& plan) {
@@ -705,7 +710,7 @@ static DictPlanDev to_dev(const Geom& g, const DictPlan& plan) {
 }
 
 hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& plan, int cur,
-                             int n_omega, hipStream_t st) {
+                             int n_omega, int n_batches, int batch, hipStream_t st) {
   const DictPlanDev d = to_dev(g, plan);
   const int blocks = g.P * plan.RG * plan.chunks;
   // the LDS holds visit records for the largest chunk the plan allows
@@ -717,10 +722,12 @@ hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& pl
   if (e != hipSuccess) return e;
   if (skip)
     dict_stats_kernel<true><<<blocks, kDictBlock, lds, st>>>(
-        g, d, n_omega, b.vpatch, b.omega_y, b.list[cur], b.nact[cur], b.scal, b.dpart, b.dx2);
+        g, d, n_omega, b.vpatch, b.omega_y, b.list[cur], b.nact[cur], b.scal, b.dpart, b.dx2,
+        n_batches, batch);
   else
     dict_stats_kernel<false><<<blocks, kDictBlock, lds, st>>>(
-        g, d, n_omega, b.vpatch, b.omega_y, b.list[cur], b.nact[cur], b.scal, b.dpart, b.dx2);
+        g, d, n_omega, b.vpatch, b.omega_y, b.list[cur], b.nact[cur], b.scal, b.dpart, b.dx2,
+        n_batches, batch);
   return hipGetLastError();
 }
 
@@ -732,14 +739,14 @@ hipError_t launch_dict_reduce(const Geom& g, const Buffers& b, const DictPlan& p
   return hipGetLastError();
 }
 
-hipError_t launch_dict_chain(const Geom& g, const Buffers& b, const DictPlan& plan,
+hipError_t launch_dict_chain(const Geom& g, const Buffers& b, const DictPlan& plan, double scale,
                              uint32_t key0, uint32_t key1, uint32_t stream, hipStream_t st) {
   (void)plan;
   const int kpl = (g.K + kWave - 1) / kWave;
 #define BPFA_CHAIN(KP, PFV)                                                              \
   dict_chain_kernel<KP, PFV><<<g.P, kWave, 0, st>>>(g, b.Cfull, b.Bvec, b.diag, b.x2p,  \
-                                                    b.scal, b.D, b.sumr2_p, key0, key1, \
-                                                    stream)
+                                                    b.scal, b.D, b.sumr2_p, scale, key0, \
+                                                    key1, stream)
   if (kpl <= 1) BPFA_CHAIN(1, 16);
   else if (kpl <= 2) BPFA_CHAIN(2, 16);
   else if (kpl <= 4) BPFA_CHAIN(4, 8);
@@ -753,8 +760,8 @@ hipError_t launch_dict_chain(const Geom& g, const Buffers& b, const DictPlan& pl
 size_t dict_chain_lds_bytes(int K) { return (size_t)K * K * 8 + (size_t)(1024 / K) * K * 8; }
 
 hipError_t launch_dict_reduce_chain_lds(const Geom& g, const Buffers& b, const DictPlan& plan,
-                                        uint32_t key0, uint32_t key1, uint32_t stream,
-                                        hipStream_t st) {
+                                        double scale, uint32_t key0, uint32_t key1,
+                                        uint32_t stream, hipStream_t st) {
   if (g.K > kChainLdsMaxK || plan.RG != 1) return hipErrorInvalidValue;
   const DictPlanDev d = to_dev(g, plan);
   const int E = g.K * (g.K + 1) / 2;
@@ -770,13 +777,13 @@ hipError_t launch_dict_reduce_chain_lds(const Geom& g, const Buffers& b, const D
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     dict_chain_lds_kernel<1><<<g.P, 1024, lds, st>>>(g, b.Cfull, b.Bvec, b.x2p, b.scal, b.D,
-                                                     b.sumr2_p, key0, key1, stream);
+                                                     b.sumr2_p, scale, key0, key1, stream);
   } else {
     e = hipFuncSetAttribute((const void*)dict_chain_lds_kernel<2>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     dict_chain_lds_kernel<2><<<g.P, 1024, lds, st>>>(g, b.Cfull, b.Bvec, b.x2p, b.scal, b.D,
-                                                     b.sumr2_p, key0, key1, stream);
+                                                     b.sumr2_p, scale, key0, key1, stream);
   }
   return hipGetLastError();
 }

@@ -3,11 +3,11 @@
 // inpainting uses only the observed pixels of each patch).
 //
 // index_kernel   one thread per patch: observed-pixel bitmask and |Obs(i)|.
-// sort_*         stable counting sort of the patches by |Obs(i)| into slots
-//                (per-block histograms, per-count scans over blocks, ranks
-//                inside a block): deterministic, so results do not depend on
-//                scheduling; the sweep's blocks then hold patches of nearly
-//                equal |Obs|.
+// sort_*         stable counting sort of the patches by (mini-batch, |Obs(i)|)
+//                into slots (per-block histograms, per-key scans over blocks,
+//                ranks inside a block): deterministic, so results do not
+//                depend on scheduling; the sweep's blocks then hold patches
+//                of one batch and nearly equal |Obs|.
 // slots_kernel   one thread per slot: the observed offsets p (ascending) and
 //                values of the slot's patch, stored [j][slot] so that a wave
 //                reads them coalesced; padding entries point at offset P,
@@ -166,24 +166,47 @@ __device__ int block_scan_1024(int* __restrict__ data, int n, int* s_tot) {
   return total;
 }
 
-// ---- stable counting sort of patches by |Obs(i)| ---------------------------
+// ---- stable counting sort of patches by (batch, |Obs(i)|) ------------------
+//
+// With B mini-batches patch i belongs to batch i mod B, and the slots hold
+// batch 0's patches first, then batch 1's, ..., each batch in ascending
+// |Obs| (ties in ascending patch index).  Batch b's patches are the rows
+// r = 0 .. nr_b - 1 of i = r B + b; each batch is counted by its own
+// sort blocks of 256 rows, so the histogram holds (P + 1) entries per block as
+// in the single-batch sort.  Histogram layout [b][c][block of b], bins [b][c].
+// With B = 1 this is the plain counting sort by |Obs|.
 
-__global__ __launch_bounds__(kSortBlock) void sort_hist_kernel(Geom g, const int32_t* __restrict__ count,
-                                                               int32_t* __restrict__ hist, int nb) {
-  extern __shared__ int s_h[];
-  for (int v = threadIdx.x; v <= g.P; v += kSortBlock) s_h[v] = 0;
-  __syncthreads();
-  const int i = blockIdx.x * kSortBlock + threadIdx.x;
-  if (i < g.N) atomicAdd(&s_h[count[i]], 1);
-  __syncthreads();
-  for (int v = threadIdx.x; v <= g.P; v += kSortBlock) hist[(size_t)v * nb + blockIdx.x] = s_h[v];
+struct SortShape {
+  int B;     // batches
+  int nrow;  // rows per batch: ceil(N / B)
+  int nbb;   // sort blocks per batch: ceil(nrow / kSortBlock)
+};
+
+__device__ __forceinline__ int sort_patch(const Geom& g, const SortShape& ss, int b, int blk, int tid) {
+  const int r = blk * kSortBlock + tid;
+  const long long i = (long long)r * ss.B + b;
+  return (r < ss.nrow && i < g.N) ? (int)i : -1;
 }
 
-// one block per count value: exclusive scan over the blocks, total into bins[v]
-__global__ __launch_bounds__(1024) void sort_scan_kernel(int32_t* __restrict__ hist, int nb,
+__global__ __launch_bounds__(kSortBlock) void sort_hist_kernel(Geom g, SortShape ss,
+                                                               const int32_t* __restrict__ count,
+                                                               int32_t* __restrict__ hist) {
+  extern __shared__ int s_h[];
+  const int b = blockIdx.x / ss.nbb, blk = blockIdx.x % ss.nbb;
+  for (int v = threadIdx.x; v <= g.P; v += kSortBlock) s_h[v] = 0;
+  __syncthreads();
+  const int i = sort_patch(g, ss, b, blk, threadIdx.x);
+  if (i >= 0) atomicAdd(&s_h[count[i]], 1);
+  __syncthreads();
+  for (int v = threadIdx.x; v <= g.P; v += kSortBlock)
+    hist[((size_t)b * (g.P + 1) + v) * ss.nbb + blk] = s_h[v];
+}
+
+// one block per key (b, c): exclusive scan over b's blocks, total into bins[key]
+__global__ __launch_bounds__(1024) void sort_scan_kernel(int32_t* __restrict__ hist, int nbb,
                                                          int32_t* __restrict__ bins) {
   __shared__ int s_tot[1024];
-  const int t = block_scan_1024(hist + (size_t)blockIdx.x * nb, nb, s_tot);
+  const int t = block_scan_1024(hist + (size_t)blockIdx.x * nbb, nbb, s_tot);
   if (threadIdx.x == 0) bins[blockIdx.x] = t;
 }
 
@@ -192,32 +215,76 @@ __global__ __launch_bounds__(1024) void sort_bins_kernel(int nbins, int32_t* __r
   block_scan_1024(bins, nbins, s_tot);
 }
 
-__global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(Geom g, const int32_t* __restrict__ count,
+__global__ __launch_bounds__(kSortBlock) void sort_scatter_kernel(Geom g, SortShape ss,
+                                                                  const int32_t* __restrict__ count,
                                                                   const int32_t* __restrict__ hist,
                                                                   const int32_t* __restrict__ bins,
-                                                                  int nb, uint32_t* __restrict__ perm,
+                                                                  uint32_t* __restrict__ perm,
                                                                   int32_t* __restrict__ inv_perm) {
   __shared__ int s_c[kSortBlock];
-  const int i = blockIdx.x * kSortBlock + threadIdx.x;
-  const int c = i < g.N ? count[i] : -1;
+  const int b = blockIdx.x / ss.nbb, blk = blockIdx.x % ss.nbb;
+  const int i = sort_patch(g, ss, b, blk, threadIdx.x);
+  const int c = i >= 0 ? count[i] : -1;
   s_c[threadIdx.x] = c;
   __syncthreads();
-  if (i >= g.N) return;
+  if (i < 0) return;
   int rank = 0;
   for (int t = 0; t < (int)threadIdx.x; ++t) rank += s_c[t] == c;
-  const int slot = bins[c] + hist[(size_t)c * nb + blockIdx.x] + rank;
+  const size_t key = (size_t)b * (g.P + 1) + c;
+  const int slot = bins[key] + hist[key * ss.nbb + blk] + rank;
   perm[slot] = (uint32_t)i;
   inv_perm[i] = slot;
 }
 
-hipError_t launch_sort(const Geom& g, const Buffers& b, int Npad, hipStream_t st) {
-  (void)Npad;
-  const int nb = (g.N + kSortBlock - 1) / kSortBlock;
-  sort_hist_kernel<<<nb, kSortBlock, (g.P + 1) * sizeof(int), st>>>(g, b.obs_count, b.sort_hist, nb);
-  sort_scan_kernel<<<g.P + 1, 1024, 0, st>>>(b.sort_hist, nb, b.sort_bin);
-  sort_bins_kernel<<<1, 1024, 0, st>>>(g.P + 1, b.sort_bin);
-  sort_scatter_kernel<<<nb, kSortBlock, 0, st>>>(g, b.obs_count, b.sort_hist, b.sort_bin, nb, b.perm,
-                                                 b.inv_perm);
+hipError_t launch_sort(const Geom& g, const Buffers& b, int n_batches, hipStream_t st) {
+  SortShape ss;
+  ss.B = n_batches;
+  ss.nrow = (g.N + n_batches - 1) / n_batches;
+  ss.nbb = (ss.nrow + kSortBlock - 1) / kSortBlock;
+  const int blocks = n_batches * ss.nbb;
+  const int keys = n_batches * (g.P + 1);
+  sort_hist_kernel<<<blocks, kSortBlock, (g.P + 1) * sizeof(int), st>>>(g, ss, b.obs_count, b.sort_hist);
+  sort_scan_kernel<<<keys, 1024, 0, st>>>(b.sort_hist, ss.nbb, b.sort_bin);
+  sort_bins_kernel<<<1, 1024, 0, st>>>(keys, b.sort_bin);
+  sort_scatter_kernel<<<blocks, kSortBlock, 0, st>>>(g, ss, b.obs_count, b.sort_hist, b.sort_bin,
+                                                     b.perm, b.inv_perm);
+  return hipGetLastError();
+}
+
+// histogram entries the sort needs for n_batches batches
+size_t sort_hist_entries(const Geom& g, int n_batches) {
+  const long long nrow = (g.N + n_batches - 1) / n_batches;
+  const long long nbb = (nrow + kSortBlock - 1) / kSortBlock;
+  return (size_t)n_batches * (size_t)(g.P + 1) * (size_t)nbb;
+}
+
+// ---- mini-batch steps: the batch's new lists back into the current buffer ----
+
+// one thread per slot of the batch: the patch's list row (n_a entries and the
+// end marker) and its count, from the sweep's output buffer to its input
+__global__ __launch_bounds__(256) void list_copy_kernel(int K, int slot0, int nslots,
+                                                        const uint32_t* __restrict__ perm,
+                                                        const int2* __restrict__ src,
+                                                        const int32_t* __restrict__ nsrc,
+                                                        int2* __restrict__ dst,
+                                                        int32_t* __restrict__ ndst) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nslots) return;
+  const size_t i = perm[slot0 + s];
+  const int na = nsrc[i];
+  const int n = na < K ? na + 1 : K;
+  const int2* a = src + i * K;
+  int2* d = dst + i * K;
+  for (int e = 0; e < n; ++e) d[e] = a[e];
+  ndst[i] = na;
+}
+
+hipError_t launch_list_copy(const Geom& g, const Buffers& b, int from, int slot0, int nslots,
+                            hipStream_t st) {
+  if (nslots <= 0) return hipSuccess;
+  list_copy_kernel<<<(nslots + 255) / 256, 256, 0, st>>>(g.K, slot0, nslots, b.perm, b.list[from],
+                                                         b.nact[from], b.list[1 - from],
+                                                         b.nact[1 - from]);
   return hipGetLastError();
 }
 

@@ -3,6 +3,9 @@
 //   logit pi_k = ln G_A - ln G_B,  G_A ~ Ga(a/K + n_k), G_B ~ Ga(b(K-1)/K + N - n_k)
 //   gamma_s   ~ Ga(c + sum(z)/2, rate d + sum(w^2)/2)
 //   gamma_eps ~ Ga(e + sum|Obs|/2, rate f + sum(r^2)/2)
+// A mini-batch step (the epoch schedule's reading of the Time-to-solution
+// section) draws them given its batch of n_b patches with every count and
+// sum multiplied by s = N / n_b: n_k -> s n_k, N -> s n_b, and so on.
 // Gamma variates follow Marsaglia & Tsang (ACM TOMS 2000) in binary64: for
 // shape alpha >= 1, d = alpha - 1/3, c = 1/sqrt(9 d), x ~ N(0,1),
 // v = (1 + c x)^3, accept when ln u < x^2/2 + d - d v + d ln v; for alpha < 1
@@ -41,7 +44,7 @@ __device__ bool log_gamma_draw(double shape, uint32_t key0, uint32_t key1, uint3
 
 __global__ __launch_bounds__(256) void scalars_kernel(Geom g, double a, double b, double c,
                                                       double dd, double e, double f,
-                                                      int learn_dict, uint32_t key0,
+                                                      int learn_dict, StepBatch sb, uint32_t key0,
                                                       uint32_t key1, uint32_t pid,
                                                       int32_t* __restrict__ nk,
                                                       const double* __restrict__ sumr2_p,
@@ -87,20 +90,22 @@ __global__ __launch_bounds__(256) void scalars_kernel(Geom g, double a, double b
     if (i < K) {
       const double nki = (double)nk[i];
       double la = 0.0, lb = 0.0;
-      const bool oka = log_gamma_draw(a / K + nki, key0, key1, stream_word(kTagPiA, pid),
+      const double s = sb.scale;
+      const bool oka = log_gamma_draw(a / K + s * nki, key0, key1, stream_word(kTagPiA, pid),
                                       (uint32_t)i, t, &la);
-      const bool okb = log_gamma_draw(b * (K - 1) / K + (double)g.N - nki, key0, key1,
+      const bool okb = log_gamma_draw(b * (K - 1) / K + s * (double)sb.n_b - s * nki, key0, key1,
                                       stream_word(kTagPiB, pid), (uint32_t)i, t, &lb);
       if (!oka || !okb || !isfinite(la - lb)) bad |= 2;
       ell[i] = la - lb;
     } else if (i == K) {
-      const double shape = c + 0.5 * (double)s_z;
-      const double rate = dd + 0.5 * scal->sum_w2;
+      const double shape = c + 0.5 * (sb.scale * (double)s_z);
+      const double rate = dd + 0.5 * (sb.scale * scal->sum_w2);
       if (!log_gamma_draw(shape, key0, key1, stream_word(kTagGS, pid), 0u, t, &lg)) bad |= 2;
       s_gs = exp(lg) / rate;
     } else {
-      const double shape = e + 0.5 * (double)scal->n_obs;
-      const double rate = f + 0.5 * s_sr2;
+      const double nobs = sb.n_obs_b >= 0 ? (double)sb.n_obs_b : (double)scal->n_obs;
+      const double shape = e + 0.5 * (sb.scale * nobs);
+      const double rate = f + 0.5 * (sb.scale * s_sr2);
       if (!log_gamma_draw(shape, key0, key1, stream_word(kTagGE, pid), 0u, t, &lg)) bad |= 2;
       s_ge = exp(lg) / rate;
     }
@@ -149,9 +154,10 @@ __global__ __launch_bounds__(256) void scalars_kernel(Geom g, double a, double b
 }
 
 hipError_t launch_scalars(const Geom& g, const Buffers& b, const double* h, int learn_dict,
-                          uint32_t key0, uint32_t key1, uint32_t problem_id, hipStream_t st) {
-  scalars_kernel<<<1, 256, 0, st>>>(g, h[0], h[1], h[2], h[3], h[4], h[5], learn_dict, key0, key1,
-                                    problem_id, b.sw_cnt, b.sumr2_p, b.ell, b.Ck, b.scal);
+                          const StepBatch& sb, uint32_t key0, uint32_t key1, uint32_t problem_id,
+                          hipStream_t st) {
+  scalars_kernel<<<1, 256, 0, st>>>(g, h[0], h[1], h[2], h[3], h[4], h[5], learn_dict, sb, key0,
+                                    key1, problem_id, b.sw_cnt, b.sumr2_p, b.ell, b.Ck, b.scal);
   return hipGetLastError();
 }
 
