@@ -1,4 +1,7 @@
 """Helpers shared by the GPU parity tests (oracle on the CPU, HIP library on the GPU)."""
+import json
+import os
+
 import numpy as np
 
 import synth
@@ -47,3 +50,24 @@ def oracle_problem(y, m, patch, stride, K, seed, problem_id=0, **hyper):
     X, Mk = patches.extract(y, m, patch, stride)
     prm = ob.Params(K=K, seed=seed, problem_id=problem_id, **hyper)
     return prm, X, Mk
+
+
+def state_errors(gs, st):
+    """Relative errors against the binary64 oracle of every sampler output:
+    normwise for D, W and logit pi, relative for the two precisions."""
+    return {"D": rel_err(gs["D"], st.D), "W": rel_err(gs["W"], st.W),
+            "logit_pi": rel_err(gs["logit_pi"], st.ell),
+            "gamma_s": abs(gs["gamma_s"] / st.gamma_s - 1.0),
+            "gamma_eps": abs(gs["gamma_eps"] / st.gamma_eps - 1.0)}
+
+
+def record(config, **errors):
+    """Append one line of measured errors against binary64 to the file named by
+    the BPFA_PARITY_RECORD environment variable (nothing when it is unset)."""
+    path = os.environ.get("BPFA_PARITY_RECORD")
+    line = {"config": config}
+    line.update({k: (float(v) if isinstance(v, (float, np.floating)) else v) for k, v in errors.items()})
+    print("errors vs binary64:", json.dumps(line), flush=True)
+    if path:
+        with open(path, "a") as fh:
+            fh.write(json.dumps(line) + "\n")

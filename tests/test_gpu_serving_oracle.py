@@ -1,0 +1,100 @@
+"""The serving form against the binary64 oracle, in follow mode.
+
+One feed stream of the server runs four frames of changing shape and sampling
+through its resident dictionary state: every frame starts from zero codes and
+the stream's D, logit pi, gammas and Philox iteration counter, runs two
+sparse-coding iterations, and every second frame adds a dictionary
+iteration.  The same sequence is driven through a problem handle per frame,
+one iteration at a time, with the oracle following its z decisions
+(problem id = stream index, t continued across frames, the stream's prior
+draw as its first dictionary), and:
+
+* every served reconstruction equals the handle's bit for bit (the server
+  and the handle run the same kernels on the same state), and
+* the handle's state after every iteration and every frame's
+  reconstruction match the oracle's at the binary32 bar (BF16 form: 1e-4 on
+  the reconstruction, inside its 2e-2 bar).
+
+Together: each served frame matches the oracle driven through the stream's
+frames, which covers the dictionary blob's export and import between frames,
+the iteration counter carried across them and the stream id.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import bpfa as ob  # noqa: E402
+from oracle import patches  # noqa: E402
+from parity_util import FP32_TOL, assert_close, record, state_errors  # noqa: E402
+
+from paper_2311_15061_amd import bpfa, serve  # noqa: E402
+from test_gpu_parity import compare_state  # noqa: E402
+import synth  # noqa: E402
+
+PATCH = (6, 6)
+K = 24
+SEED = 0x5EED
+STREAM = 1
+SC_ITERS = 2
+DICT_EVERY = 2
+
+
+def stream_frames():
+    rng = np.random.Generator(np.random.PCG64(808))
+    wl = synth.workload("stem512")
+    out = []
+    for side, rho in ((40, 0.2), (52, 0.15), (34, 0.3), (46, 0.25)):
+        y, m, _ = synth.make_frame(wl, data_seed=int(rng.integers(1 << 30)), shape=(side, side),
+                                   rho=rho)
+        out.append((y.astype(np.float32), m))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_stream_matches_oracle_in_follow_mode(precision):
+    frames = stream_frames()
+    print("server stream %d: %d frames, %s" % (STREAM, len(frames), precision), flush=True)
+    srv = serve.Server(patch=PATCH, K=K, n_streams=3, sc_iters=SC_ITERS, dict_every=DICT_EVERY,
+                       max_slots=2, seed=SEED, precision=precision)
+    tickets = [srv.submit(STREAM, y, m)[0] for y, m in frames]
+    srv.drain()
+    res = {r["ticket"]: r for r in srv.poll()}
+    srv.close()
+
+    prm = ob.Params(K=K, seed=SEED, problem_id=STREAM)
+    st = ob.init_state(prm, 1, int(np.prod(PATCH)))
+    tol_x = FP32_TOL if precision == "fp32" else 1e-4
+    worst = {}
+    for f, (y, m) in enumerate(frames):
+        r = res[tickets[f]]
+        assert r["status"] == bpfa.OK and r["frame_index"] == f
+        learn_frame = (f + 1) % DICT_EVERY == 0
+        assert r["learned"] == int(learn_frame)
+        X, Mk = patches.extract(y.astype(np.float64), m, PATCH, (1, 1))
+        N = X.shape[0]
+        st = ob.State(D=st.D, W=np.zeros((N, K)), Z=np.zeros((N, K), bool), ell=st.ell,
+                      gamma_s=st.gamma_s, gamma_eps=st.gamma_eps, t=st.t)
+        # the first frame starts from the handle's own prior draw (the stream's
+        # first dictionary is that draw, made on the device), later ones from
+        # the state the previous frame's handle ended with
+        prob = bpfa.Problem(y, m, PATCH, K=K, seed=SEED, problem_id=STREAM)
+        prob.set_precision(precision)
+        if f > 0:
+            prob.set_state(D=gs["D"], logit_pi=gs["logit_pi"], gamma_s=gs["gamma_s"],
+                           gamma_eps=gs["gamma_eps"], t=gs["t"])
+        for learn in [False] * SC_ITERS + ([True] if learn_frame else []):
+            prob.iterate(1, bpfa.LEARN_DICT if learn else bpfa.SPARSE_CODE_ONLY)
+            gs = prob.get_state()
+            st, rep = ob.iterate(prm, X, Mk, st, learn_dict=learn, follow_z=gs["Z"])
+            assert rep.hard_mismatches == 0, "frame %d: %s" % (f, rep.hard_sites[:5])
+            compare_state(gs, st, FP32_TOL, "frame %d" % f)
+            for k, v in state_errors(gs, st).items():
+                worst[k] = max(worst.get(k, 0.0), v)
+        xh = prob.reconstruct()
+        prob.close()
+        assert np.array_equal(r["out"], xh), "served frame %d differs from the handle's" % f
+        ex = assert_close(xh, ob.reconstruct(st, y.shape, PATCH, (1, 1)), tol_x,
+                          "frame %d reconstruction" % f)
+        worst["recon"] = max(worst.get("recon", 0.0), ex)
+    record("serving stream, 4 frames 34-52 px, K=24, %s" % precision, **worst)
