@@ -44,6 +44,30 @@ def test_fully_sampled_known_dictionary_recovery():
     assert np.all(proj > 0.99), proj
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_one_to_one_recovery_from_a_prior_draw(seed):
+    """8 true atoms (P = 16), usage pi = 0.2, noise sigma = 0.1, all pixels
+    observed, K = 16 from a prior draw of D: after 200 iterations at least
+    7 of the 8 true atoms are matched one to one (Hungarian matching) with
+    |cos| > 0.95 and gamma_eps is within 10% of 1/sigma^2.  (At sigma = 0.01
+    the same chain mixes slowly -- atoms stay blended for hundreds of
+    iterations -- so that noise level pins the span above, not identity.)"""
+    from scipy.optimize import linear_sum_assignment
+    rng = np.random.Generator(np.random.PCG64(21 + seed))
+    Kt, P, N, sig = 8, 16, 2000, 0.1
+    Dt = rng.standard_normal((Kt, P))
+    Dt /= np.linalg.norm(Dt, axis=1, keepdims=True)
+    Zt = rng.random((N, Kt)) < 0.2
+    X = (Zt * rng.standard_normal((N, Kt))) @ Dt + sig * rng.standard_normal((N, P))
+    prm = bpfa.Params(K=16, seed=101 + seed)
+    st = bpfa.init_state(prm, N, P)
+    for _ in range(200):
+        st, _ = bpfa.iterate(prm, X, np.ones((N, P), bool), st)
+    cos = _matched_cos(Dt, st.D)
+    assert (cos > 0.95).sum() >= 7, cos
+    assert abs(st.gamma_eps * sig ** 2 - 1) < 0.10
+
+
 def test_true_dictionary_is_kept():
     """Started at the true atoms (plus 8 prior atoms), 100 iterations keep at
     least 7 of 8 true atoms matched one to one with |cos| > 0.95."""
