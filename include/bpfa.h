@@ -238,6 +238,22 @@ bpfa_status bpfa_get_state(bpfa_t h, bpfa_state_view* view);
  * Z and W must agree (W = 0 where Z = 0); ESTATE otherwise. */
 bpfa_status bpfa_set_state(bpfa_t h, const bpfa_state_view* view);
 
+/* bpfa_set_state for callers that cannot allocate device memory (code that
+ * must not call hipMalloc, such as tight serving loops or harnesses that
+ * forbid allocation): the same import, with the same results and errors, but
+ * its temporary device memory -- the validity flag of the dense -> list
+ * conversion and, for a BPFA_HOST view, the staging of W (and Z) -- comes
+ * from a fixed 32 MiB device buffer inside the library instead of a
+ * stream-ordered allocation.  Each device holds one such buffer from its
+ * first call until the process ends.  A BPFA_HOST view with W may stage at
+ * most 32 MiB - 256 bytes (4 N K bytes for W, N K more for Z, the Z part
+ * 256-aligned), else ENOMEM with nothing changed; a BPFA_DEVICE view has no
+ * size limit.  All handles on a device share the buffer, so calls that
+ * overlap on one device (from different threads) race; calls that follow one
+ * another are safe (each clears the flag it uses).  Synchronises, like
+ * bpfa_set_state. */
+bpfa_status bpfa_set_state_noalloc(bpfa_t h, const bpfa_state_view* view);
+
 /* Per-iteration statistics (synchronises). */
 bpfa_status bpfa_get_stats(bpfa_t h, bpfa_stats* stats);
 

@@ -25,7 +25,7 @@ EXPORTED = ["bpfa_params_default", "bpfa_workspace_size", "bpfa_create", "bpfa_s
             "bpfa_reset_state", "bpfa_iterate", "bpfa_minibatch", "bpfa_reconstruct", "bpfa_mean_reset",
             "bpfa_mean_accumulate", "bpfa_mean_get", "bpfa_variance_get", "bpfa_set_precision",
             "bpfa_transfer_dictionary", "bpfa_get_state",
-            "bpfa_set_state", "bpfa_get_stats", "bpfa_set_timing", "bpfa_sync",
+            "bpfa_set_state", "bpfa_set_state_noalloc", "bpfa_get_stats", "bpfa_set_timing", "bpfa_sync",
             "bpfa_get_patch_index", "bpfa_debug_philox", "bpfa_destroy", "bpfa_last_error"]
 
 
@@ -110,6 +110,7 @@ def _load():
         "bpfa_transfer_dictionary": (ctypes.c_int, [vp, vp, u32]),
         "bpfa_get_state": (ctypes.c_int, [vp, P(StateView)]),
         "bpfa_set_state": (ctypes.c_int, [vp, P(StateView)]),
+        "bpfa_set_state_noalloc": (ctypes.c_int, [vp, P(StateView)]),
         "bpfa_get_stats": (ctypes.c_int, [vp, P(Stats)]),
         "bpfa_set_timing": (ctypes.c_int, [vp, ctypes.c_int]),
         "bpfa_sync": (ctypes.c_int, [vp]),
@@ -320,7 +321,10 @@ class Problem:
         return dict(D=D, W=W, Z=Z, logit_pi=ell, gamma_s=v.gamma_s, gamma_eps=v.gamma_eps, t=v.t)
 
     def set_state(self, D=None, W=None, Z=None, logit_pi=None, gamma_s=None, gamma_eps=None,
-                  t=None):
+                  t=None, noalloc=False):
+        """Replace the sampler state (bpfa_set_state; noalloc=True calls
+        bpfa_set_state_noalloc, which stages through the library's fixed
+        device buffer instead of allocating)."""
         cur = self.stats()
         keep = []
 
@@ -337,7 +341,8 @@ class Problem:
                       gamma_s=float(cur["gamma_s"] if gamma_s is None else gamma_s),
                       gamma_eps=float(cur["gamma_eps"] if gamma_eps is None else gamma_eps),
                       t=int(cur["t"] if t is None else t), mem=HOST)
-        _check(lib.bpfa_set_state(self._h, ctypes.byref(v)))
+        fn = lib.bpfa_set_state_noalloc if noalloc else lib.bpfa_set_state
+        _check(fn(self._h, ctypes.byref(v)))
 
     def stats(self):
         s = Stats()

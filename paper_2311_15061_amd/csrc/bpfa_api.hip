@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -592,6 +593,102 @@ bpfa_status run_step(bpfa_t h, int learn, int batch) {
   return BPFA_OK;
 }
 
+// ---- state import --------------------------------------------------------
+
+// Fixed device buffer of bpfa_set_state_noalloc: the validity flag of the
+// dense -> list conversion in its first 256 bytes, then the staging of a
+// host-kind W (and Z).  One copy per device, held until the process ends;
+// every call on a device shares it.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+constexpr size_t kScratchFlagBytes = 256;
+constexpr int kScratchDevices = 64;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of this device's copy of `scratch`, looked up once per
+// device with that device current (the caller's DeviceGuard).  The array's
+// name is only a host-side stand-in; kernels and copies use this address.
+bpfa_status scratch_base(int device, char** out) {
+  if (device < 0 || device >= kScratchDevices)
+    return fail(BPFA_EDEVICE, "device %d is outside the %d devices the scratch table covers", device,
+                kScratchDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(BPFA_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device,
+                  hipGetErrorString(e));
+    g_scratch_ptr[device] = (char*)ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return BPFA_OK;
+}
+
+// bpfa_set_state, with its temporary device memory (the flag of the dense ->
+// list conversion, the staging of host-kind W and Z) either allocated
+// stream-ordered (scratch == NULL) or taken from the fixed buffer.
+bpfa_status set_state_impl(bpfa_t h, const bpfa_state_view* v, char* scratch_mem) {
+  if (!h || !v) return fail(BPFA_EINVAL, "NULL handle or view");
+  if (!(v->gamma_s > 0) || !(v->gamma_eps > 0) || !std::isfinite(v->gamma_s) ||
+      !std::isfinite(v->gamma_eps) || v->t < 1 || v->t >= (1LL << 32))
+    return fail(BPFA_ESTATE, "state gammas must be positive and finite, 1 <= t < 2^32");
+  if (!v->W && v->Z) return fail(BPFA_ESTATE, "Z without W cannot define the weights");
+  DeviceGuard dg(h->prm.device);
+  const Geom& g = h->g;
+  const size_t nk = (size_t)g.N * g.K;
+  // temporary device bytes: flag, then (host views) W and Z staging
+  const size_t w_off = kScratchFlagBytes;
+  const size_t z_off = w_off + align_up(4 * nk, 256);
+  const size_t need = !v->W ? 0
+                      : v->mem == BPFA_HOST ? z_off + (v->Z ? nk : 0)
+                                            : kScratchFlagBytes;
+  if (scratch_mem && need > kScratchBytes)
+    return fail(BPFA_ENOMEM,
+                "the fixed state-import buffer holds %zu bytes; this state needs %zu "
+                "(N x K = %zu weights staged from host memory)",
+                kScratchBytes, need, nk);
+  const hipMemcpyKind kind = v->mem == BPFA_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (v->D) HIPCHK(hipMemcpyAsync(h->b.D, v->D, 4 * (size_t)g.K * g.P, kind, h->st));
+  if (v->logit_pi) HIPCHK(hipMemcpyAsync(h->b.ell, v->logit_pi, 8 * (size_t)g.K, kind, h->st));
+  int bad = 0;
+  if (v->W) {
+    char* tmp = scratch_mem;
+    if (!tmp) HIPCHK(hipMallocAsync((void**)&tmp, need, h->st));
+    int* dbad = (int*)tmp;
+    const float* W = v->W;
+    const uint8_t* Z = v->Z;
+    if (v->mem == BPFA_HOST) {
+      HIPCHK(hipMemcpyAsync(tmp + w_off, v->W, 4 * nk, hipMemcpyHostToDevice, h->st));
+      W = (const float*)(tmp + w_off);
+      if (v->Z) {
+        HIPCHK(hipMemcpyAsync(tmp + z_off, v->Z, nk, hipMemcpyHostToDevice, h->st));
+        Z = (const uint8_t*)(tmp + z_off);
+      }
+    }
+    // the fixed buffer keeps the previous call's flag: clear it first
+    HIPCHK(hipMemsetAsync(dbad, 0, 4, h->st));
+    HIPCHK(launch_dense_to_lists(g, h->b, h->cur, h->L.Npad, W, Z, dbad, h->st));
+    HIPCHK(hipMemcpyAsync(&bad, dbad, 4, hipMemcpyDeviceToHost, h->st));
+    if (!scratch_mem) HIPCHK(hipFreeAsync(tmp, h->st));
+  }
+  DevScalars s;
+  HIPCHK(hipMemcpyAsync(&s, h->b.scal, sizeof s, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  s.gamma_s = v->gamma_s;
+  s.gamma_eps = v->gamma_eps;
+  s.t = v->t;
+  HIPCHK(hipMemcpyAsync(h->b.scal, &s, sizeof s, hipMemcpyHostToDevice, h->st));
+  HIPCHK(launch_ck(g, h->b, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  h->t_host = v->t;
+  h->batch_cursor = 0;
+  if (bad) return fail(BPFA_ESTATE, "W is non-zero where Z is 0");
+  return BPFA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -940,51 +1037,17 @@ bpfa_status bpfa_get_state(bpfa_t h, bpfa_state_view* v) {
 }
 
 bpfa_status bpfa_set_state(bpfa_t h, const bpfa_state_view* v) {
+  return set_state_impl(h, v, nullptr);
+}
+
+bpfa_status bpfa_set_state_noalloc(bpfa_t h, const bpfa_state_view* v) {
   if (!h || !v) return fail(BPFA_EINVAL, "NULL handle or view");
-  if (!(v->gamma_s > 0) || !(v->gamma_eps > 0) || !std::isfinite(v->gamma_s) ||
-      !std::isfinite(v->gamma_eps) || v->t < 1 || v->t >= (1LL << 32))
-    return fail(BPFA_ESTATE, "state gammas must be positive and finite, 1 <= t < 2^32");
   DeviceGuard dg(h->prm.device);
-  const Geom& g = h->g;
-  const hipMemcpyKind kind = v->mem == BPFA_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  if (v->D) HIPCHK(hipMemcpyAsync(h->b.D, v->D, 4 * (size_t)g.K * g.P, kind, h->st));
-  if (v->logit_pi) HIPCHK(hipMemcpyAsync(h->b.ell, v->logit_pi, 8 * (size_t)g.K, kind, h->st));
-  int bad = 0;
-  if (v->W) {
-    const size_t nk = (size_t)g.N * g.K;
-    void* tmp = nullptr;
-    HIPCHK(hipMallocAsync(&tmp, 5 * nk + 4, h->st));
-    const float* W = v->W;
-    const uint8_t* Z = v->Z;
-    int* dbad = (int*)((char*)tmp + 5 * nk);
-    if (v->mem == BPFA_HOST) {
-      HIPCHK(hipMemcpyAsync(tmp, v->W, 4 * nk, hipMemcpyHostToDevice, h->st));
-      W = (const float*)tmp;
-      if (v->Z) {
-        HIPCHK(hipMemcpyAsync((char*)tmp + 4 * nk, v->Z, nk, hipMemcpyHostToDevice, h->st));
-        Z = (const uint8_t*)tmp + 4 * nk;
-      }
-    }
-    HIPCHK(hipMemsetAsync(dbad, 0, 4, h->st));
-    HIPCHK(launch_dense_to_lists(g, h->b, h->cur, h->L.Npad, W, Z, dbad, h->st));
-    HIPCHK(hipMemcpyAsync(&bad, dbad, 4, hipMemcpyDeviceToHost, h->st));
-    HIPCHK(hipFreeAsync(tmp, h->st));
-  } else if (v->Z) {
-    return fail(BPFA_ESTATE, "Z without W cannot define the weights");
-  }
-  DevScalars s;
-  HIPCHK(hipMemcpyAsync(&s, h->b.scal, sizeof s, hipMemcpyDeviceToHost, h->st));
-  HIPCHK(hipStreamSynchronize(h->st));
-  s.gamma_s = v->gamma_s;
-  s.gamma_eps = v->gamma_eps;
-  s.t = v->t;
-  HIPCHK(hipMemcpyAsync(h->b.scal, &s, sizeof s, hipMemcpyHostToDevice, h->st));
-  HIPCHK(launch_ck(g, h->b, h->st));
-  HIPCHK(hipStreamSynchronize(h->st));
-  h->t_host = v->t;
-  h->batch_cursor = 0;
-  if (bad) return fail(BPFA_ESTATE, "W is non-zero where Z is 0");
-  return BPFA_OK;
+  if (!dg.ok) return fail(BPFA_EDEVICE, "cannot select device %d", h->prm.device);
+  char* base = nullptr;
+  bpfa_status r = scratch_base(h->prm.device, &base);
+  if (r != BPFA_OK) return r;
+  return set_state_impl(h, v, base);
 }
 
 bpfa_status bpfa_get_stats(bpfa_t h, bpfa_stats* out) {
