@@ -9,8 +9,10 @@ overlap-averaged reconstruction into HBM.
 
 value = patch-atom Gibbs updates per second over the whole step,
 N * K * 20 / (seconds per frame); frames/s is reported beside it.
-The roofline object describes the z/s sweep kernel, the dominant one; its
-duration comes from HIP events the library records around each sweep launch
+The roofline object describes the kernel that takes the most time per frame
+(the z/s sweep on the 512 x 512 frame, the dictionary-statistics kernel on
+the 1024 x 1024 frame and the video); `kernels` holds the roofline of both.
+Their durations come from HIP events the library records around each launch
 on the handle's stream during the timed region.
 """
 import argparse
@@ -28,6 +30,10 @@ sys.path.insert(0, ROOT)
 # per lane per clock; quarter-rate ops (transcendentals, 32x32->64 products) cost 4.
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 PEAK_HBM = 8.0e12
+# The statistics kernel adds 64-bit fixed-point terms into LDS accumulators:
+# one LDS atomic add of 8 bytes per term.  A CU's LDS moves 128 bytes per
+# clock, so at most 16 such adds per CU per clock: 256 x 16 x 2.4 GHz.
+PEAK_LDS_ADDS64 = 256 * 16 * 2.4e9
 
 
 def sweep_ops_per_update(obs_per_patch):
@@ -41,26 +47,58 @@ def sweep_ops_per_update(obs_per_patch):
     return 50.0 + 4.0 + 10.0 + 20.0 + 3.0 * obs_per_patch
 
 
-def kernel_source_hash():
+def stats_terms(n_active, n_obs):
+    """Algorithmic 64-bit accumulations of one dictionary-statistics launch:
+    every observed pixel of patch i (a visit) adds the n_a (n_a + 1) / 2
+    products w_j w_k (j <= k) of the patch's active atoms to C_p, its n_a
+    products w_k x_ip to B_p and x_ip^2 to the residual sum."""
+    import numpy as np
+    na = np.asarray(n_active, np.float64)
+    return float(np.sum(np.asarray(n_obs, np.float64) * (na * (na + 1) / 2 + na + 1)))
+
+
+def kernel_source_hash(names=("kernels_sweep.hip", "internal.hpp", "philox.hpp")):
     h = hashlib.sha256()
-    for name in ("kernels_sweep.hip", "internal.hpp", "philox.hpp"):
+    for name in names:
         with open(os.path.join(ROOT, "paper_2311_15061_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
-    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
-    or None when it is missing or was taken on a different sweep kernel source."""
-    path = os.path.join(ROOT, "profiles", "sweep_%s_pmc.json" % workload)
+STATS_SOURCES = ("kernels_dict.hip", "internal.hpp")
+
+
+def measured_traffic(workload, kernel="sweep"):
+    """HBM bytes per launch of the sweep (or the statistics kernel) from the
+    committed rocprofv3 counter summary, or None when it is missing or was
+    taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_pmc.json" % (kernel, workload))
     try:
         with open(path) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_hash") != kernel_source_hash():
+    names = STATS_SOURCES if kernel == "stats" else ("kernels_sweep.hip", "internal.hpp", "philox.hpp")
+    if rec.get("kernel_source_hash") != kernel_source_hash(names):
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def frame_stats_terms(prob, y_d, m_d, iters):
+    """Replays one frame (the timed steps are identical: same prior, frame and
+    Philox streams) and returns the statistics kernel's algorithmic terms per
+    launch, averaged over the frame's iterations."""
+    import numpy as np
+    from paper_2311_15061_amd import bpfa
+    _, n_obs = prob.patch_index()
+    prob.reset_state()
+    prob.set_frame(y_d, m_d, reset_codes=True)
+    total = 0.0
+    for _ in range(iters):
+        prob.iterate(1, bpfa.LEARN_DICT)
+        Z = prob.get_state()["Z"]
+        total += stats_terms(Z.sum(axis=1), n_obs)
+    return total / iters
 
 
 def cpu_baseline(wl, y, m, iters):
@@ -372,14 +410,29 @@ def main():
             "reconstruct": st["ms_recon"] / args.steps},
         "sweep_updates_per_s": N * K / (sweep_ms * 1e-3),
         "mean_active_atoms": st["mean_active"],
-        "roofline": {"kernel": "sweep_kernel", "bound": "alu", "achieved": achieved / 1e12,
-                     "peak": PEAK_LANE_OPS / 1e12, "unit": "TOP/s",
-                     "frac": achieved / PEAK_LANE_OPS,
-                     "traffic": traffic,
-                     "sweep_ms": sweep_ms,
-                     "ops_per_update": sweep_ops_per_update(obs_per_patch),
-                     "kernel_source_hash": kernel_source_hash()},
+        "phase_ms_per_frame_dict_stats": st["ms_dict_stats"] / args.steps,
     }
+    stats_ms = st["ms_dict_stats"] / max(st["n_sweeps"], 1)
+    terms = frame_stats_terms(prob, y_d, m_d, iters)
+    lds_achieved = terms / (stats_ms * 1e-3)
+    kernels = {
+        "sweep_kernel": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                         "unit": "TOP/s", "frac": achieved / PEAK_LANE_OPS, "traffic": traffic,
+                         "ms_per_launch": sweep_ms, "ms_per_frame": st["ms_sweep"] / args.steps,
+                         "ops_per_update": sweep_ops_per_update(obs_per_patch),
+                         "kernel_source_hash": kernel_source_hash()},
+        "dict_stats_kernel": {"bound": "lds", "achieved": lds_achieved / 1e12,
+                              "peak": PEAK_LDS_ADDS64 / 1e12, "unit": "T 64-bit LDS adds/s",
+                              "frac": lds_achieved / PEAK_LDS_ADDS64,
+                              "traffic": measured_traffic(args.workload, "stats"),
+                              "ms_per_launch": stats_ms,
+                              "ms_per_frame": st["ms_dict_stats"] / args.steps,
+                              "terms_per_launch": terms,
+                              "kernel_source_hash": kernel_source_hash(STATS_SOURCES)},
+    }
+    dominant = max(kernels, key=lambda k: kernels[k]["ms_per_frame"])
+    res["roofline"] = dict(kernel=dominant, **kernels[dominant])
+    res["kernels"] = kernels
     # the reconstruction's contraction in both precision forms, on the final state
     rec_ms = {}
     outs = {}

@@ -115,6 +115,7 @@ typedef struct {
   int32_t timing;           /* 1 if per-phase timing is on */
   double ms_index, ms_sweep, ms_dict, ms_scalars, ms_recon; /* accumulated, when timing is on */
   int64_t n_sweeps;         /* sweep launches timed */
+  double ms_dict_stats;     /* the dictionary-statistics kernel alone (part of ms_dict) */
 } bpfa_stats;
 
 /* Device bytes of state for these parameters (the caller may allocate them,

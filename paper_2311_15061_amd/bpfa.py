@@ -71,7 +71,8 @@ class Stats(ctypes.Structure):
                 ("max_obs", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("ms_index", ctypes.c_double), ("ms_sweep", ctypes.c_double),
                 ("ms_dict", ctypes.c_double), ("ms_scalars", ctypes.c_double),
-                ("ms_recon", ctypes.c_double), ("n_sweeps", ctypes.c_int64)]
+                ("ms_recon", ctypes.c_double), ("n_sweeps", ctypes.c_int64),
+                ("ms_dict_stats", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

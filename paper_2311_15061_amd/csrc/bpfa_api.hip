@@ -267,9 +267,11 @@ struct bpfa_problem {
   bool frame_ok = false;        // the last frame load completed (the index is whole)
   // timing
   bool timing = false;
-  std::vector<std::array<hipEvent_t, 4>> iter_events;
+  // per step: before / after the sweep, before / after the statistics kernel,
+  // after the dictionary draws, after the scalar draws
+  std::vector<std::array<hipEvent_t, 6>> iter_events;
   std::vector<std::array<hipEvent_t, 2>> index_events, recon_events;
-  double ms_index = 0, ms_sweep = 0, ms_dict = 0, ms_scalars = 0, ms_recon = 0;
+  double ms_index = 0, ms_sweep = 0, ms_dict = 0, ms_dict_stats = 0, ms_scalars = 0, ms_recon = 0;
   int64_t n_sweeps = 0;
 };
 
@@ -297,9 +299,11 @@ bpfa_status collect_timing(bpfa_problem* h) {
   for (auto& e : h->iter_events) {
     HIPCHK(hipEventElapsedTime(&ms, e[0], e[1]));
     h->ms_sweep += ms;
-    HIPCHK(hipEventElapsedTime(&ms, e[1], e[2]));
+    HIPCHK(hipEventElapsedTime(&ms, e[1], e[4]));
     h->ms_dict += ms;
     HIPCHK(hipEventElapsedTime(&ms, e[2], e[3]));
+    h->ms_dict_stats += ms;
+    HIPCHK(hipEventElapsedTime(&ms, e[4], e[5]));
     h->ms_scalars += ms;
     for (auto ev : e) (void)hipEventDestroy(ev);
     ++h->n_sweeps;
@@ -554,7 +558,7 @@ bpfa_status run_step(bpfa_t h, int learn, int batch) {
   a.nact_out = b.nact[1 - h->cur];
   a.cnt = b.sw_cnt;
   a.part = b.sw_part;
-  std::array<hipEvent_t, 4> ev{};
+  std::array<hipEvent_t, 6> ev{};
   bpfa_status r;
   if (h->timing && (r = record(h, &ev[0])) != BPFA_OK) return r;
   HIPCHK(launch_sweep(b.sweep_waves + w0, w1 - w0, L.sweep_lds, a, h->st));
@@ -568,25 +572,34 @@ bpfa_status run_step(bpfa_t h, int learn, int batch) {
     const int s0 = h->batch_slot0[batch];
     HIPCHK(launch_list_copy(g, b, 1 - h->cur, s0, h->batch_slot0[batch + 1] - s0, h->st));
   }
+  if (h->timing && (r = record(h, &ev[2])) != BPFA_OK) return r;
   if (learn) {
     DictPlan plan = L.plan;
     plan.chunks = h->dict_groups;
     plan.chunk_visits = h->dict_cv;
     plan.xcd = plan.chunks % 8 == 0;
     HIPCHK(launch_dict_stats(g, b, plan, h->cur, h->n_omega, nbat, bsel, h->st));
+  }
+  if (h->timing && (r = record(h, &ev[3])) != BPFA_OK) return r;
+  if (learn) {
+    const DictPlan& plan = L.plan;
+    DictPlan fp = plan;
+    fp.chunks = h->dict_groups;
+    fp.chunk_visits = h->dict_cv;
+    fp.xcd = fp.chunks % 8 == 0;
     if (g.K <= kChainLdsMaxK && plan.RG == 1) {
-      HIPCHK(launch_dict_reduce_chain_lds(g, b, plan, sb.scale, h->key0, h->key1,
+      HIPCHK(launch_dict_reduce_chain_lds(g, b, fp, sb.scale, h->key0, h->key1,
                                           stream_word(2, h->prm.problem_id), h->st));
     } else {
-      HIPCHK(launch_dict_reduce(g, b, plan, h->st));
+      HIPCHK(launch_dict_reduce(g, b, fp, h->st));
       HIPCHK(launch_dict_chain(g, b, L.plan, sb.scale, h->key0, h->key1,
                                stream_word(2, h->prm.problem_id), h->st));
     }
   }
-  if (h->timing && (r = record(h, &ev[2])) != BPFA_OK) return r;
+  if (h->timing && (r = record(h, &ev[4])) != BPFA_OK) return r;
   HIPCHK(launch_scalars(g, b, hyper, learn, sb, h->key0, h->key1, h->prm.problem_id, h->st));
   if (h->timing) {
-    if ((r = record(h, &ev[3])) != BPFA_OK) return r;
+    if ((r = record(h, &ev[5])) != BPFA_OK) return r;
     h->iter_events.push_back(ev);
   }
   ++h->t_host;
@@ -1078,6 +1091,7 @@ bpfa_status bpfa_get_stats(bpfa_t h, bpfa_stats* out) {
   out->ms_index = h->ms_index;
   out->ms_sweep = h->ms_sweep;
   out->ms_dict = h->ms_dict;
+  out->ms_dict_stats = h->ms_dict_stats;
   out->ms_scalars = h->ms_scalars;
   out->ms_recon = h->ms_recon;
   out->n_sweeps = h->n_sweeps;
@@ -1091,7 +1105,7 @@ bpfa_status bpfa_set_timing(bpfa_t h, int on) {
   bpfa_status r = collect_timing(h);
   if (r != BPFA_OK) return r;
   h->timing = on != 0;
-  h->ms_index = h->ms_sweep = h->ms_dict = h->ms_scalars = h->ms_recon = 0.0;
+  h->ms_index = h->ms_sweep = h->ms_dict = h->ms_dict_stats = h->ms_scalars = h->ms_recon = 0.0;
   h->n_sweeps = 0;
   return BPFA_OK;
 }

@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 from oracle import bpfa as ob  # noqa: E402
 from oracle import patches  # noqa: E402
-from parity_util import FP32_TOL, assert_close  # noqa: E402
+from parity_util import FP32_TOL, assert_close, record, rel_err, state_errors  # noqa: E402
 
 from paper_2311_15061_amd import bpfa  # noqa: E402
 import synth  # noqa: E402
@@ -50,6 +50,7 @@ def test_stem512_two_iterations_whole_frame():
     X, Mk = patches.extract(y, m, wl.patch, wl.stride)
     prob = _gpu(wl, y, m)
     st = ob.init_state(prm, X.shape[0], X.shape[1])
+    worst = {}
     for it in range(2):
         prob.iterate(1, bpfa.LEARN_DICT)
         gs = prob.get_state()
@@ -62,9 +63,13 @@ def test_stem512_two_iterations_whole_frame():
         assert abs(gs["gamma_s"] / st.gamma_s - 1) < FP32_TOL
         assert abs(gs["gamma_eps"] / st.gamma_eps - 1) < FP32_TOL
         assert np.all(np.abs(gs["logit_pi"] - st.ell) <= FP32_TOL * (1 + np.abs(st.ell)))
+        for k, v in state_errors(gs, st).items():
+            worst[k] = max(worst.get(k, 0.0), v)
     xh = prob.reconstruct()
-    assert_close(xh, ob.reconstruct(st, wl.shape, wl.patch, wl.stride), FP32_TOL, "reconstruction")
+    worst["recon"] = assert_close(xh, ob.reconstruct(st, wl.shape, wl.patch, wl.stride), FP32_TOL,
+                                  "reconstruction")
     prob.close()
+    record("stem512 whole frame, 2 iterations in follow mode, fp32", **worst)
 
 
 def _rows(image, mask, wl, rows):
@@ -119,7 +124,7 @@ def test_full_size_second_iteration_on_samples(name):
     print("%s: sampled sweep near-ties %d" % (name, rep.near_ties), flush=True)
     assert rep.hard_mismatches == 0, rep.hard_sites[:5]
     assert np.array_equal(g2["Z"][S].astype(bool), Z)
-    assert_close(g2["W"][S], W, FP32_TOL, "sampled W")
+    eW = assert_close(g2["W"][S], W, FP32_TOL, "sampled W")
 
     # dictionary draws of sampled positions, given the GPU's codes after the sweep
     cols = np.sort(rng.choice(P, size=6, replace=False))
@@ -130,7 +135,7 @@ def test_full_size_second_iteration_on_samples(name):
     sub = ob.State(D=D1[:, cols], W=W2, Z=g2["Z"].astype(bool), ell=g1["logit_pi"],
                    gamma_s=g1["gamma_s"], gamma_eps=g1["gamma_eps"], t=g1["t"])
     Dc, _ = ob.dictionary_update(prm, Mc, sub, W2, R, positions=cols, prior_P=P)
-    assert_close(g2["D"][:, cols], Dc, FP32_TOL, "sampled D columns")
+    eD = assert_close(g2["D"][:, cols], Dc, FP32_TOL, "sampled D columns")
 
     # pi and gamma draws from the whole-frame counts and sums
     ell = ob.pi_update(prm, g2["Z"].astype(bool), g1["t"])
@@ -140,3 +145,31 @@ def test_full_size_second_iteration_on_samples(name):
     r2, n_obs = _residual_sum_of_squares(y, m, wl, g2["W"], g2["D"].astype(np.float64))
     ged = ob.gamma_eps_update(prm, np.ones((1, n_obs), bool), np.sqrt(np.full((1, 1), r2)), g1["t"])
     assert abs(g2["gamma_eps"] / ged - 1) < FP32_TOL
+    record("%s iteration 2 on samples (1500 patches, 6 positions), fp32" % name,
+           W=eW, D=eD, logit_pi=rel_err(g2["logit_pi"], ell),
+           gamma_s=abs(g2["gamma_s"] / gsd - 1), gamma_eps=abs(g2["gamma_eps"] / ged - 1))
+
+
+def test_stem1024_precision_forms_at_full_size():
+    """The 1024 x 1024 frame (K = 256) after two iterations, reconstructed in both
+    precision forms from the same state: binary32 within 1e-5 of the binary64
+    overlap average of the GPU's state, the BF16 matrix-core form within the
+    BF16 bar 2e-2 and within 1e-4 (which holds only with its correction pass)."""
+    wl = synth.workload("stem1024")
+    y, m, g = synth.make_frame(wl)
+    prob = _gpu(wl, y, m)
+    prob.iterate(2, bpfa.LEARN_DICT)
+    gs = prob.get_state()
+    xs = {}
+    for prec in ("fp32", "bf16"):
+        prob.set_precision(prec)
+        xs[prec] = prob.reconstruct()
+    prob.close()
+    st = _state(gs)
+    ref = ob.reconstruct(st, wl.shape, wl.patch, wl.stride)
+    e32 = assert_close(xs["fp32"], ref, FP32_TOL, "binary32 reconstruction")
+    assert_close(xs["bf16"], ref, 2e-2, "bf16 reconstruction")
+    e16 = assert_close(xs["bf16"], ref, 1e-4, "bf16 reconstruction with its correction pass")
+    print("stem1024 reconstruction error vs binary64: fp32 %.3e, bf16 %.3e" % (e32, e16), flush=True)
+    record("stem1024 reconstruction from the GPU state after 2 iterations",
+           recon_fp32=e32, recon_bf16=e16, recon_bf16_vs_fp32=rel_err(xs["bf16"], xs["fp32"]))

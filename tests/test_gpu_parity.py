@@ -14,7 +14,8 @@ pytestmark = pytest.mark.gpu
 
 from oracle import bpfa as ob  # noqa: E402
 from oracle import patches, philox  # noqa: E402
-from parity_util import FP32_TOL, assert_close, case, oracle_problem, rel_err  # noqa: E402
+from parity_util import (FP32_TOL, assert_close, case, oracle_problem, record, rel_err,  # noqa: E402
+                         state_errors)
 
 from paper_2311_15061_amd import bpfa  # noqa: E402
 import synth  # noqa: E402
@@ -102,6 +103,7 @@ def run_follow(y, m, patch, stride, K, seed, iters, flags=bpfa.LEARN_DICT, state
                        gamma_eps=st.gamma_eps, t=st.t)
     ties = 0
     errs = []
+    worst = {}
     for it in range(iters):
         prob.iterate(1, flags)
         gs = prob.get_state()
@@ -111,6 +113,9 @@ def run_follow(y, m, patch, stride, K, seed, iters, flags=bpfa.LEARN_DICT, state
             it, rep.hard_mismatches, rep.hard_sites[:5])
         ties += rep.near_ties
         errs.append(compare_state(gs, st, tol, "iteration %d" % it))
+        for k, v in state_errors(gs, st).items():
+            worst[k] = max(worst.get(k, 0.0), v)
+    run_follow.worst = worst
     return prob, st, ties, errs
 
 
@@ -131,6 +136,7 @@ def test_trajectory_parity_lattice64_full_run():
     ref = ob.reconstruct(st, wl.shape, wl.patch, wl.stride)
     e = assert_close(xh, ref, FP32_TOL, "reconstruction")
     print("near-ties %d; final errors D %.2e W %.2e recon %.2e" % (ties, errs[-1][0], errs[-1][1], e))
+    record("lattice64 whole run, 10 iterations in follow mode, fp32", recon=e, **run_follow.worst)
     prob.close()
 
 
