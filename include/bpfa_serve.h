@@ -18,6 +18,13 @@
  * is deterministic and a stream's random numbers depend only on its own
  * counter (problem id = stream index, t continuing across its frames).
  *
+ * Each slot replays its frame body (patch index, iterations, state export,
+ * reconstruction) from a HIP graph captured on its second frame of a kind
+ * (with or without the dictionary iteration); the per-frame plan of the
+ * index is built on the device, so one graph serves every frame of the
+ * slot's shape, and a frame costs an upload, the state import, one graph
+ * launch and the result copy.
+ *
  * Threading: submit / poll / stats may be called from any thread; the server
  * runs one dispatcher thread and one worker thread per slot.
  */
@@ -46,12 +53,15 @@ typedef struct {
   uint64_t hbm_budget;             /* bytes of slot workspaces the server may hold */
   int32_t device;
   int32_t precision;               /* BPFA_FP32 or BPFA_BF16: contraction precision of every slot */
+  int32_t use_graphs;              /* 1: replay each slot's frame body from a captured HIP graph
+                                      (after one uncaptured frame of each kind); 0: launch directly.
+                                      Results are the same either way. */
 } bpfa_server_params;
 
 /* Defaults: 2-D 10 x 10 patches stride 1, K = 128, priors as bpfa_params_default,
  * 4 streams, 5 sparse-coding iterations, dictionary every 10 frames, 4 slots,
  * 16 GiB budget, device 0, binary32 reconstruction (BPFA_FP32; the BF16 form
- * is selectable and is slower on these sparse codes). */
+ * is selectable and is slower on these sparse codes), graph replay on. */
 void bpfa_server_params_default(bpfa_server_params* p);
 
 /* Start a server.  EINVAL / ESHAPE for bad parameters (ESHAPE also for
@@ -102,6 +112,8 @@ typedef struct {
   int64_t slots, slot_bytes;       /* live slots and their workspace bytes */
   int64_t peak_slot_bytes;
   int64_t slot_creations, slot_evictions;
+  int64_t graph_frames;            /* frames whose body was replayed from a captured graph */
+  int64_t graph_captures;          /* graphs captured (one per slot and kind of frame) */
 } bpfa_serve_stats;
 
 bpfa_status bpfa_server_stats(bpfa_server_t s, bpfa_serve_stats* st);

@@ -63,7 +63,7 @@ struct Layout {
   size_t sweep_lds = 0;
   DictPlan plan;
   // byte offsets
-  size_t image, mask, poff, pcoord, obs_bits, obs_count, perm, inv_perm, obs_idx, obs_val, sweep_waves, sort_hist, sort_bin,
+  size_t image, mask, poff, pcoord, obs_bits, obs_count, perm, inv_perm, obs_idx, obs_val, sweep_waves, fplan, sort_hist, sort_bin,
       omega, omega_c, omega_blk, vpatch, omega_y, D, list0, list1, nact0, nact1, Ck, ell, scal, nk, sw_cnt, sw_part, dpart,
       dx2, Cfull, Bvec, diag, x2p, sumr2_p, Y, recon, mean, mean2, total;
 };
@@ -142,8 +142,8 @@ DictPlan make_dict_plan(const Geom& g) {
   const long long room = (long long)kLdsBytes - (rec_max + kWave) * 8 - (long long)(K + 1) * 4;
   pl.chunk_visits = (int)std::max<long long>(
       kDictBlock, std::min<long long>(kDictBlock * kDictVpt, room / 10 / kDictBlock * kDictBlock));
-  // partial accumulators per (p, row group): set per frame from the observed
-  // pixels (bpfa_problem::dict_groups), at most this many
+  // chunk slots per (p, row group): the frame plan uses the first few of them,
+  // chosen on the device from the frame's observed pixels
   const long long mt = g.Mtot;
   pl.chunks = (int)std::min<long long>(16, std::max<long long>(1, (mt + pl.chunk_visits - 1) / pl.chunk_visits));
   if (pl.chunks > 1 && pl.chunks < 8) pl.chunks = 8;   // room for the XCD-aligned chunking
@@ -195,6 +195,7 @@ Layout make_layout(const Geom& g) {
   L.obs_idx = take(2 * (size_t)L.Jcap * Np);
   L.obs_val = take(4 * (size_t)L.Jcap * Np);
   L.sweep_waves = take(16 * (size_t)L.wave_cap);
+  L.fplan = take(sizeof(FramePlan));
   // the sort's histogram for up to kMaxBatches batches: each batch's sort
   // blocks hold ceil(N / B / 256) <= ceil(N / 256 / B) + 1 blocks' worth
   L.sort_hist = take(4 * (P + 1) * ((N + kSortBlock - 1) / kSortBlock + kMaxBatches));
@@ -244,23 +245,24 @@ struct bpfa_problem {
   bool own_stream = false;
   int cur = 0;
   int precision = BPFA_FP32;    // contraction precision of the reconstruction
-  int max_obs = 0, n_omega = 0;
-  int dict_groups = 1;          // statistics partials per (p, row group) for this frame
-  int dict_cv = 0;              // observed pixels per statistics chunk for this frame
+  int max_obs = 0, n_omega = 0;  // host copies from the last frame plan read back
   int n_cu = 256;               // compute units of the device
-  int n_waves = 0;              // sweep wavefronts of this frame
-  int jpad = 4;                 // obs rows written per slot for this frame
-  // pinned host staging (hipHostMalloc): the frame load's readback of the
-  // scalars and |Obs| bin starts, and the wavefront table it uploads, so the
-  // copies run as DMA without a pageable bounce
+  int sweep_grid = 0;           // blocks of a sweep launch (they stride over the 8-wave groups)
+  int dict_slots = 0;           // statistics blocks resident at once
+  // pinned host staging (hipHostMalloc) of the frame load's readback of the
+  // scalars and the frame plan, so the copy runs as DMA without a pageable bounce
   char* stage = nullptr;
   size_t stage_bytes = 0;
   // mini-batch partition of the slot order (patch i in batch i mod n_batches)
   int n_batches = 1;
   int batch_cursor = 0;            // batch of the next mini-batch step
+  // host copy of the mini-batch ranges of the plan (read back when a
+  // mini-batch step needs them: plan_known)
   std::vector<int> batch_slot0;    // n_batches + 1: first slot of each batch
   std::vector<int> batch_wave0;    // n_batches + 1: first wavefront of each batch
   std::vector<long long> batch_nobs;  // observed pixels of each batch
+  int dict_chunks = 0;             // statistics chunks of the frame
+  bool plan_known = false;
   uint32_t key0 = 0, key1 = 0;
   int64_t t_host = 1;
   int64_t mean_count = 0;       // samples in the posterior-mean running sum
@@ -342,154 +344,83 @@ bpfa_status check_status(bpfa_problem* h) {
   return BPFA_OK;
 }
 
-// Pinned staging of the frame load: the device scalars, the slot sort's key
-// offsets for `batches` batches, and the wavefront table.
-size_t stage_size(const Geom& g, const Layout& L, int batches) {
-  return align_up(sizeof(DevScalars), 16) + align_up(4 * ((size_t)g.P + 1) * batches, 16) +
-         16 * (size_t)L.wave_cap;
-}
-
-bpfa_status ensure_stage(bpfa_problem* h, int batches) {
-  const size_t need = stage_size(h->g, h->L, batches);
-  if (need <= h->stage_bytes) return BPFA_OK;
-  HIPCHK(hipStreamSynchronize(h->st));   // a pending upload may still read the old staging
-  if (h->stage) (void)hipHostFree(h->stage);
-  h->stage = nullptr;
-  h->stage_bytes = 0;
-  if (hipHostMalloc((void**)&h->stage, need, hipHostMallocDefault) != hipSuccess)
-    return fail(BPFA_ENOMEM, "hipHostMalloc of %zu staging bytes failed", need);
-  h->stage_bytes = need;
+// Host copies of the frame plan: sizes for the statistics and the mini-batch
+// ranges; ESHAPE when a patch has more than 256 observed pixels (the index
+// is then not usable and the frame load has failed).  Synchronises.
+bpfa_status read_plan(bpfa_problem* h) {
+  DevScalars* sp = reinterpret_cast<DevScalars*>(h->stage);
+  FramePlan* fp = reinterpret_cast<FramePlan*>(h->stage + align_up(sizeof(DevScalars), 16));
+  HIPCHK(hipMemcpyAsync(sp, h->b.scal, sizeof(DevScalars), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipMemcpyAsync(fp, h->b.plan, sizeof(FramePlan), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  h->max_obs = sp->max_obs;
+  h->n_omega = sp->n_omega;
+  if (fp->bad)
+    return fail(BPFA_ESHAPE, "a patch has %d observed pixels; at most 256 are supported", h->max_obs);
+  const int B = fp->n_batches;
+  h->batch_slot0.assign(fp->batch_slot0, fp->batch_slot0 + B + 1);
+  h->batch_wave0.assign(fp->batch_wave0, fp->batch_wave0 + B + 1);
+  h->batch_nobs.assign(fp->batch_nobs, fp->batch_nobs + B);
+  h->dict_chunks = fp->dict_chunks;
+  h->plan_known = true;
   return BPFA_OK;
 }
 
+// Pinned staging of the frame load's readback: the device scalars and the
+// frame plan.
+size_t stage_size() { return align_up(sizeof(DevScalars), 16) + sizeof(FramePlan); }
+
 // Slot order of the current frame for a partition into n_batches
-// mini-batches: sort by (batch, |Obs|), read the key offsets back (one host
-// synchronisation), fill the per-slot observed tables and build the sweep's
-// wavefront table, whose wavefronts never straddle two batches.  with_plan:
-// also size the dictionary-statistics launch from the frame's observed
-// pixels (a new frame).
-bpfa_status order_slots(bpfa_problem* h, int n_batches, bool with_plan) {
+// mini-batches, the frame plan (wavefront table, observed rows per slot,
+// statistics chunking, batch ranges) and the per-slot observed tables, all
+// built on the device: nothing the launches of an iteration need comes from
+// the host.  readback: read the scalars and the plan back (one host
+// synchronisation) to report a patch with more than 256 observed pixels
+// (ESHAPE) and keep host copies of the frame's sizes and batch ranges.
+bpfa_status order_slots(bpfa_problem* h, int n_batches, bool readback) {
   const Geom& g = h->g;
-  bpfa_status r = ensure_stage(h, n_batches);
-  if (r != BPFA_OK) return r;
   if (sort_hist_entries(g, n_batches) >
       (size_t)(g.P + 1) * ((g.N + kSortBlock - 1) / kSortBlock + kMaxBatches))
     return fail(BPFA_EINVAL, "sort histogram too small for %d batches", n_batches);
   HIPCHK(launch_sort(g, h->b, n_batches, h->st));
-  // (the synchronisation also retires the previous table upload before its
-  // staging is rewritten)
-  DevScalars* sp = reinterpret_cast<DevScalars*>(h->stage);
-  int32_t* bin_start = reinterpret_cast<int32_t*>(h->stage + align_up(sizeof(DevScalars), 16));
-  int4* wave_stage = reinterpret_cast<int4*>(h->stage + align_up(sizeof(DevScalars), 16) +
-                                             align_up(4 * ((size_t)g.P + 1) * n_batches, 16));
-  const size_t nkeys = (size_t)(g.P + 1) * n_batches;
-  HIPCHK(hipMemcpyAsync(sp, h->b.scal, sizeof(DevScalars), hipMemcpyDeviceToHost, h->st));
-  HIPCHK(hipMemcpyAsync(bin_start, h->b.sort_bin, 4 * nkeys, hipMemcpyDeviceToHost, h->st));
-  HIPCHK(hipStreamSynchronize(h->st));
-  const DevScalars s = *sp;   // bin_start[b (P + 1) + c]: first slot of batch b's |Obs| = c
-  h->max_obs = s.max_obs;
-  h->n_omega = s.n_omega;
-  if (with_plan) {
-    // The statistics blocks run in rounds of (CUs x blocks per CU): pick the
-    // chunk count c >= need that minimises rounds(c) / c, the time per visit,
-    // so that the last round is not a near-empty tail (ties: the smaller c,
-    // fewer partials to reduce).
-    const DictPlan& pl = h->L.plan;
-    const int need = std::min(pl.chunks, std::max(1, (h->n_omega + pl.chunk_visits - 1) / pl.chunk_visits));
-    auto cv_of = [&](int cc) {
-      const int per = (h->n_omega + cc - 1) / cc;
-      return std::min(pl.chunk_visits, std::max(kDictBlock, (per + kDictBlock - 1) / kDictBlock * kDictBlock));
-    };
-    int best = need;
-    double best_cost = 1e300;
-    for (int cc = need; cc <= pl.chunks; ++cc) {
-      const size_t lds = dict_stats_lds(g.K, h->L.rec_stride, cv_of(cc));
-      const long long slots = (long long)h->n_cu * std::max<long long>(1, (160 * 1024) / (long long)lds);
-      const long long blocks = (long long)g.P * pl.RG * cc;
-      const double cost = (double)((blocks + slots - 1) / slots) / cc;
-      if (cost < best_cost * (1.0 - 1e-9)) {
-        best_cost = cost;
-        best = cc;
-      }
-    }
-    h->dict_groups = best;
-    h->dict_cv = cv_of(best);
-  }
-  if (h->max_obs > 256)
-    return fail(BPFA_ESHAPE, "a patch has %d observed pixels; at most 256 are supported", h->max_obs);
-  const int J4 = std::max(4, (h->max_obs + 3) & ~3);
-  h->jpad = J4;
-  HIPCHK(launch_slots(g, h->b, h->L.Npad, J4, h->st));
-  // wavefront table of the sweep: within a batch, slots ascend in |Obs|; a
-  // wavefront takes consecutive slots of one batch and one lane count
-  // (sweep_lanes), 64 / lanes of them, and its register count J covers its
-  // last (largest) slot
-  h->batch_slot0.assign(n_batches + 1, g.N);
-  h->batch_wave0.assign(n_batches + 1, 0);
-  h->batch_nobs.assign(n_batches, 0);
-  long long n = 0;
-  for (int bt = 0; bt < n_batches; ++bt) {
-    const int32_t* bs = bin_start + (size_t)bt * (g.P + 1);
-    const int send = bt + 1 < n_batches ? bin_start[(size_t)(bt + 1) * (g.P + 1)] : g.N;
-    // end of |Obs| bin c of this batch
-    auto bin_end = [&](int c) { return c >= g.P ? send : bs[c + 1]; };
-    h->batch_slot0[bt] = bs[0];
-    h->batch_wave0[bt] = (int)n;
-    long long nobs = 0;
-    for (int c = 1; c <= g.P; ++c) nobs += (long long)c * (bin_end(c) - bs[c]);
-    h->batch_nobs[bt] = nobs;
-    // the |Obs| queries come in ascending slot order, so the bin is found by
-    // a pointer that only moves forward
-    int bin = 0;
-    auto count_of = [&](int slot) {
-      while (bin < g.P && bin_end(bin) <= slot) ++bin;
-      return bin;
-    };
-    auto first_above = [&](int c) { return c >= g.P ? send : bs[c + 1]; };
-    int slot = bs[0];
-    while (slot < send) {
-      const int lpp = sweep_lanes(count_of(slot));
-      const int climit = lpp == 1 ? 16 : lpp == 2 ? 32 : lpp == 4 ? 64 : lpp == 8 ? 128 : 256;
-      const int end = std::min({send, slot + kWave / lpp, first_above(climit)});
-      const int clast = count_of(end - 1);
-      int J = 16;
-      if (lpp == 1) J = std::max(4, (clast + 1) & ~1);
-      else if (lpp == 2 && clast <= 24) J = 12;
-      if (n >= h->L.wave_cap)
-        return fail(BPFA_EDEVICE, "sweep wavefront table overflow (> %lld)", h->L.wave_cap);
-      wave_stage[n++] = make_int4(slot, end - slot, lpp, J);
-      slot = end;
-    }
-  }
-  h->batch_slot0[n_batches] = g.N;
-  h->batch_wave0[n_batches] = (int)n;
-  h->n_waves = (int)n;
-  HIPCHK(hipMemcpyAsync(h->b.sweep_waves, wave_stage, 16 * (size_t)n, hipMemcpyHostToDevice, h->st));
+  const DictPlan& pl = h->L.plan;
+  HIPCHK(launch_frame_plan(g, h->b, n_batches, h->L.wave_cap, pl.chunks, pl.chunk_visits,
+                           h->dict_slots, g.P * pl.RG, h->st));
+  HIPCHK(launch_slots(g, h->b, h->L.Npad, h->st));
   h->n_batches = n_batches;
   h->batch_cursor = 0;
+  h->plan_known = false;
+  if (readback) return read_plan(h);
   return BPFA_OK;
 }
 
-// Upload a frame and rebuild the patch index.  keep_codes: the active lists
-// (stored by patch, not by slot) stay as they are; otherwise they are cleared.
-bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask, bpfa_mem mem,
-                       bool keep_codes) {
+// No active atoms in either list buffer (a fill kernel, not a memset, so the
+// sequence can be captured into a graph); the sweep then starts from buffer 0.
+bpfa_status clear_codes(bpfa_problem* h) {
+  HIPCHK(launch_fill_i32(h->b.nact[0], h->L.Npad, 0, h->st));
+  HIPCHK(launch_fill_i32(h->b.nact[1], h->L.Npad, 0, h->st));
+  h->cur = 0;
+  return BPFA_OK;
+}
+
+// Rebuild the patch index of the frame in the workspace.  keep_codes: the
+// active lists (stored by patch, not by slot) stay as they are; otherwise
+// they are cleared.  readback: finish with the plan readback (one host
+// synchronisation; ESHAPE for a patch with more than 256 observed pixels).
+// Without it the sequence is stream-ordered launches only (no
+// synchronisation, no memset, so it can be captured into a graph) and a
+// refused frame shows in the plan's `bad` flag.
+bpfa_status index_frame(bpfa_problem* h, bool keep_codes, bool readback) {
   const Geom& g = h->g;
   h->frame_ok = false;   // until every table of the new frame is built
-  bpfa_status r = upload(h, h->b.image, image, 4 * (size_t)g.Mtot, mem);
-  if (r != BPFA_OK) return r;
-  r = upload(h, h->b.mask, mask, (size_t)g.Mtot, mem);
-  if (r != BPFA_OK) return r;
+  bpfa_status r;
   std::array<hipEvent_t, 2> ev{};
   if (h->timing && (r = record(h, &ev[0])) != BPFA_OK) return r;
   HIPCHK(launch_index(g, h->b, h->L.Npad, h->st));
-  if (!keep_codes) {
-    HIPCHK(hipMemsetAsync(h->b.nact[0], 0, 4 * (size_t)h->L.Npad, h->st));
-    HIPCHK(hipMemsetAsync(h->b.nact[1], 0, 4 * (size_t)h->L.Npad, h->st));
-  }
+  if (!keep_codes && (r = clear_codes(h)) != BPFA_OK) return r;
   HIPCHK(launch_omega(g, h->b, h->st));
-  if ((r = order_slots(h, h->n_batches, true)) != BPFA_OK) return r;
-  HIPCHK(launch_visit_table(g, h->b, h->n_omega, h->st));
+  HIPCHK(launch_visit_table(g, h->b, h->st));
+  if ((r = order_slots(h, h->n_batches, readback)) != BPFA_OK) return r;
   if (h->timing) {
     if ((r = record(h, &ev[1])) != BPFA_OK) return r;
     h->index_events.push_back(ev);
@@ -498,10 +429,15 @@ bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask,
   return BPFA_OK;
 }
 
-bpfa_status clear_codes(bpfa_problem* h) {
-  HIPCHK(hipMemsetAsync(h->b.nact[0], 0, 4 * (size_t)h->L.Npad, h->st));
-  HIPCHK(hipMemsetAsync(h->b.nact[1], 0, 4 * (size_t)h->L.Npad, h->st));
-  return BPFA_OK;
+// Upload a frame and rebuild its patch index (with the plan readback).
+bpfa_status load_frame(bpfa_problem* h, const float* image, const uint8_t* mask, bpfa_mem mem,
+                       bool keep_codes) {
+  const Geom& g = h->g;
+  h->frame_ok = false;
+  bpfa_status r;
+  if ((r = upload(h, h->b.image, image, 4 * (size_t)g.Mtot, mem)) != BPFA_OK) return r;
+  if ((r = upload(h, h->b.mask, mask, (size_t)g.Mtot, mem)) != BPFA_OK) return r;
+  return index_frame(h, keep_codes, true);
 }
 
 bpfa_status check_iter_flags(bpfa_t h, uint32_t flags) {
@@ -524,11 +460,12 @@ bpfa_status run_step(bpfa_t h, int learn, int batch) {
   const Layout& L = h->L;
   Buffers& b = h->b;
   const double hyper[6] = {h->prm.a, h->prm.b, h->prm.c, h->prm.d, h->prm.e, h->prm.f};
-  int w0 = 0, w1 = h->n_waves, nbat = 1, bsel = 0;
+  // the sweep's wavefront range lives in the frame plan: all of it, or the batch's
+  const int* range = b.plan->all_waves;
+  int nbat = 1, bsel = 0;
   StepBatch sb{g.N, -1, 1.0};
   if (batch >= 0) {
-    w0 = h->batch_wave0[batch];
-    w1 = h->batch_wave0[batch + 1];
+    range = b.plan->batch_wave0 + batch;
     nbat = h->n_batches;
     bsel = batch;
     sb.n_b = h->batch_slot0[batch + 1] - h->batch_slot0[batch];
@@ -546,7 +483,7 @@ bpfa_status run_step(bpfa_t h, int learn, int batch) {
   a.key1 = h->key1;
   a.stream = stream_word(1, h->prm.problem_id);
   a.perm = b.perm;
-  a.Jpad = h->jpad;
+  a.plan = b.plan;
   a.obs_idx = b.obs_idx;
   a.obs_val = b.obs_val;
   a.D = b.D;
@@ -561,9 +498,17 @@ bpfa_status run_step(bpfa_t h, int learn, int batch) {
   std::array<hipEvent_t, 6> ev{};
   bpfa_status r;
   if (h->timing && (r = record(h, &ev[0])) != BPFA_OK) return r;
-  HIPCHK(launch_sweep(b.sweep_waves + w0, w1 - w0, L.sweep_lds, a, h->st));
+  // with the plan on the host one block per 8-wave group; otherwise (a
+  // captured sequence) the fixed grid that strides over them
+  if (h->plan_known) {
+    const int nw = batch >= 0 ? h->batch_wave0[batch + 1] - h->batch_wave0[batch] : h->batch_wave0.back();
+    HIPCHK(launch_sweep(b.sweep_waves, range, (nw + kSweepWaves - 1) / kSweepWaves, false, L.sweep_lds,
+                        a, h->st));
+  } else {
+    HIPCHK(launch_sweep(b.sweep_waves, range, h->sweep_grid, true, L.sweep_lds, a, h->st));
+  }
   if (h->timing && (r = record(h, &ev[1])) != BPFA_OK) return r;
-  HIPCHK(launch_sweep_reduce(g, b, (w1 - w0 + kSweepWaves - 1) / kSweepWaves, h->st));
+  HIPCHK(launch_sweep_reduce(g, b, range, h->st));
   if (batch < 0) {
     h->cur = 1 - h->cur;
   } else {
@@ -573,31 +518,23 @@ bpfa_status run_step(bpfa_t h, int learn, int batch) {
     HIPCHK(launch_list_copy(g, b, 1 - h->cur, s0, h->batch_slot0[batch + 1] - s0, h->st));
   }
   if (h->timing && (r = record(h, &ev[2])) != BPFA_OK) return r;
-  if (learn) {
-    DictPlan plan = L.plan;
-    plan.chunks = h->dict_groups;
-    plan.chunk_visits = h->dict_cv;
-    plan.xcd = plan.chunks % 8 == 0;
-    HIPCHK(launch_dict_stats(g, b, plan, h->cur, h->n_omega, nbat, bsel, h->st));
-  }
+  if (learn)
+    HIPCHK(launch_dict_stats(g, b, L.plan, h->plan_known ? h->dict_chunks : L.plan.chunks, h->cur, nbat,
+                             bsel, h->st));
   if (h->timing && (r = record(h, &ev[3])) != BPFA_OK) return r;
   if (learn) {
     const DictPlan& plan = L.plan;
-    DictPlan fp = plan;
-    fp.chunks = h->dict_groups;
-    fp.chunk_visits = h->dict_cv;
-    fp.xcd = fp.chunks % 8 == 0;
     if (g.K <= kChainLdsMaxK && plan.RG == 1) {
-      HIPCHK(launch_dict_reduce_chain_lds(g, b, fp, sb.scale, h->key0, h->key1,
+      HIPCHK(launch_dict_reduce_chain_lds(g, b, plan, sb.scale, h->key0, h->key1,
                                           stream_word(2, h->prm.problem_id), h->st));
     } else {
-      HIPCHK(launch_dict_reduce(g, b, fp, h->st));
+      HIPCHK(launch_dict_reduce(g, b, plan, h->st));
       HIPCHK(launch_dict_chain(g, b, L.plan, sb.scale, h->key0, h->key1,
                                stream_word(2, h->prm.problem_id), h->st));
     }
   }
   if (h->timing && (r = record(h, &ev[4])) != BPFA_OK) return r;
-  HIPCHK(launch_scalars(g, b, hyper, learn, sb, h->key0, h->key1, h->prm.problem_id, h->st));
+  HIPCHK(launch_scalars(g, b, hyper, learn, sb, h->key0, h->key1, h->st));
   if (h->timing) {
     if ((r = record(h, &ev[5])) != BPFA_OK) return r;
     h->iter_events.push_back(ev);
@@ -754,7 +691,7 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
       return bail(fail(BPFA_EDEVICE, "hipStreamCreate failed"));
     h->own_stream = true;
   }
-  h->stage_bytes = stage_size(g, h->L, 1);
+  h->stage_bytes = stage_size();
   if (hipHostMalloc((void**)&h->stage, h->stage_bytes, hipHostMallocDefault) != hipSuccess)
     return bail(fail(BPFA_ENOMEM, "hipHostMalloc of %zu staging bytes failed", h->stage_bytes));
   {
@@ -762,6 +699,19 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, params->device) ==
             hipSuccess && ncu > 0)
       h->n_cu = ncu;
+  }
+  {
+    // launch shapes fixed per handle: the sweep's grid strides over the
+    // frame's 8-wave groups with as many blocks as are resident at once (two
+    // per CU at 128 VGPRs unless the LDS tile allows fewer); the statistics
+    // blocks resident at once size the frame plan's chunk choice
+    const Layout& L = h->L;
+    const long long lds_cu = 160 * 1024;
+    const int sweep_per_cu = (int)std::max(1LL, std::min(2LL, lds_cu / (long long)L.sweep_lds));
+    h->sweep_grid = (int)std::min<long long>((L.wave_cap + kSweepWaves - 1) / kSweepWaves,
+                                             (long long)h->n_cu * sweep_per_cu);
+    const size_t dlds = dict_stats_lds(g.K, L.rec_stride, L.plan.chunk_visits);
+    h->dict_slots = h->n_cu * (int)std::max(1LL, lds_cu / (long long)dlds);
   }
   if (workspace) {
     if (ws_bytes < h->L.total)
@@ -786,6 +736,7 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
   b.obs_idx = (uint16_t*)(w + L.obs_idx);
   b.obs_val = (float*)(w + L.obs_val);
   b.sweep_waves = (int4*)(w + L.sweep_waves);
+  b.plan = (FramePlan*)(w + L.fplan);
   b.sort_hist = (int32_t*)(w + L.sort_hist);
   b.sort_bin = (int32_t*)(w + L.sort_bin);
   b.omega = (int32_t*)(w + L.omega);
@@ -830,6 +781,7 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
   s0.gamma_s = params->gamma_s0;
   s0.gamma_eps = params->gamma_eps0;
   s0.t = 1;
+  s0.problem_id = params->problem_id;
   std::vector<double> ell(g.K, g.K > 1 ? std::log(params->a / g.K) -
                                            std::log(params->b * (g.K - 1) / g.K)
                                      : 0.0);
@@ -900,8 +852,10 @@ bpfa_status bpfa_minibatch(bpfa_t h, int32_t n_batches, int32_t n_steps, uint32_
   DeviceGuard dg(h->prm.device);
   if (n_batches != h->n_batches) {
     h->frame_ok = false;   // until the new slot order is whole
-    if ((r = order_slots(h, n_batches, false)) != BPFA_OK) return r;
+    if ((r = order_slots(h, n_batches, true)) != BPFA_OK) return r;
     h->frame_ok = true;
+  } else if (!h->plan_known && (r = read_plan(h)) != BPFA_OK) {
+    return r;
   }
   for (int st = 0; st < n_steps; ++st) {
     if ((r = run_step(h, learn, h->batch_cursor)) != BPFA_OK) return r;
@@ -1179,7 +1133,12 @@ int problem_dims(bpfa_problem* h, int* K, int* P) {
   return BPFA_OK;
 }
 
-void problem_set_id(bpfa_problem* h, uint32_t problem_id) { h->prm.problem_id = problem_id; }
+int problem_set_id(bpfa_problem* h, uint32_t problem_id) {
+  DeviceGuard dg(h->prm.device);
+  h->prm.problem_id = problem_id;
+  HIPCHK(launch_set_t(h->b.scal, 0, problem_id, h->st, false));
+  return BPFA_OK;
+}
 
 int problem_export_dict(bpfa_problem* h, void* blob) {
   DeviceGuard dg(h->prm.device);
@@ -1202,11 +1161,57 @@ int problem_import_dict(bpfa_problem* h, const void* blob, long long t, uint32_t
   HIPCHK(hipMemcpyAsync(h->b.ell, b, 8 * (size_t)g.K, hipMemcpyDeviceToDevice, h->st));
   b += 8 * (size_t)g.K;
   HIPCHK(hipMemcpyAsync(&h->b.scal->gamma_s, b, 16, hipMemcpyDeviceToDevice, h->st));
-  HIPCHK(launch_set_t(h->b.scal, t, h->st));
+  // a new frame of the stream: its counter and id, and no failure recorded yet
+  HIPCHK(launch_set_t(h->b.scal, t, problem_id, h->st, true));
   HIPCHK(launch_ck(g, h->b, h->st));
   h->prm.problem_id = problem_id;
   h->t_host = t;
   return BPFA_OK;
 }
+
+int problem_upload_frame(bpfa_problem* h, const float* image, const uint8_t* mask) {
+  DeviceGuard dg(h->prm.device);
+  const Geom& g = h->g;
+  HIPCHK(hipMemcpyAsync(h->b.image, image, 4 * (size_t)g.Mtot, hipMemcpyHostToDevice, h->st));
+  HIPCHK(hipMemcpyAsync(h->b.mask, mask, (size_t)g.Mtot, hipMemcpyHostToDevice, h->st));
+  return BPFA_OK;
+}
+
+int problem_frame_body(bpfa_problem* h, int sc_iters, int learn) {
+  DeviceGuard dg(h->prm.device);
+  if (h->timing) return fail(BPFA_ESTATE, "a served frame runs without per-phase timing");
+  if (h->n_batches != 1) return fail(BPFA_ESTATE, "a served frame runs full-batch iterations");
+  bpfa_status r = index_frame(h, false, false);
+  if (r != BPFA_OK) return r;
+  for (int it = 0; it < sc_iters; ++it)
+    if ((r = run_step(h, 0, -1)) != BPFA_OK) return r;
+  if (learn && (r = run_step(h, 1, -1)) != BPFA_OK) return r;
+  HIPCHK(launch_recon(h->g, h->b, h->cur, h->L.Npad, (float*)(h->ws + h->L.recon),
+                      h->precision == BPFA_BF16, h->st));
+  return BPFA_OK;
+}
+
+int problem_frame_result(bpfa_problem* h, float* out) {
+  DeviceGuard dg(h->prm.device);
+  DevScalars* sp = reinterpret_cast<DevScalars*>(h->stage);
+  FramePlan* fp = reinterpret_cast<FramePlan*>(h->stage + align_up(sizeof(DevScalars), 16));
+  HIPCHK(hipMemcpyAsync(out, h->ws + h->L.recon, 4 * (size_t)h->g.Mtot, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipMemcpyAsync(sp, h->b.scal, sizeof(DevScalars), hipMemcpyDeviceToHost, h->st));
+  // the plan's leading scalars (through `bad`)
+  HIPCHK(hipMemcpyAsync(fp, h->b.plan, offsetof(FramePlan, dict_chunks), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  h->t_host = sp->t;
+  h->max_obs = sp->max_obs;
+  h->n_omega = sp->n_omega;
+  if (fp->bad) {
+    h->frame_ok = false;
+    return fail(BPFA_ESHAPE, "a patch has %d observed pixels; at most 256 are supported", sp->max_obs);
+  }
+  if (sp->status)
+    return fail(BPFA_ENUMERIC, "numeric failure in an iteration (flags %d)", sp->status);
+  return BPFA_OK;
+}
+
+hipStream_t problem_stream(bpfa_problem* h) { return h->st; }
 
 }  // namespace bpfa

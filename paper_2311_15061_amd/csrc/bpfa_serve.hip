@@ -4,14 +4,21 @@
 // frame whose stream is idle as soon as a slot of its shape is free; slots
 // (a problem handle with its own HIP stream and workspace) are created while
 // the HBM budget allows and idle slots of other shapes are evicted to make
-// room.  One worker thread per slot runs a frame: upload and index the frame,
-// load the stream's dictionary state, sparse-coding iterations (plus one
-// dictionary iteration every dict_every-th frame), save the state back,
-// reconstruct into the caller's buffer.  Slots work on separate streams, so
-// frames of different feed streams overlap on the device.
+// room.  One worker thread per slot runs a frame: upload the frame, load the
+// stream's dictionary state, then the frame body -- patch index,
+// sparse-coding iterations (plus one dictionary iteration every
+// dict_every-th frame), the reconstruction -- then save the state into the
+// stream's second blob and copy the reconstruction into the caller's buffer.
+// Nothing in the body depends on host knowledge of the frame (the per-frame
+// plan lives on the device), so after the first frame of each kind a slot
+// captures the body into a HIP graph and replays it for every later frame
+// of that kind: one launch instead of ~40, and no host round trip between
+// upload and result.  Slots work on separate streams, so frames of different
+// feed streams overlap on the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -49,8 +56,14 @@ struct Frame {
 struct Slot {
   std::vector<int64_t> shape;
   bpfa_t h = nullptr;
-  void* staging = nullptr;    // device blob the frame's state is saved into before it is known good
   size_t bytes = 0;
+  // the frame body as a replayable graph per kind of frame (0: sparse coding
+  // only, 1: with the dictionary iteration); the first frame of a kind runs
+  // uncaptured, the second is captured
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  int runs[2] = {0, 0};
+  bool graphs_ok = true;      // a capture failed: this slot runs uncaptured from then on
+  int64_t graph_frames = 0, captures = 0;
   bool busy = false;
   bool stop = false;
   Frame* job = nullptr;
@@ -60,6 +73,7 @@ struct Slot {
 
 struct StreamState {
   void* blob = nullptr;       // device: D, logit pi, gammas
+  void* pending = nullptr;    // device: where a frame saves its state until it is known good
   long long t = 1;
   int64_t frames = 0;
   bool busy = false;
@@ -79,6 +93,7 @@ struct bpfa_server {
   uint64_t next_ticket = 1;
   int64_t submitted = 0, completed = 0, failed = 0, in_flight = 0, queued = 0;
   int64_t slot_bytes = 0, peak_slot_bytes = 0, creations = 0, evictions = 0;
+  int64_t graph_frames = 0, captures = 0;   // of destroyed slots (live slots keep their own)
   bool stopping = false;
   std::thread dispatcher;
 };
@@ -128,25 +143,66 @@ void finish(bpfa_server* s, Frame* f, int status, bool learned) {
   delete f;
 }
 
-// one frame on a slot (called by the slot's worker without the server lock).
-// The updated state goes to the slot's staging blob; the caller swaps it in as
-// the stream's state only when the frame succeeded, so a frame whose draws
-// failed (ENUMERIC) leaves the stream at its last good state and iteration.
-int run_frame(bpfa_server* s, Slot* sl, Frame* f, StreamState* ss) {
-  const bpfa_server_params& p = s->prm;
+// The frame body on the slot's stream: replayed from the slot's graph for this
+// kind of frame when one is captured; otherwise run directly, and captured
+// on the way when this kind has run once before (the direct run also sets
+// the kernels' launch attributes) and graphs are on.  A capture that fails
+// leaves the slot on direct runs.
+int run_body(bpfa_server* s, Slot* sl, int learn) {
   bpfa_t h = sl->h;
-  int st = bpfa_set_frame(h, f->img, f->mask, BPFA_HOST, 1);
+  const int sc = s->prm.sc_iters;
+  hipStream_t hs = bpfa::problem_stream(h);
+  if (sl->exec[learn]) {
+    ++sl->graph_frames;
+    return hipGraphLaunch(sl->exec[learn], hs) == hipSuccess ? BPFA_OK : BPFA_EDEVICE;
+  }
+  const bool capture = s->prm.use_graphs && sl->graphs_ok && sl->runs[learn] >= 1;
+  ++sl->runs[learn];
+  if (!capture) return bpfa::problem_frame_body(h, sc, learn);
+  if (hipStreamBeginCapture(hs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    sl->graphs_ok = false;
+    (void)hipGetLastError();
+    return bpfa::problem_frame_body(h, sc, learn);
+  }
+  const int st = bpfa::problem_frame_body(h, sc, learn);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(hs, &graph);
+  hipGraphExec_t ex = nullptr;
+  const bool ok = st == BPFA_OK && e == hipSuccess && graph != nullptr &&
+                  hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0) == hipSuccess;
+  if (graph) (void)hipGraphDestroy(graph);
+  if (!ok) {
+    (void)hipGetLastError();
+    sl->graphs_ok = false;
+    return bpfa::problem_frame_body(h, sc, learn);
+  }
+  sl->exec[learn] = ex;
+  ++sl->captures;
+  ++sl->graph_frames;
+  return hipGraphLaunch(ex, hs) == hipSuccess ? BPFA_OK : BPFA_EDEVICE;
+}
+
+// one frame on a slot (called by the slot's worker without the server lock).
+// The updated state goes to the stream's pending blob (outside the graph:
+// the blobs belong to streams, a slot serves any stream); the caller swaps
+// it in as the stream's state only when the frame succeeded, so a frame that
+// was refused (ESHAPE) or whose draws failed (ENUMERIC) leaves the stream at
+// its last good state and iteration.
+int run_frame(bpfa_server* s, Slot* sl, Frame* f, StreamState* ss) {
+  bpfa_t h = sl->h;
+  int st = bpfa::problem_upload_frame(h, f->img, f->mask);
   if (st != BPFA_OK) return st;
   st = bpfa::problem_import_dict(h, ss->blob, f->t0, (uint32_t)f->stream);
   if (st != BPFA_OK) return st;
-  st = bpfa_iterate(h, p.sc_iters, BPFA_SPARSE_CODE_ONLY);
-  if (st == BPFA_OK && f->learn) st = bpfa_iterate(h, 1, BPFA_LEARN_DICT);
-  if (st != BPFA_OK) return st;
-  st = bpfa::problem_export_dict(h, sl->staging);
-  if (st != BPFA_OK) return st;
-  // synchronises the slot's stream and reports a numeric failure of any
-  // iteration of this frame
-  return bpfa_reconstruct(h, f->out, BPFA_HOST);
+  st = run_body(s, sl, f->learn ? 1 : 0);
+  if (st == BPFA_OK) st = bpfa::problem_export_dict(h, ss->pending);
+  if (st != BPFA_OK) {
+    (void)hipStreamSynchronize(bpfa::problem_stream(h));   // the frame's buffers stay valid until then
+    return st;
+  }
+  // synchronises the slot's stream; reports a refused frame or a numeric
+  // failure of any iteration of this frame
+  return bpfa::problem_frame_result(h, f->out);
 }
 
 void worker_loop(bpfa_server* s, Slot* sl) {
@@ -161,7 +217,7 @@ void worker_loop(bpfa_server* s, Slot* sl) {
     lk.lock();
     const bool learned = f->learn;
     if (st == BPFA_OK) {
-      std::swap(ss->blob, sl->staging);   // the frame's state becomes the stream's
+      std::swap(ss->blob, ss->pending);   // the frame's state becomes the stream's
       ss->t = f->t0 + s->prm.sc_iters + (learned ? 1 : 0);
     }
     ss->busy = false;
@@ -176,8 +232,9 @@ void worker_loop(bpfa_server* s, Slot* sl) {
 
 void destroy_slot(Slot* sl) {
   if (sl->worker.joinable()) sl->worker.join();
+  for (auto& ex : sl->exec)
+    if (ex) (void)hipGraphExecDestroy(ex);
   if (sl->h) bpfa_destroy(sl->h);
-  if (sl->staging) (void)hipFree(sl->staging);
   delete sl;
 }
 
@@ -215,6 +272,8 @@ Slot* acquire_slot(bpfa_server* s, const std::vector<int64_t>& shape, size_t nee
     s->slots.erase(it);
     s->slot_bytes -= (int64_t)ev->bytes;
     ++s->evictions;
+    s->graph_frames += ev->graph_frames;
+    s->captures += ev->captures;
     ev->stop = true;
     ev->cv.notify_all();
     lk.unlock();
@@ -237,13 +296,8 @@ Slot* acquire_slot(bpfa_server* s, const std::vector<int64_t>& shape, size_t nee
   std::vector<float> zimg((size_t)px, 0.f);
   std::vector<uint8_t> zmask((size_t)px, 0);
   bpfa_t h = nullptr;
-  void* staging = nullptr;
   int st = bpfa_create(&fp, nullptr, 0, zimg.data(), zmask.data(), BPFA_HOST, &h);
   if (st == BPFA_OK) st = bpfa_set_precision(h, (uint32_t)s->prm.precision);
-  if (st == BPFA_OK && hipMalloc(&staging, bpfa::dict_blob_bytes(s->K, s->P)) != hipSuccess) {
-    staging = nullptr;
-    st = BPFA_ENOMEM;
-  }
   if (st != BPFA_OK && h) {
     bpfa_destroy(h);
     h = nullptr;
@@ -257,7 +311,6 @@ Slot* acquire_slot(bpfa_server* s, const std::vector<int64_t>& shape, size_t nee
     return nullptr;
   }
   sl->h = h;
-  sl->staging = staging;
   sl->busy = false;
   sl->worker = std::thread(worker_loop, s, sl);
   return sl;
@@ -349,6 +402,7 @@ void bpfa_server_params_default(bpfa_server_params* p) {
   p->max_slots = 4;
   p->hbm_budget = 16ull << 30;
   p->precision = BPFA_FP32;
+  p->use_graphs = 1;
 }
 
 bpfa_status bpfa_server_create(const bpfa_server_params* p, bpfa_server_t* out) {
@@ -390,7 +444,8 @@ bpfa_status bpfa_server_create(const bpfa_server_params* p, bpfa_server_t* out) 
   for (int n = 0; n < p->n_streams; ++n) {
     StreamState& ss = s->streams[n];
     bpfa::problem_set_id(h0, (uint32_t)n);
-    if (hipMalloc(&ss.blob, blob) != hipSuccess || bpfa_reset_state(h0) != BPFA_OK ||
+    if (hipMalloc(&ss.blob, blob) != hipSuccess || hipMalloc(&ss.pending, blob) != hipSuccess ||
+        bpfa_reset_state(h0) != BPFA_OK ||
         bpfa::problem_export_dict(h0, ss.blob) != BPFA_OK) {
       bpfa_destroy(h0);
       bpfa_server_destroy(s);
@@ -492,6 +547,12 @@ bpfa_status bpfa_server_stats(bpfa_server_t s, bpfa_serve_stats* st) {
   st->peak_slot_bytes = s->peak_slot_bytes;
   st->slot_creations = s->creations;
   st->slot_evictions = s->evictions;
+  st->graph_frames = s->graph_frames;
+  st->graph_captures = s->captures;
+  for (Slot* sl : s->slots) {
+    st->graph_frames += sl->graph_frames;
+    st->graph_captures += sl->captures;
+  }
   return BPFA_OK;
 }
 
@@ -520,6 +581,7 @@ void bpfa_server_destroy(bpfa_server_t s) {
       delete f;
     }
     if (ss.blob) (void)hipFree(ss.blob);
+    if (ss.pending) (void)hipFree(ss.pending);
   }
   delete s;
 }

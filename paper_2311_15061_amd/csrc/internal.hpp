@@ -49,7 +49,32 @@ struct DevScalars {
   float wmax;             // max |w| after the last sweep
   float ymax;             // max |y| over observed pixels
   int n_omega;            // number of observed pixels
-  int pad_;
+  uint32_t problem_id;    // Philox stream id: the kernels form their stream words from it,
+                          // so a captured launch sequence serves any problem id
+};
+
+// lane classes of the sweep: patches with |Obs| in [lo, hi] get `lanes` lanes
+constexpr int kLaneClasses = 5;
+
+// Per-frame plan, built on the device from the slot sort and the frame's
+// scalars, so that no launch of an iteration depends on host knowledge of the
+// frame (the sweep and statistics grids are fixed per handle and read their
+// ranges from here).
+struct FramePlan {
+  int all_waves[2];                 // wavefront range of a full sweep: [0, n_waves)
+  int jpad;                         // observed rows per slot the slot tables write (>= 4, mult. of 4)
+  int bad;                          // 1: a patch has more than 256 observed pixels
+  int dict_chunks;                  // statistics partials per (p, row group) for this frame
+  int dict_cv;                      // observed pixels per statistics chunk
+  int dict_xcd;                     // dict_chunks is a multiple of 8: XCD-aligned chunk mapping
+  int n_batches;
+  int batch_wave0[kMaxBatches + 1]; // first wavefront of each mini-batch (+ the total)
+  int batch_slot0[kMaxBatches + 1]; // first slot of each mini-batch (+ N)
+  long long batch_nobs[kMaxBatches];
+  // per (batch, lane class): first slot, end slot, first wavefront (+ the total)
+  int cls_s0[kMaxBatches * kLaneClasses];
+  int cls_s1[kMaxBatches * kLaneClasses];
+  int cls_w0[kMaxBatches * kLaneClasses + 1];
 };
 
 struct SweepPart {
@@ -62,9 +87,10 @@ struct SweepPart {
 // Arguments of the z/s sweep.
 struct SweepArgs {
   int N, Npad, P, K, KT, KS;     // KT atoms per LDS tile, KS = KT + 1 (odd column stride)
-  uint32_t key0, key1, stream;   // Philox key and stream word (tag | problem_id << 8)
+  uint32_t key0, key1, stream;   // Philox key and stream word (tag | problem_id << 8; the
+                                 // kernel takes problem_id from the device scalars)
   const uint32_t* perm;          // slot -> patch
-  int Jpad;                      // obs rows written per slot (padding rows hold P / 0)
+  const FramePlan* plan;         // jpad: obs rows written per slot (padding rows hold P / 0)
   const uint16_t* obs_idx;       // [J][Npad] pixel offset p in the patch (P = padding)
   const float* obs_val;          // [J][Npad] observed value (0 = padding)
   const float* D;                // K x P
@@ -90,6 +116,7 @@ struct Buffers {
   uint16_t* obs_idx = nullptr;   // [Jcap][Npad]
   float* obs_val = nullptr;      // [Jcap][Npad]
   int4* sweep_waves = nullptr;   // per-frame wavefront table (first slot, slots, lanes per slot, J)
+  FramePlan* plan = nullptr;
   int32_t* sort_hist = nullptr;  // [batch][P + 1][sort blocks of the batch]
   int32_t* sort_bin = nullptr;   // [batch][P + 1]: key totals, then key offsets
   int32_t* omega = nullptr;      // observed pixel indices, ascending (Mtot capacity)
@@ -147,13 +174,27 @@ inline size_t sweep_lds_bytes(int P, int KS, int K) {
 
 // ---- launchers (each checks its own launch and returns the HIP status) ----
 hipError_t launch_index(const Geom& g, const Buffers& b, int Npad, hipStream_t st);
-hipError_t launch_slots(const Geom& g, const Buffers& b, int Npad, int Jcap4, hipStream_t st);
+// slot tables: rows up to the plan's jpad
+hipError_t launch_slots(const Geom& g, const Buffers& b, int Npad, hipStream_t st);
 hipError_t launch_omega(const Geom& g, const Buffers& b, hipStream_t st);
-hipError_t launch_visit_table(const Geom& g, const Buffers& b, int n_omega, hipStream_t st);
+// p[0 .. n) = v (a kernel, so that it can be captured into a graph)
+hipError_t launch_fill_i32(int32_t* p, long long n, int32_t v, hipStream_t st);
+// visit table over the frame's observed pixels (count read on the device)
+hipError_t launch_visit_table(const Geom& g, const Buffers& b, hipStream_t st);
+// Frame plan and wavefront table from the slot sort of n_batches batches.
+// Statistics chunking: the launch is sized for `dict_chunks_max` chunks of
+// `dict_cv_max` observed pixels for each of `dict_npr` (position, row group)
+// pairs; `dict_slots` blocks of it run at once.
+hipError_t launch_frame_plan(const Geom& g, const Buffers& b, int n_batches, long long wave_cap,
+                             int dict_chunks_max, int dict_cv_max, int dict_slots, int dict_npr,
+                             hipStream_t st);
 hipError_t launch_init_dict(const Geom& g, const Buffers& b, uint32_t key0, uint32_t key1,
                             uint32_t stream, hipStream_t st);
-hipError_t launch_sweep(const int4* waves, int nwaves, size_t lds, const SweepArgs& a,
-                        hipStream_t st);
+// the sweep over the wavefronts [range[0], range[1]) of the table (a device
+// pair): `blocks` blocks, one per 8-wave group, or (strided) a fixed grid of
+// `blocks` blocks that stride over the groups
+hipError_t launch_sweep(const int4* waves, const int* range, int blocks, bool strided, size_t lds,
+                        const SweepArgs& a, hipStream_t st);
 // lanes per patch of the sweep for a patch with c observed pixels
 inline int sweep_lanes(int c) { return c <= 16 ? 1 : c <= 32 ? 2 : c <= 64 ? 4 : c <= 128 ? 8 : 16; }
 // wavefronts the sweep table can need for N slots: at least 4 slots per wave
@@ -165,10 +206,14 @@ size_t sort_hist_entries(const Geom& g, int n_batches);
 // copy the new lists of slots slot0 .. slot0 + nslots - 1 from buffer `from` to the other
 hipError_t launch_list_copy(const Geom& g, const Buffers& b, int from, int slot0, int nslots,
                             hipStream_t st);
-hipError_t launch_sweep_reduce(const Geom& g, const Buffers& b, int blocks, hipStream_t st);
+// block partials of the sweep over the wavefront range (device pair)
+hipError_t launch_sweep_reduce(const Geom& g, const Buffers& b, const int* range, hipStream_t st);
 // statistics over the visits of patches i with i mod n_batches == batch
-hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& plan, int cur,
-                             int n_omega, int n_batches, int batch, hipStream_t st);
+// (chunk count, chunk size and mapping from the frame plan; plan.chunks and
+// plan.chunk_visits give the launch's maximum; the grid covers grid_chunks
+// chunk slots, at least the frame's)
+hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& plan, int grid_chunks,
+                             int cur, int n_batches, int batch, hipStream_t st);
 hipError_t launch_dict_reduce(const Geom& g, const Buffers& b, const DictPlan& plan,
                               hipStream_t st);
 // the chain draws with the data statistics multiplied by `scale` (a
@@ -185,9 +230,9 @@ struct StepBatch {
   long long n_obs_b;
   double scale;
 };
+// (the Philox stream id is the device scalars' problem_id)
 hipError_t launch_scalars(const Geom& g, const Buffers& b, const double* hyper, int learn_dict,
-                          const StepBatch& sb, uint32_t key0, uint32_t key1, uint32_t problem_id,
-                          hipStream_t st);
+                          const StepBatch& sb, uint32_t key0, uint32_t key1, hipStream_t st);
 // posterior moments: (sum, sum2) = (x, x^2) (first) or += (x, x^2);
 // mean = sum / count; variance = (sum2 - sum^2 / count) / (count - 1)
 hipError_t launch_mean_add(long long n, const float* x, double* sum, double* sum2, bool first,
@@ -204,7 +249,10 @@ hipError_t launch_lists_to_dense(const Geom& g, const Buffers& b, int cur, float
 hipError_t launch_dense_to_lists(const Geom& g, const Buffers& b, int cur, int Npad,
                                  const float* W, const uint8_t* Z, int* bad, hipStream_t st);
 hipError_t launch_ck(const Geom& g, const Buffers& b, hipStream_t st);
-hipError_t launch_set_t(DevScalars* scal, long long t, hipStream_t st);
+// next iteration number (t > 0), Philox stream id and (clear_status) no
+// recorded failure, stream-ordered
+hipError_t launch_set_t(DevScalars* scal, long long t, uint32_t problem_id, hipStream_t st,
+                        bool clear_status);
 hipError_t launch_reset_scalars(const Geom& g, const Buffers& b, double ell0, double gamma_s0,
                                 double gamma_eps0, hipStream_t st);
 hipError_t launch_debug_philox(uint32_t key0, uint32_t key1, uint32_t c1, uint32_t t,
@@ -223,5 +271,18 @@ int problem_export_dict(bpfa_problem* h, void* blob);
 // load a blob, set the Philox stream id and the next iteration number
 int problem_import_dict(bpfa_problem* h, const void* blob, long long t, uint32_t problem_id);
 int problem_dims(bpfa_problem* h, int* K, int* P);
-void problem_set_id(bpfa_problem* h, uint32_t problem_id);
+// A served frame in three stream-ordered parts.  upload: the frame's image
+// and mask from pinned host memory (no synchronisation; the buffers must
+// stay valid until the stream has copied them).  body: patch index (codes
+// cleared), sc_iters sparse-coding iterations, a dictionary iteration if
+// `learn`, the reconstruction into the workspace -- launches only, with no
+// pointer that changes between frames, so the body can be captured into a
+// graph and replayed for any frame of the handle's shape.  result:
+// the reconstruction to host `out`, then a synchronisation that reports a
+// refused frame (ESHAPE) or a failed draw (ENUMERIC).
+int problem_upload_frame(bpfa_problem* h, const float* image, const uint8_t* mask);
+int problem_frame_body(bpfa_problem* h, int sc_iters, int learn);
+int problem_frame_result(bpfa_problem* h, float* out);
+hipStream_t problem_stream(bpfa_problem* h);
+int problem_set_id(bpfa_problem* h, uint32_t problem_id);
 }  // namespace bpfa

@@ -27,6 +27,8 @@
 //   prefetched ahead of use, keeping u = C_p d current instead of reducing a
 //   dot product per step, draws d_kp with the Philox DICT stream, and forms
 //   the residual sum of squares.
+#include <algorithm>
+
 #include "internal.hpp"
 #include "philox.hpp"
 
@@ -44,6 +46,9 @@ struct VisitRow {
 };
 
 
+// chunks: chunk slots of the launch (the partials' stride); chunk_visits: the
+// largest chunk (the LDS layout).  A frame uses the first dict_chunks slots of
+// dict_cv visits each (frame plan).
 struct DictPlanDev {
   int RG, chunks, K, chunk_visits, xcd;
   int row0[65];
@@ -121,26 +126,28 @@ __device__ __forceinline__ void stats_pairs(const StatsRow& sr, const int (&kk)[
 // Per frame: for every position p and observed pixel v (in omega order), the
 // patch whose origin is q_v - b(p), or -1 when that origin is off the grid;
 // and the observed values in omega order.
-__global__ __launch_bounds__(256) void visit_table_kernel(Geom g, int nom, const int4* __restrict__ omega_c,
+__global__ __launch_bounds__(256) void visit_table_kernel(Geom g, const DevScalars* __restrict__ scal,
+                                                          const int4* __restrict__ omega_c,
                                                           const int32_t* __restrict__ omega,
                                                           const float* __restrict__ image,
                                                           const int32_t* __restrict__ pcoord,
                                                           int32_t* __restrict__ vpatch,
                                                           float* __restrict__ omega_y) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nom = scal->n_omega;
   const int p = blockIdx.y;
-  if (v >= nom) return;
   int bc[kMaxDim] = {0, 0, 0, 0};
   for (int d = 0; d < g.ndim; ++d) bc[d] = pcoord[p * kMaxDim + d];
-  const int pidx = visit_patch(g, omega_c[v], bc);
-  vpatch[(size_t)p * g.Mtot + v] = pidx;
-  if (p == 0) omega_y[v] = image[omega[v]];
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nom; v += gridDim.x * blockDim.x) {
+    vpatch[(size_t)p * g.Mtot + v] = visit_patch(g, omega_c[v], bc);
+    if (p == 0) omega_y[v] = image[omega[v]];
+  }
 }
 
-hipError_t launch_visit_table(const Geom& g, const Buffers& b, int n_omega, hipStream_t st) {
-  if (n_omega <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((n_omega + 255) / 256), (unsigned)g.P);
-  visit_table_kernel<<<grid, 256, 0, st>>>(g, n_omega, b.omega_c, b.omega, b.image, b.pcoord,
+// the grid strides over the frame's observed pixels (their count is read on
+// the device): up to 64 blocks of 256 per position
+hipError_t launch_visit_table(const Geom& g, const Buffers& b, hipStream_t st) {
+  const dim3 grid((unsigned)std::min<long long>(64, ((long long)g.Mtot + 255) / 256), (unsigned)g.P);
+  visit_table_kernel<<<grid, 256, 0, st>>>(g, b.scal, b.omega_c, b.omega, b.image, b.pcoord,
                                            b.vpatch, b.omega_y);
   return hipGetLastError();
 }
@@ -150,26 +157,32 @@ hipError_t launch_visit_table(const Geom& g, const Buffers& b, int n_omega, hipS
 // each wavefront's pair loop runs to a bound its lanes share.
 template <bool SKIP>
 __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
-    Geom g, DictPlanDev pl, int nom, const int32_t* __restrict__ vpatch,
+    Geom g, DictPlanDev pl, const FramePlan* __restrict__ fplan, const int32_t* __restrict__ vpatch,
     const float* __restrict__ omega_y, const int2* __restrict__ list,
     const int32_t* __restrict__ nact, const DevScalars* __restrict__ scal,
     long long* __restrict__ dpart, double* __restrict__ dx2, int n_batches, int batch) {
   extern __shared__ long long acc[];
   __shared__ double s_x2[kDictBlock / kWave];
   __shared__ int s_total;
+  // this frame's chunking: cc chunks of cvf observed pixels (the launch has
+  // room for pl.chunks chunks of pl.chunk_visits)
+  const int nom = scal->n_omega;
+  const int cc = fplan->dict_chunks, cvf = fplan->dict_cv;
+  const int npr = g.P * pl.RG;
+  if ((int)blockIdx.x >= npr * cc) return;   // chunk slots this frame leaves empty
   // block -> (chunk c, position p, row group rg).  Workgroups are dispatched
-  // round-robin over the 8 XCDs; with chunks a multiple of 8 every block of
+  // round-robin over the 8 XCDs; with cc a multiple of 8 every block of
   // chunk c has blockIdx = c mod 8, and an XCD takes all (p, rg) blocks of
   // one chunk before its next chunk, so the blocks that read the same
   // patches' lists (a band of image rows) run together on one L2.
   int c, prg;
-  if (pl.xcd) {
-    const int npr = gridDim.x / pl.chunks, j = blockIdx.x >> 3;
+  if (fplan->dict_xcd) {
+    const int j = blockIdx.x >> 3;
     c = (blockIdx.x & 7) + 8 * (j / npr);
     prg = j % npr;
   } else {
-    c = blockIdx.x % pl.chunks;
-    prg = blockIdx.x / pl.chunks;
+    c = blockIdx.x % cc;
+    prg = blockIdx.x / cc;
   }
   const int p = prg / pl.RG, rg = prg % pl.RG;
   const int r0 = pl.row0[rg], r1 = pl.row0[rg + 1];
@@ -188,9 +201,9 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
   const int32_t* vs = vpatch + (size_t)p * g.Mtot;
   double x2 = 0.0;
 
-  // block c of its (p, row group) takes chunks c, c + chunks, ... of the observed pixels
-  for (int ch = c; ch * pl.chunk_visits < nom; ch += pl.chunks) {
-  const int v0 = ch * pl.chunk_visits, v1 = min(nom, v0 + pl.chunk_visits);
+  // block c of its (p, row group) takes chunks c, c + cc, ... of the observed pixels
+  for (int ch = c; ch * cvf < nom; ch += cc) {
+  const int v0 = ch * cvf, v1 = min(nom, v0 + cvf);
   for (int e = tid; e <= K; e += kDictBlock) bins[e] = 0;
   __syncthreads();
 
@@ -417,10 +430,11 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
 
 // one block per (p, row k): C_p[k][j] = C_p[j][k] for j >= k, B_p[k], diag, X2_p
 __global__ __launch_bounds__(256) void dict_reduce_kernel(
-    Geom g, DictPlanDev pl, const long long* __restrict__ dpart, const double* __restrict__ dx2,
-    const DevScalars* __restrict__ scal, double* __restrict__ Cfull, double* __restrict__ Bvec,
-    double* __restrict__ diag, double* __restrict__ x2p) {
+    Geom g, DictPlanDev pl, const FramePlan* __restrict__ fplan, const long long* __restrict__ dpart,
+    const double* __restrict__ dx2, const DevScalars* __restrict__ scal, double* __restrict__ Cfull,
+    double* __restrict__ Bvec, double* __restrict__ diag, double* __restrict__ x2p) {
   const int K = g.K;
+  const int cc = fplan->dict_chunks;
   const int p = blockIdx.x / K, k = blockIdx.x % K;
   int rg = 0;
   while (rg + 1 < pl.RG && pl.row0[rg + 1] <= k) ++rg;
@@ -432,7 +446,7 @@ __global__ __launch_bounds__(256) void dict_reduce_kernel(
   double* C = Cfull + (size_t)p * K * K;
   for (int j = k + threadIdx.x; j < K; j += blockDim.x) {
     long long sum = 0;
-    for (int c = 0; c < pl.chunks; ++c) sum += rec[(size_t)c * pl.rec_stride + ek + j];
+    for (int c = 0; c < cc; ++c) sum += rec[(size_t)c * pl.rec_stride + ek + j];
     const double v = (double)sum * inv_c;
     C[(size_t)k * K + j] = v;
     C[(size_t)j * K + k] = v;
@@ -440,11 +454,11 @@ __global__ __launch_bounds__(256) void dict_reduce_kernel(
   }
   if (threadIdx.x == 0) {
     long long sum = 0;
-    for (int c = 0; c < pl.chunks; ++c) sum += rec[(size_t)c * pl.rec_stride + E + (k - pl.row0[rg])];
+    for (int c = 0; c < cc; ++c) sum += rec[(size_t)c * pl.rec_stride + E + (k - pl.row0[rg])];
     Bvec[(size_t)p * K + k] = (double)sum / scal->scale_b;
     if (k == 0) {
       double x2 = 0.0;
-      for (int c = 0; c < pl.chunks; ++c) x2 += dx2[p * pl.chunks + c];
+      for (int c = 0; c < cc; ++c) x2 += dx2[p * pl.chunks + c];
       x2p[p] = x2;
     }
   }
@@ -482,6 +496,8 @@ __device__ __forceinline__ void chain_run(const Geom& g, int p, int lane, const 
   static_assert(kWave % PF == 0, "a ring slot keeps its row across register groups");
   const int K = g.K, P = g.P;
   const uint32_t t = (uint32_t)scal->t;
+  // the tag comes with `stream`, the problem id from the device scalars
+  stream = (stream & 0xFFu) | (scal->problem_id << 8);
   const double ge = scal->gamma_eps * scale;
   double dreg[KPL], ureg[KPL], greg[KPL], treg[KPL], breg[KPL];
 #pragma unroll
@@ -606,23 +622,24 @@ __global__ __launch_bounds__(kWave) void dict_chain_kernel(
 // K <= kChainLdsMaxK (one row group): the chunk partials are summed into the
 // packed upper triangle of C_p (binary64, coalesced), B_p and X2_p.
 __global__ __launch_bounds__(256) void dict_reduce_tri_kernel(
-    Geom g, DictPlanDev pl, const long long* __restrict__ dpart, const double* __restrict__ dx2,
-    const DevScalars* __restrict__ scal, double* __restrict__ Ctri, double* __restrict__ Bvec,
-    double* __restrict__ x2p) {
+    Geom g, DictPlanDev pl, const FramePlan* __restrict__ fplan, const long long* __restrict__ dpart,
+    const double* __restrict__ dx2, const DevScalars* __restrict__ scal, double* __restrict__ Ctri,
+    double* __restrict__ Bvec, double* __restrict__ x2p) {
   const int K = g.K, E = K * (K + 1) / 2;
+  const int cc = fplan->dict_chunks;
   const int per_p = (E + K + 255) / 256;
   const int p = blockIdx.x / per_p;
   const int e = (blockIdx.x % per_p) * 256 + threadIdx.x;
   const long long* rec = dpart + (size_t)p * pl.chunks * pl.rec_stride;
   if (e < E + K) {
     long long sum = 0;
-    for (int c = 0; c < pl.chunks; ++c) sum += rec[(size_t)c * pl.rec_stride + e];
+    for (int c = 0; c < cc; ++c) sum += rec[(size_t)c * pl.rec_stride + e];
     if (e < E) Ctri[(size_t)p * E + e] = (double)sum * (1.0 / scal->scale_c);
     else Bvec[(size_t)p * K + (e - E)] = (double)sum / scal->scale_b;
   }
   if (e == 0) {
     double x2 = 0.0;
-    for (int c = 0; c < pl.chunks; ++c) x2 += dx2[p * pl.chunks + c];
+    for (int c = 0; c < cc; ++c) x2 += dx2[p * pl.chunks + c];
     x2p[p] = x2;
   }
 }
@@ -709,10 +726,13 @@ static DictPlanDev to_dev(const Geom& g, const DictPlan& plan) {
   return d;
 }
 
-hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& plan, int cur,
-                             int n_omega, int n_batches, int batch, hipStream_t st) {
+hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& plan, int grid_chunks,
+                             int cur, int n_batches, int batch, hipStream_t st) {
   const DictPlanDev d = to_dev(g, plan);
-  const int blocks = g.P * plan.RG * plan.chunks;
+  // blocks for grid_chunks chunk slots per (p, row group): the frame's count
+  // when the host knows it, else all of them (blocks of slots the frame
+  // leaves empty return at once)
+  const int blocks = g.P * plan.RG * std::max(1, std::min(grid_chunks, plan.chunks));
   // the LDS holds visit records for the largest chunk the plan allows
   const size_t lds = dict_stats_lds(g.K, d.rec_stride, plan.chunk_visits);
   const bool skip = plan.RG >= 3;
@@ -722,11 +742,11 @@ hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& pl
   if (e != hipSuccess) return e;
   if (skip)
     dict_stats_kernel<true><<<blocks, kDictBlock, lds, st>>>(
-        g, d, n_omega, b.vpatch, b.omega_y, b.list[cur], b.nact[cur], b.scal, b.dpart, b.dx2,
+        g, d, b.plan, b.vpatch, b.omega_y, b.list[cur], b.nact[cur], b.scal, b.dpart, b.dx2,
         n_batches, batch);
   else
     dict_stats_kernel<false><<<blocks, kDictBlock, lds, st>>>(
-        g, d, n_omega, b.vpatch, b.omega_y, b.list[cur], b.nact[cur], b.scal, b.dpart, b.dx2,
+        g, d, b.plan, b.vpatch, b.omega_y, b.list[cur], b.nact[cur], b.scal, b.dpart, b.dx2,
         n_batches, batch);
   return hipGetLastError();
 }
@@ -734,8 +754,8 @@ hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& pl
 hipError_t launch_dict_reduce(const Geom& g, const Buffers& b, const DictPlan& plan,
                               hipStream_t st) {
   const DictPlanDev d = to_dev(g, plan);
-  dict_reduce_kernel<<<g.P * g.K, 256, 0, st>>>(g, d, b.dpart, b.dx2, b.scal, b.Cfull, b.Bvec,
-                                                b.diag, b.x2p);
+  dict_reduce_kernel<<<g.P * g.K, 256, 0, st>>>(g, d, b.plan, b.dpart, b.dx2, b.scal, b.Cfull,
+                                                b.Bvec, b.diag, b.x2p);
   return hipGetLastError();
 }
 
@@ -767,7 +787,7 @@ hipError_t launch_dict_reduce_chain_lds(const Geom& g, const Buffers& b, const D
   const int E = g.K * (g.K + 1) / 2;
   const int per_p = (E + g.K + 255) / 256;
   // the packed triangles go where the full matrices would (P x K x K >= P x E)
-  dict_reduce_tri_kernel<<<g.P * per_p, 256, 0, st>>>(g, d, b.dpart, b.dx2, b.scal, b.Cfull,
+  dict_reduce_tri_kernel<<<g.P * per_p, 256, 0, st>>>(g, d, b.plan, b.dpart, b.dx2, b.scal, b.Cfull,
                                                        b.Bvec, b.x2p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -14,6 +14,8 @@
 //                which the sweep keeps at zero.
 // omega_*        ordered compaction of the observed pixels (the dictionary
 //                statistics visit patches through them).
+#include <algorithm>
+
 #include "internal.hpp"
 #include "philox.hpp"
 
@@ -98,7 +100,8 @@ __global__ __launch_bounds__(256) void slots_kernel(Geom g, const float* __restr
                                                     uint16_t* __restrict__ obs_idx,
                                                     float* __restrict__ obs_val,
                                                     int Npad,
-                                                    int Jcap4) {
+                                                    const FramePlan* __restrict__ plan) {
+  const int Jcap4 = plan->jpad;
   const int s = blockIdx.x * blockDim.x + threadIdx.x;   // grid covers Npad exactly
   const bool valid = s < g.N;
   int cnt = 0;
@@ -368,6 +371,137 @@ __global__ void init_dict_kernel(Geom g, float* __restrict__ D, uint32_t key0, u
   D[idx] = (float)(n / sqrt((double)g.P));
 }
 
+// ---- frame plan: wavefront table, slot rows, statistics chunking ----------
+//
+// Built on the device from the slot sort's key offsets, so a frame load needs
+// no host round trip.  Within a batch the slots ascend in |Obs|; the sweep
+// gives a patch with |Obs| in class c = [lo_c, hi_c] lanes_c lanes, and cuts
+// each (batch, class) run of slots into wavefronts of 64 / lanes_c slots
+// (the last one shorter).  A wavefront's register count J covers its last,
+// largest slot: J = max(4, |Obs| rounded up to even) for one lane per patch,
+// 12 or 16 for two lanes, 16 otherwise.
+
+__device__ __constant__ int kClassLo[kLaneClasses] = {0, 17, 33, 65, 129};
+__device__ __constant__ int kClassHi[kLaneClasses] = {16, 32, 64, 128, 256};
+__device__ __constant__ int kClassLanes[kLaneClasses] = {1, 2, 4, 8, 16};
+
+struct PlanArgs {
+  int n_batches;
+  int dict_chunks_max, dict_cv_max, dict_slots, dict_npr;   // npr: (p, row group) pairs
+};
+
+// one block of 1024 threads
+__global__ __launch_bounds__(1024) void frame_plan_kernel(Geom g, PlanArgs pa,
+                                                          const int32_t* __restrict__ bins,
+                                                          const DevScalars* __restrict__ scal,
+                                                          FramePlan* __restrict__ plan) {
+  __shared__ int s_tot[1024];
+  __shared__ long long s_red[1024];
+  const int B = pa.n_batches, P = g.P, tid = threadIdx.x;
+  const int E = B * kLaneClasses;
+  // first slot of batch b with |Obs| >= c (c > P: the batch's end)
+  auto start = [&](int b, int c) -> int {
+    if (c <= P) return bins[(size_t)b * (P + 1) + c];
+    return b + 1 < B ? bins[(size_t)(b + 1) * (P + 1)] : g.N;
+  };
+  for (int e = tid; e < E; e += 1024) {
+    const int b = e / kLaneClasses, c = e - b * kLaneClasses;
+    const int s0 = start(b, min(kClassLo[c], P + 1));
+    const int s1 = start(b, min(kClassHi[c] + 1, P + 1));
+    const int per = kWave / kClassLanes[c];
+    plan->cls_s0[e] = s0;
+    plan->cls_s1[e] = s1;
+    plan->cls_w0[e] = (s1 - s0 + per - 1) / per;   // wavefront count, scanned below
+  }
+  __syncthreads();
+  const int total = block_scan_1024(plan->cls_w0, E, s_tot);
+  if (tid == 0) {
+    plan->cls_w0[E] = total;
+    plan->all_waves[0] = 0;
+    plan->all_waves[1] = total;
+    plan->n_batches = B;
+    plan->batch_wave0[B] = total;
+    plan->batch_slot0[B] = g.N;
+    const int mo = scal->max_obs;
+    plan->bad = mo > 256 ? 1 : 0;
+    const int jcap = (P + 3) & ~3;
+    plan->jpad = min(jcap, max(4, (mo + 3) & ~3));
+    // statistics chunking: the chunk count c >= need that minimises the
+    // block rounds per chunk, rounds(c) / c (ties: the smaller c)
+    const int nom = scal->n_omega;
+    const int need = min(pa.dict_chunks_max, max(1, (nom + pa.dict_cv_max - 1) / pa.dict_cv_max));
+    int best = need;
+    double best_cost = 1e300;
+    for (int cc = need; cc <= pa.dict_chunks_max; ++cc) {
+      const long long blocks = (long long)pa.dict_npr * cc;
+      const double cost = (double)((blocks + pa.dict_slots - 1) / pa.dict_slots) / cc;
+      if (cost < best_cost * (1.0 - 1e-9)) {
+        best_cost = cost;
+        best = cc;
+      }
+    }
+    const int per = (nom + best - 1) / best;
+    plan->dict_chunks = best;
+    plan->dict_cv = min(pa.dict_cv_max, max(kDictBlock, (per + kDictBlock - 1) / kDictBlock * kDictBlock));
+    plan->dict_xcd = best % 8 == 0 ? 1 : 0;
+  }
+  __syncthreads();
+  for (int b = tid; b < B; b += 1024) {
+    plan->batch_wave0[b] = plan->cls_w0[b * kLaneClasses];
+    plan->batch_slot0[b] = start(b, 0);
+  }
+  // observed pixels of each batch: sum over |Obs| = c of c times the bin size
+  for (int b = 0; b < B; ++b) {
+    long long part = 0;
+    for (int c = 1 + tid; c <= P; c += 1024) part += (long long)c * (start(b, c + 1) - start(b, c));
+    s_red[tid] = part;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+      if (tid < o) s_red[tid] += s_red[tid + o];
+      __syncthreads();
+    }
+    if (tid == 0) plan->batch_nobs[b] = s_red[0];
+    __syncthreads();
+  }
+}
+
+// one thread per wavefront of the table
+__global__ __launch_bounds__(256) void plan_waves_kernel(int E, const FramePlan* __restrict__ plan,
+                                                         const int32_t* __restrict__ count,
+                                                         const uint32_t* __restrict__ perm,
+                                                         int4* __restrict__ waves) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= plan->all_waves[1]) return;
+  // the last (batch, class) whose first wavefront is <= w (empty runs share
+  // their offset with the next one, so this is the run that holds w)
+  int lo = 0, hi = E - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (plan->cls_w0[mid] <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  const int c = lo % kLaneClasses;
+  const int lanes = kClassLanes[c], per = kWave / lanes;
+  const int slot = plan->cls_s0[lo] + (w - plan->cls_w0[lo]) * per;
+  const int ns = min(per, plan->cls_s1[lo] - slot);
+  const int clast = count[perm[slot + ns - 1]];
+  int J = 16;
+  if (lanes == 1) J = max(4, (clast + 1) & ~1);
+  else if (lanes == 2 && clast <= 24) J = 12;
+  waves[w] = make_int4(slot, ns, lanes, J);
+}
+
+hipError_t launch_frame_plan(const Geom& g, const Buffers& b, int n_batches, long long wave_cap,
+                             int dict_chunks_max, int dict_cv_max, int dict_slots, int dict_npr,
+                             hipStream_t st) {
+  PlanArgs pa{n_batches, dict_chunks_max, dict_cv_max, dict_slots, dict_npr};
+  frame_plan_kernel<<<1, 1024, 0, st>>>(g, pa, b.sort_bin, b.scal, b.plan);
+  const int E = n_batches * kLaneClasses;
+  plan_waves_kernel<<<(unsigned)((wave_cap + 255) / 256), 256, 0, st>>>(E, b.plan, b.obs_count,
+                                                                       b.perm, b.sweep_waves);
+  return hipGetLastError();
+}
+
 // ---- launchers ----------------------------------------------------------
 
 hipError_t launch_index(const Geom& g, const Buffers& b, int Npad, hipStream_t st) {
@@ -375,6 +509,19 @@ hipError_t launch_index(const Geom& g, const Buffers& b, int Npad, hipStream_t s
   const int n = max(g.N, Npad);
   index_kernel<<<(n + 255) / 256, 256, 0, st>>>(g, b.mask, b.poff, b.obs_bits, b.obs_count,
                                                 b.perm, Npad, b.scal);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void fill_i32_kernel(int32_t* __restrict__ p, long long n, int32_t v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t* p, long long n, int32_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const long long blocks = std::min<long long>(1024, (n + 255) / 256);
+  fill_i32_kernel<<<(unsigned)blocks, 256, 0, st>>>(p, n, v);
   return hipGetLastError();
 }
 
@@ -386,9 +533,9 @@ hipError_t launch_omega(const Geom& g, const Buffers& b, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_slots(const Geom& g, const Buffers& b, int Npad, int Jcap4, hipStream_t st) {
+hipError_t launch_slots(const Geom& g, const Buffers& b, int Npad, hipStream_t st) {
   slots_kernel<<<Npad / 256, 256, 0, st>>>(g, b.image, b.poff, b.obs_bits, b.obs_count, b.perm,
-                                           b.obs_idx, b.obs_val, Npad, Jcap4);
+                                           b.obs_idx, b.obs_val, Npad, b.plan);
   return hipGetLastError();
 }
 

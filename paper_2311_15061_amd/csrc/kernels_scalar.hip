@@ -45,7 +45,7 @@ __device__ bool log_gamma_draw(double shape, uint32_t key0, uint32_t key1, uint3
 __global__ __launch_bounds__(256) void scalars_kernel(Geom g, double a, double b, double c,
                                                       double dd, double e, double f,
                                                       int learn_dict, StepBatch sb, uint32_t key0,
-                                                      uint32_t key1, uint32_t pid,
+                                                      uint32_t key1,
                                                       int32_t* __restrict__ nk,
                                                       const double* __restrict__ sumr2_p,
                                                       double* __restrict__ ell,
@@ -56,6 +56,7 @@ __global__ __launch_bounds__(256) void scalars_kernel(Geom g, double a, double b
   __shared__ double s_min[256], s_max[256], s_sum[256];
   __shared__ long long s_zp[256];
   const int K = g.K, tid = threadIdx.x;
+  const uint32_t pid = scal->problem_id;
   const uint32_t t = (uint32_t)scal->t;
   // sum(z) and the residual sum of squares: strided partials, fixed-order tree
   long long zp = 0;
@@ -154,10 +155,9 @@ __global__ __launch_bounds__(256) void scalars_kernel(Geom g, double a, double b
 }
 
 hipError_t launch_scalars(const Geom& g, const Buffers& b, const double* h, int learn_dict,
-                          const StepBatch& sb, uint32_t key0, uint32_t key1, uint32_t problem_id,
-                          hipStream_t st) {
+                          const StepBatch& sb, uint32_t key0, uint32_t key1, hipStream_t st) {
   scalars_kernel<<<1, 256, 0, st>>>(g, h[0], h[1], h[2], h[3], h[4], h[5], learn_dict, sb, key0,
-                                    key1, problem_id, b.sw_cnt, b.sumr2_p, b.ell, b.Ck, b.scal);
+                                    key1, b.sw_cnt, b.sumr2_p, b.ell, b.Ck, b.scal);
   return hipGetLastError();
 }
 
@@ -193,10 +193,15 @@ hipError_t launch_reset_scalars(const Geom& g, const Buffers& b, double ell0, do
   return hipGetLastError();
 }
 
-__global__ void set_t_kernel(DevScalars* scal, long long t) { scal->t = t; }
+__global__ void set_t_kernel(DevScalars* scal, long long t, uint32_t problem_id, int clear_status) {
+  if (t > 0) scal->t = t;
+  scal->problem_id = problem_id;
+  if (clear_status) scal->status = 0;
+}
 
-hipError_t launch_set_t(DevScalars* scal, long long t, hipStream_t st) {
-  set_t_kernel<<<1, 1, 0, st>>>(scal, t);
+hipError_t launch_set_t(DevScalars* scal, long long t, uint32_t problem_id, hipStream_t st,
+                        bool clear_status) {
+  set_t_kernel<<<1, 1, 0, st>>>(scal, t, problem_id, clear_status ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -82,7 +82,9 @@ __device__ __forceinline__ float group_sum(float v) {
 // One wavefront: slots wt.x .. wt.x + wt.y - 1, LPP lanes per slot, J
 // observed pixels per lane (lane `sub` of a group holds rows sub*J .. sub*J+J-1)
 template <int J, int LPP>
-__device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslots, int slot0) {
+__device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslots, int slot0,
+                                           int jpad, uint32_t zs_stream, int tid, uint32_t key0,
+                                           uint32_t key1, int npad) {
   extern __shared__ float lds[];
   uint8_t* cnt_lds = reinterpret_cast<uint8_t*>(lds + (a.P + 1) * a.KS);  // [wave][K] z counts
   // per-wave partials in the dynamic LDS, not in static __shared__ arrays:
@@ -93,7 +95,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslo
   long long* s_z = reinterpret_cast<long long*>(s_r2 + kSweepWaves);
   float* s_wm = reinterpret_cast<float*>(s_z + kSweepWaves);
 
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  const int lane = tid & (kWave - 1), wid = tid / kWave;
   const int grp = lane / LPP, sub = lane - grp * LPP;
   const int s = slot0 + grp;
   const bool valid = grp < nslots;
@@ -112,9 +114,9 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslo
     const int j = sub * J + jj;
     int p = a.P;
     float x = 0.f;
-    if (valid && j < a.Jpad) {
-      p = a.obs_idx[(size_t)j * a.Npad + s];
-      x = a.obs_val[(size_t)j * a.Npad + s];
+    if (valid && j < jpad) {
+      p = a.obs_idx[(size_t)j * npad + s];
+      x = a.obs_val[(size_t)j * npad + s];
     }
     col[jj] = L + p * a.KS;
     r[jj] = x;
@@ -225,7 +227,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslo
         e0 = lin[cur];
         e1 = lin[cur + 1];
       }
-      const Block4 rb = philox10(ip, (uint32_t)(k >> 1), t, a.stream, a.key0, a.key1);
+      const Block4 rb = philox10(ip, (uint32_t)(k >> 1), t, zs_stream, key0, key1);
       float dl0 = 0.f, dl1 = 0.f, rh0 = 0.f, rh1 = 0.f, g01 = 0.f;
 #pragma unroll
       for (int j = 0; j < J; ++j) {
@@ -306,50 +308,85 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslo
   }
 }
 
-// One kernel for every wavefront of the frame: wavefront w of the grid reads
-// its (first slot, slots, lanes per slot, J) from the table and runs the body
-// compiled for that pair; wavefronts past the table run with no valid lane
-// (every body passes the same barriers).
-__global__ __launch_bounds__(kSweepBlock, kSweepWavesPerSimd) void sweep_kernel(SweepArgs a, const int4* __restrict__ waves,
-                                                            int nwaves) {
-  const int blk = blockIdx.x;
-  const int w = blk * (kSweepWaves) + (int)(threadIdx.x / kWave);
+// One 8-wave group of the launch's wavefront range: wavefront w of group grp
+// reads its (first slot, slots, lanes per slot, J) from the table and runs the
+// body compiled for that pair; the group's partials go to entry grp.
+// Wavefronts past the range run with no valid lane (every body passes the
+// same barriers).  tid, keys and npad are passed in so that the strided
+// kernel can hide them from loop-invariant hoisting.
+__device__ __forceinline__ void sweep_group(const SweepArgs& a, const int4* __restrict__ waves, int w0,
+                                            int nwaves, int grp, int jpad, uint32_t zs, int tid,
+                                            uint32_t key0, uint32_t key1, int npad) {
+  const int w = grp * kSweepWaves + tid / kWave;
   int4 wt = make_int4(0, 0, 1, 4);
-  if (w < nwaves) wt = waves[w];
+  if (w < nwaves) wt = waves[w0 + w];
   const int slot0 = __builtin_amdgcn_readfirstlane(wt.x);
   const int ns = __builtin_amdgcn_readfirstlane(wt.y);
   const int lpp = __builtin_amdgcn_readfirstlane(wt.z);
   const int J = __builtin_amdgcn_readfirstlane(wt.w);
+#define BPFA_BODY(JJ, LL) sweep_wave<JJ, LL>(a, grp, ns, slot0, jpad, zs, tid, key0, key1, npad)
   switch (lpp) {
     case 1:
       switch (J) {
-        case 4: sweep_wave<4, 1>(a, blk, ns, slot0); break;
-        case 6: sweep_wave<6, 1>(a, blk, ns, slot0); break;
-        case 8: sweep_wave<8, 1>(a, blk, ns, slot0); break;
-        case 10: sweep_wave<10, 1>(a, blk, ns, slot0); break;
-        case 12: sweep_wave<12, 1>(a, blk, ns, slot0); break;
-        case 14: sweep_wave<14, 1>(a, blk, ns, slot0); break;
-        default: sweep_wave<16, 1>(a, blk, ns, slot0); break;
+        case 4: BPFA_BODY(4, 1); break;
+        case 6: BPFA_BODY(6, 1); break;
+        case 8: BPFA_BODY(8, 1); break;
+        case 10: BPFA_BODY(10, 1); break;
+        case 12: BPFA_BODY(12, 1); break;
+        case 14: BPFA_BODY(14, 1); break;
+        default: BPFA_BODY(16, 1); break;
       }
       break;
     case 2:
-      if (J <= 12) sweep_wave<12, 2>(a, blk, ns, slot0);
-      else sweep_wave<16, 2>(a, blk, ns, slot0);
+      if (J <= 12) BPFA_BODY(12, 2);
+      else BPFA_BODY(16, 2);
       break;
-    case 4: sweep_wave<16, 4>(a, blk, ns, slot0); break;
-    case 8: sweep_wave<16, 8>(a, blk, ns, slot0); break;
-    default: sweep_wave<16, 16>(a, blk, ns, slot0); break;
+    case 4: BPFA_BODY(16, 4); break;
+    case 8: BPFA_BODY(16, 8); break;
+    default: BPFA_BODY(16, 16); break;
+  }
+#undef BPFA_BODY
+}
+
+// The sweep over the table's wavefronts [range[0], range[1]) (a pair in
+// device memory).  STRIDED = false: one block per 8-wave group (the grid is
+// the group count, known on the host).  STRIDED = true: a grid fixed per
+// handle strides over the groups, so a launch needs no host knowledge of the
+// frame (captured launch sequences); the values the bodies derive lane and
+// key constants from are made opaque per group, which keeps the loop from
+// hoisting them into spilled registers.
+template <bool STRIDED>
+__global__ __launch_bounds__(kSweepBlock, kSweepWavesPerSimd) void sweep_kernel(const SweepArgs a, const int4* __restrict__ waves,
+                                                            const int* __restrict__ range) {
+  const int w0 = __builtin_amdgcn_readfirstlane(range[0]);
+  const int nwaves = __builtin_amdgcn_readfirstlane(range[1]) - w0;
+  // observed rows per slot and the stream word, from the frame plan and the
+  // device scalars (kept out of `a`, which stays in kernel-argument memory)
+  const int jpad = __builtin_amdgcn_readfirstlane(a.plan->jpad);
+  const uint32_t zs = (a.stream & 0xFFu) |
+                      ((uint32_t)__builtin_amdgcn_readfirstlane(a.scal->problem_id) << 8);
+  const int ngroups = (nwaves + kSweepWaves - 1) / kSweepWaves;
+  if constexpr (STRIDED) {
+    for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+      int tid = threadIdx.x, npad = a.Npad;
+      uint32_t key0 = a.key0, key1 = a.key1;
+      asm volatile("" : "+v"(tid), "+s"(npad), "+s"(key0), "+s"(key1));
+      sweep_group(a, waves, w0, nwaves, grp, jpad, zs, tid, key0, key1, npad);
+    }
+  } else {
+    if ((int)blockIdx.x < ngroups)
+      sweep_group(a, waves, w0, nwaves, blockIdx.x, jpad, zs, threadIdx.x, a.key0, a.key1, a.Npad);
   }
 }
 
-hipError_t launch_sweep(const int4* waves, int nwaves, size_t lds, const SweepArgs& a,
-                        hipStream_t st) {
-  const int blocks = (nwaves + kSweepWaves - 1) / (kSweepWaves);
+hipError_t launch_sweep(const int4* waves, const int* range, int blocks, bool strided, size_t lds,
+                        const SweepArgs& a, hipStream_t st) {
   if (blocks <= 0) return hipSuccess;
-  hipError_t e = hipFuncSetAttribute((const void*)sweep_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const void* fn = strided ? (const void*)sweep_kernel<true> : (const void*)sweep_kernel<false>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  sweep_kernel<<<blocks, kSweepBlock, lds, st>>>(a, waves, nwaves);
+  if (strided) sweep_kernel<true><<<blocks, kSweepBlock, lds, st>>>(a, waves, range);
+  else sweep_kernel<false><<<blocks, kSweepBlock, lds, st>>>(a, waves, range);
   return hipGetLastError();
 }
 
@@ -364,8 +401,10 @@ __device__ double fixed_scale(double bound, double n) {
   return ldexp(1.0, min(50 - e1, 62 - e2));
 }
 
-__global__ __launch_bounds__(256) void sweep_reduce_kernel(int blocks, const SweepPart* __restrict__ part,
+__global__ __launch_bounds__(256) void sweep_reduce_kernel(const int* __restrict__ range,
+                                                           const SweepPart* __restrict__ part,
                                                            DevScalars* scal) {
+  const int blocks = (range[1] - range[0] + kSweepWaves - 1) / kSweepWaves;   // 8-wave groups
   __shared__ double s_w2[256], s_r2[256];
   __shared__ long long s_z[256];
   __shared__ float s_m[256];
@@ -408,9 +447,9 @@ __global__ __launch_bounds__(256) void sweep_reduce_kernel(int blocks, const Swe
   }
 }
 
-hipError_t launch_sweep_reduce(const Geom& g, const Buffers& b, int blocks, hipStream_t st) {
+hipError_t launch_sweep_reduce(const Geom& g, const Buffers& b, const int* range, hipStream_t st) {
   (void)g;
-  sweep_reduce_kernel<<<1, 256, 0, st>>>(blocks, b.sw_part, b.scal);
+  sweep_reduce_kernel<<<1, 256, 0, st>>>(range, b.sw_part, b.scal);
   return hipGetLastError();
 }
 

@@ -17,7 +17,8 @@ class ServerParams(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("n_streams", ctypes.c_int32),
                 ("sc_iters", ctypes.c_int32), ("dict_every", ctypes.c_int32),
                 ("max_slots", ctypes.c_int32), ("hbm_budget", ctypes.c_uint64),
-                ("device", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("use_graphs", ctypes.c_int32)]
 
 
 class ServeResult(ctypes.Structure):
@@ -32,7 +33,8 @@ class ServeStats(ctypes.Structure):
                 ("failed", ctypes.c_int64), ("in_flight", ctypes.c_int64),
                 ("queued", ctypes.c_int64), ("slots", ctypes.c_int64),
                 ("slot_bytes", ctypes.c_int64), ("peak_slot_bytes", ctypes.c_int64),
-                ("slot_creations", ctypes.c_int64), ("slot_evictions", ctypes.c_int64)]
+                ("slot_creations", ctypes.c_int64), ("slot_evictions", ctypes.c_int64),
+                ("graph_frames", ctypes.c_int64), ("graph_captures", ctypes.c_int64)]
 
 
 EXPORTED = ["bpfa_server_params_default", "bpfa_server_create", "bpfa_server_set_dictionary",
@@ -68,7 +70,8 @@ class Server:
     """Live-feed server: per-stream dictionaries resident on the GPU, frames of any size."""
 
     def __init__(self, patch=(10, 10), stride=None, K=128, n_streams=4, sc_iters=5, dict_every=10,
-                 max_slots=4, hbm_budget=16 << 30, seed=0, device=0, precision="fp32", **hyper):
+                 max_slots=4, hbm_budget=16 << 30, seed=0, device=0, precision="fp32", use_graphs=True,
+                 **hyper):
         p = ServerParams()
         lib.bpfa_server_params_default(ctypes.byref(p))
         p.ndim = len(patch)
@@ -78,6 +81,7 @@ class Server:
         p.K, p.n_streams, p.sc_iters, p.dict_every = int(K), int(n_streams), int(sc_iters), int(dict_every)
         p.max_slots, p.hbm_budget, p.seed, p.device = int(max_slots), int(hbm_budget), int(seed), int(device)
         p.precision = _b.precision_code(precision)
+        p.use_graphs = 1 if use_graphs else 0
         for k, v in hyper.items():
             setattr(p, k, float(v))
         self.params = p

@@ -9,6 +9,9 @@
 * Admission respects the HBM budget: frames larger than the whole budget
   fail with ENOMEM, the slot bytes never exceed the budget, and idle slots of
   other shapes are evicted to make room.
+* Frames replayed from a slot's captured graph equal frames launched
+  directly, bit for bit, in both precision forms and for both kinds of frame
+  (with and without the dictionary iteration).
 """
 import numpy as np
 import pytest
@@ -37,11 +40,12 @@ def frames_for(stream, n, sizes=(40, 52)):
 
 
 def run_server(frames_by_stream, n_streams, max_slots=4, sc_iters=2, dict_every=3, budget=8 << 30,
-               order="interleave", precision="bf16"):
-    print("server: streams=%d slots=%d %s" % (n_streams, max_slots, precision), flush=True)
+               order="interleave", precision="bf16", use_graphs=True):
+    print("server: streams=%d slots=%d %s graphs=%d" % (n_streams, max_slots, precision, use_graphs),
+          flush=True)
     srv = serve.Server(patch=PATCH, K=K, n_streams=n_streams, sc_iters=sc_iters,
                        dict_every=dict_every, max_slots=max_slots, hbm_budget=budget, seed=SEED,
-                       precision=precision)
+                       precision=precision, use_graphs=use_graphs)
     tickets = {}
     if order == "interleave":
         n = max(len(v) for v in frames_by_stream.values())
@@ -180,3 +184,22 @@ def test_failed_frame_leaves_stream_state():
     ref = direct_sequence(good, stream=3, dict_every=0, precision="fp32")
     assert np.array_equal(outs[(3, 0)][1], ref[0])
     assert np.array_equal(outs[(3, 2)][1], ref[1]), "frame after the failure"
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_graph_replay_matches_direct_launches(precision):
+    """Two streams, frames of two sizes, a dictionary iteration every third
+    frame: each slot runs its first frame of a kind directly, captures the
+    second and replays the rest.  The same sequence with graphs off gives
+    the same reconstructions bit for bit."""
+    frames = {s: frames_for(10 + s, 8, sizes=(40, 52)) for s in range(2)}
+    graphed, gst = run_server(frames, n_streams=2, max_slots=4, precision=precision, use_graphs=True)
+    direct, dst = run_server(frames, n_streams=2, max_slots=4, precision=precision, use_graphs=False)
+    print("graph captures %d, replayed frames %d" % (gst["graph_captures"], gst["graph_frames"]),
+          flush=True)
+    assert gst["completed"] == 16 and dst["completed"] == 16
+    assert gst["graph_captures"] >= 2 and gst["graph_frames"] >= 6
+    assert dst["graph_captures"] == 0 and dst["graph_frames"] == 0
+    for key in direct:
+        assert graphed[key][0] == bpfa.OK and direct[key][0] == bpfa.OK
+        assert np.array_equal(graphed[key][1], direct[key][1]), "frame %s" % (key,)
