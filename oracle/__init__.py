@@ -14,4 +14,4 @@ independent facts: Philox known-answer vectors, scipy distributions,
 quadrature, dense Gaussian algebra, brute-force enumeration of all 2^K
 configurations, Geweke's joint-distribution test and closed-form coverage.
 """
-from . import bpfa, gamma, patches, philox  # noqa: F401
+from . import acquire, bpfa, gamma, patches, philox  # noqa: F401

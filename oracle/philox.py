@@ -29,6 +29,7 @@ TAG_PI_B = 4    # Beta denominator gamma for atom k: (k, attempt)
 TAG_GS = 5      # weight precision gamma: (0, attempt)
 TAG_GE = 6      # noise precision gamma: (0, attempt)
 TAG_INIT = 7    # initial dictionary: (pixel position, atom), iteration word 0
+TAG_ACQ = 8     # acquisition masks of a served stream: (pixel or line, hop), frame index
 
 
 def philox4x32_10_int(c0, c1, c2, c3, k0, k1):
