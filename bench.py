@@ -210,6 +210,43 @@ def serving_run(duration_s=8.0, rate=30.0, n_streams=4, seed=7, saturate_frames=
     return out
 
 
+def isolated_latency(frames=20, precision="fp32"):
+    """Per-frame latency with nothing else in flight: one stream, one frame at a
+    time (submit, wait for its result), for every serving frame size, with the
+    slots' graph replay on and off.  The frame work is the serving leg's (5
+    sparse-coding iterations, K = 128, 10 x 10 patches, 10% sampled), from
+    submission to the reconstruction in host memory; two warm-up frames per
+    size let each slot capture its graph first."""
+    import numpy as np
+    from paper_2311_15061_amd import bpfa, serve
+    import synth
+    base = synth.workload("stem512")
+    out = {}
+    for graphs in (True, False):
+        srv = serve.Server(patch=base.patch, K=base.K, n_streams=1, sc_iters=5, dict_every=0,
+                           max_slots=3, hbm_budget=64 << 30, seed=0x15, precision=precision,
+                           use_graphs=graphs)
+        for side in synth.lattice.SERVING_SIZES:
+            y, _, _ = synth.make_frame(base, data_seed=6000 + side, shape=(side, side))
+            rng = np.random.Generator(np.random.PCG64(side))
+            lat = []
+            for f in range(frames + 2):
+                m = synth.make_mask((side, side), 0.10, rng)
+                srv.submit(0, y, m)
+                srv.drain()
+                r = srv.poll(10)
+                assert r and r[0]["status"] == 0, r
+                if f >= 2:
+                    lat.append(r[0]["latency_ms"])
+            key = "%s_%d" % ("graph" if graphs else "direct", side)
+            out[key + "_p50_ms"] = float(np.percentile(lat, 50))
+            out[key + "_p99_ms"] = float(np.percentile(lat, 99))
+        st = srv.stats()
+        out[("graph" if graphs else "direct") + "_replayed_frames"] = st["graph_frames"]
+        srv.close()
+    return out
+
+
 def time_to_solution(epochs=2, reps=3):
     """Context for the paper's one published timing (Time-to-solution section:
     a greyscale 1024 x 1024 image, a dictionary of 64 atoms of 10 x 10 patches
@@ -483,6 +520,7 @@ def main():
         res["serving"] = sv
         res["serving_bf16"] = serving_run(duration_s=args.serving_seconds, precision="bf16")
         res["p99_frame_latency_ms_512"] = sv.get("p99_ms_512")
+        res["serving_isolated_latency"] = isolated_latency()
     if not args.no_tts:
         res["paper_time_to_solution"] = time_to_solution()
     if not args.no_extras:

@@ -99,6 +99,60 @@ typedef struct {
   int32_t learned;       /* 1 if the frame ran a dictionary iteration */
 } bpfa_serve_result;
 
+/* Acquisition policies of a stream (Feature summary: pre-determined indexing
+ * methods, and on-the-fly strategic selections that improve the
+ * reconstruction; the paper gives no rule, these are the library's).  Masks
+ * are drawn on the device from Philox4x32-10 under the server's seed with
+ * counter (pixel or line, hop, frame index of the stream, 8 | stream << 8);
+ * word 0 gives the uniform u = (floor(w / 2^9) + 1/2) 2^-23 and a pixel is
+ * acquired when u < p (binary64):
+ *   BPFA_ACQ_UNIFORM   p = fraction for every pixel;
+ *   BPFA_ACQ_LINE_HOP  each line along the last axis from a random start by
+ *                      hops of 1 .. hmax pixels, hmax = max(1,
+ *                      floor(2 / fraction + 1/2) - 1): start floor(u hmax)
+ *                      (counter (line, 0)), hop j moves floor(u_j hmax) + 1
+ *                      (counter (line, j));
+ *   BPFA_ACQ_TARGETED  p_q = min(1, (1 - s) f + s f M v_q / sum v) with f the
+ *                      fraction, s = targeted_share, M the pixel count and v
+ *                      the per-pixel posterior variance of the last
+ *                      var_samples samples of the stream's previous frame
+ *                      (the uniform rule when the stream has no variance of
+ *                      this shape yet, or sum v = 0).
+ * BPFA_ACQ_CALLER (the default) takes the caller's masks only. */
+enum { BPFA_ACQ_CALLER = 0, BPFA_ACQ_UNIFORM = 1, BPFA_ACQ_LINE_HOP = 2, BPFA_ACQ_TARGETED = 3 };
+
+typedef struct {
+  int32_t kind;            /* BPFA_ACQ_* */
+  int32_t var_samples;     /* TARGETED: the last 2 .. (sc_iters + 1) samples of a frame whose
+                              spread steers the next frame */
+  double fraction;         /* expected acquired fraction, (0, 1] */
+  double targeted_share;   /* TARGETED: share of the expected acquisitions placed by v, [0, 1] */
+} bpfa_acq_policy;
+
+/* Set stream `stream`'s policy (waits for the stream to be idle; a new
+ * policy forgets the stream's variance).  EINVAL for a bad stream, kind,
+ * fraction, share or sample count. */
+bpfa_status bpfa_server_set_policy(bpfa_server_t s, int32_t stream, const bpfa_acq_policy* policy);
+
+/* Queue one frame of a stream whose policy is not BPFA_ACQ_CALLER: `scene`
+ * (host, prod(shape) floats, copied before return) is what the instrument
+ * would see; the server acquires the pixels its policy draws for this frame
+ * and reconstructs from those only.  out as for bpfa_server_submit; mask_out,
+ * if not NULL, receives the frame's mask (prod(shape) bytes, 1 = acquired;
+ * valid when the ticket is reported).  EINVAL for a stream without a policy. */
+bpfa_status bpfa_server_submit_scene(bpfa_server_t s, int32_t stream, const int64_t* shape,
+                                     const float* scene, float* out, uint8_t* mask_out,
+                                     uint64_t* ticket);
+
+/* The mask the policy gives frame `frame` of stream `stream` under `seed`
+ * (the server's rule, computed on the device `device`): ndim / shape as for a
+ * frame, weights the variance v for BPFA_ACQ_TARGETED (NULL: the uniform
+ * rule), mask prod(shape) bytes; weights and mask of kind `mem`.
+ * Synchronises.  EINVAL for a bad policy. */
+bpfa_status bpfa_acquire_mask(const bpfa_acq_policy* policy, int32_t ndim, const int64_t* shape,
+                              const float* weights, uint64_t seed, int32_t stream, int64_t frame,
+                              uint8_t* mask, bpfa_mem mem, int32_t device);
+
 /* Completed frames since the last poll, oldest first; at most `max`.  */
 bpfa_status bpfa_server_poll(bpfa_server_t s, bpfa_serve_result* results, int32_t max,
                              int32_t* n);

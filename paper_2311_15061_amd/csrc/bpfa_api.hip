@@ -65,7 +65,7 @@ struct Layout {
   // byte offsets
   size_t image, mask, poff, pcoord, obs_bits, obs_count, perm, inv_perm, obs_idx, obs_val, sweep_waves, fplan, sort_hist, sort_bin,
       omega, omega_c, omega_blk, vpatch, omega_y, D, list0, list1, nact0, nact1, Ck, ell, scal, nk, sw_cnt, sw_part, dpart,
-      dx2, Cfull, Bvec, diag, x2p, sumr2_p, Y, recon, mean, mean2, total;
+      dx2, Cfull, Bvec, diag, x2p, sumr2_p, Y, recon, mean, mean2, var, wsum, total;
 };
 
 bpfa_status make_geom(const bpfa_params* p, Geom* g) {
@@ -228,6 +228,8 @@ Layout make_layout(const Geom& g) {
   L.recon = take(4 * (size_t)g.Mtot);
   L.mean = take(8 * (size_t)g.Mtot);   // posterior-moment running sums
   L.mean2 = take(8 * (size_t)g.Mtot);
+  L.var = take(4 * (size_t)g.Mtot);    // a served frame's posterior variance
+  L.wsum = take(8);                     // sum of acquisition weights
   L.total = off;
   return L;
 }
@@ -1177,19 +1179,55 @@ int problem_upload_frame(bpfa_problem* h, const float* image, const uint8_t* mas
   return BPFA_OK;
 }
 
-int problem_frame_body(bpfa_problem* h, int sc_iters, int learn) {
+int problem_frame_body(bpfa_problem* h, int sc_iters, int learn, int var_samples) {
   DeviceGuard dg(h->prm.device);
   if (h->timing) return fail(BPFA_ESTATE, "a served frame runs without per-phase timing");
   if (h->n_batches != 1) return fail(BPFA_ESTATE, "a served frame runs full-batch iterations");
   bpfa_status r = index_frame(h, false, false);
   if (r != BPFA_OK) return r;
-  for (int it = 0; it < sc_iters; ++it)
-    if ((r = run_step(h, 0, -1)) != BPFA_OK) return r;
-  if (learn && (r = run_step(h, 1, -1)) != BPFA_OK) return r;
-  HIPCHK(launch_recon(h->g, h->b, h->cur, h->L.Npad, (float*)(h->ws + h->L.recon),
-                      h->precision == BPFA_BF16, h->st));
+  const int n_it = sc_iters + (learn ? 1 : 0);
+  const int V = std::min(var_samples, n_it);
+  float* x = (float*)(h->ws + h->L.recon);
+  double* s1 = (double*)(h->ws + h->L.mean);
+  double* s2 = (double*)(h->ws + h->L.mean2);
+  for (int it = 0; it < n_it; ++it) {
+    if ((r = run_step(h, it < sc_iters ? 0 : 1, -1)) != BPFA_OK) return r;
+    // the last V samples: their reconstructions into the binary64 moment
+    // sums (the last one is the frame's result)
+    if (V >= 2 && it >= n_it - V) {
+      HIPCHK(launch_recon(h->g, h->b, h->cur, h->L.Npad, x, h->precision == BPFA_BF16, h->st));
+      HIPCHK(launch_mean_add(h->g.Mtot, x, s1, s2, it == n_it - V, h->st));
+    }
+  }
+  if (V >= 2) {
+    HIPCHK(launch_variance_get(h->g.Mtot, s1, s2, (double)V, (float*)(h->ws + h->L.var), h->st));
+  } else {
+    HIPCHK(launch_recon(h->g, h->b, h->cur, h->L.Npad, x, h->precision == BPFA_BF16, h->st));
+  }
+  h->mean_count = 0;   // the moment sums hold a frame's samples, not the caller's mean
   return BPFA_OK;
 }
+
+int problem_upload_image(bpfa_problem* h, const float* image) {
+  DeviceGuard dg(h->prm.device);
+  HIPCHK(hipMemcpyAsync(h->b.image, image, 4 * (size_t)h->g.Mtot, hipMemcpyHostToDevice, h->st));
+  return BPFA_OK;
+}
+
+int problem_acquire(bpfa_problem* h, const AcqArgs& a, int kind, const float* weights) {
+  DeviceGuard dg(h->prm.device);
+  const Geom& g = h->g;
+  int64_t shape[kMaxDim];
+  for (int d = 0; d < g.ndim; ++d) shape[d] = g.M[d];
+  AcqArgs aa = a;
+  aa.M = g.Mtot;
+  HIPCHK(launch_acquire(aa, kind, g.ndim, shape, weights, (double*)(h->ws + h->L.wsum), h->b.mask,
+                        h->st));
+  return BPFA_OK;
+}
+
+const float* problem_variance(bpfa_problem* h) { return (const float*)(h->ws + h->L.var); }
+const uint8_t* problem_mask(bpfa_problem* h) { return h->b.mask; }
 
 int problem_frame_result(bpfa_problem* h, float* out) {
   DeviceGuard dg(h->prm.device);

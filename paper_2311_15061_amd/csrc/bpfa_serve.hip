@@ -30,6 +30,7 @@
 
 #include "../../include/bpfa_serve.h"
 #include "internal.hpp"
+#include "philox.hpp"
 
 namespace {
 
@@ -51,6 +52,8 @@ struct Frame {
   int64_t frame_index = 0;
   long long t0 = 1;           // first Philox iteration number of this frame
   bool learn = false;
+  bool scene = false;         // the stream's policy draws the mask (img is the scene)
+  uint8_t* mask_out = nullptr;  // caller's host buffer for the drawn mask, or NULL
 };
 
 struct Slot {
@@ -60,8 +63,9 @@ struct Slot {
   // the frame body as a replayable graph per kind of frame (0: sparse coding
   // only, 1: with the dictionary iteration); the first frame of a kind runs
   // uncaptured, the second is captured
-  hipGraphExec_t exec[2] = {nullptr, nullptr};
-  int runs[2] = {0, 0};
+  // [learn][variance kept]
+  hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  int runs[2][2] = {{0, 0}, {0, 0}};
   bool graphs_ok = true;      // a capture failed: this slot runs uncaptured from then on
   int64_t graph_frames = 0, captures = 0;
   bool busy = false;
@@ -74,6 +78,14 @@ struct Slot {
 struct StreamState {
   void* blob = nullptr;       // device: D, logit pi, gammas
   void* pending = nullptr;    // device: where a frame saves its state until it is known good
+  bpfa_acq_policy pol{};      // acquisition policy (kind BPFA_ACQ_CALLER: the caller's masks)
+  // targeted policy: the posterior variance of the last good frame (weights)
+  // and of the frame in flight (pending), device, both of shape wshape
+  float* weights = nullptr;
+  float* wpending = nullptr;
+  size_t wcap = 0;            // floats each weight buffer holds
+  std::vector<int64_t> wshape;
+  bool wvalid = false;
   long long t = 1;
   int64_t frames = 0;
   bool busy = false;
@@ -139,7 +151,7 @@ void finish(bpfa_server* s, Frame* f, int status, bool learned) {
   if (status == BPFA_OK) ++s->completed;
   else ++s->failed;
   (void)hipHostFree(f->img);
-  (void)hipHostFree(f->mask);
+  if (f->mask) (void)hipHostFree(f->mask);
   delete f;
 }
 
@@ -148,23 +160,25 @@ void finish(bpfa_server* s, Frame* f, int status, bool learned) {
 // on the way when this kind has run once before (the direct run also sets
 // the kernels' launch attributes) and graphs are on.  A capture that fails
 // leaves the slot on direct runs.
-int run_body(bpfa_server* s, Slot* sl, int learn) {
+int run_body(bpfa_server* s, Slot* sl, int learn, int var_samples) {
   bpfa_t h = sl->h;
   const int sc = s->prm.sc_iters;
+  const int kv = var_samples >= 2 ? 1 : 0;
   hipStream_t hs = bpfa::problem_stream(h);
-  if (sl->exec[learn]) {
+  hipGraphExec_t& exec = sl->exec[learn][kv];
+  if (exec) {
     ++sl->graph_frames;
-    return hipGraphLaunch(sl->exec[learn], hs) == hipSuccess ? BPFA_OK : BPFA_EDEVICE;
+    return hipGraphLaunch(exec, hs) == hipSuccess ? BPFA_OK : BPFA_EDEVICE;
   }
-  const bool capture = s->prm.use_graphs && sl->graphs_ok && sl->runs[learn] >= 1;
-  ++sl->runs[learn];
-  if (!capture) return bpfa::problem_frame_body(h, sc, learn);
+  const bool capture = s->prm.use_graphs && sl->graphs_ok && sl->runs[learn][kv] >= 1;
+  ++sl->runs[learn][kv];
+  if (!capture) return bpfa::problem_frame_body(h, sc, learn, var_samples);
   if (hipStreamBeginCapture(hs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     sl->graphs_ok = false;
     (void)hipGetLastError();
-    return bpfa::problem_frame_body(h, sc, learn);
+    return bpfa::problem_frame_body(h, sc, learn, var_samples);
   }
-  const int st = bpfa::problem_frame_body(h, sc, learn);
+  const int st = bpfa::problem_frame_body(h, sc, learn, var_samples);
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(hs, &graph);
   hipGraphExec_t ex = nullptr;
@@ -174,9 +188,9 @@ int run_body(bpfa_server* s, Slot* sl, int learn) {
   if (!ok) {
     (void)hipGetLastError();
     sl->graphs_ok = false;
-    return bpfa::problem_frame_body(h, sc, learn);
+    return bpfa::problem_frame_body(h, sc, learn, var_samples);
   }
-  sl->exec[learn] = ex;
+  exec = ex;
   ++sl->captures;
   ++sl->graph_frames;
   return hipGraphLaunch(ex, hs) == hipSuccess ? BPFA_OK : BPFA_EDEVICE;
@@ -190,14 +204,58 @@ int run_body(bpfa_server* s, Slot* sl, int learn) {
 // its last good state and iteration.
 int run_frame(bpfa_server* s, Slot* sl, Frame* f, StreamState* ss) {
   bpfa_t h = sl->h;
-  int st = bpfa::problem_upload_frame(h, f->img, f->mask);
+  hipStream_t hs = bpfa::problem_stream(h);
+  const bpfa_acq_policy& pol = ss->pol;
+  const bool targeted = pol.kind == BPFA_ACQ_TARGETED;
+  int st;
+  if (f->scene) {
+    // the policy's mask for this frame of the stream, drawn on the device
+    st = bpfa::problem_upload_image(h, f->img);
+    if (st != BPFA_OK) return st;
+    bpfa::AcqArgs a{};
+    a.rho = pol.fraction;
+    a.share = pol.targeted_share;
+    a.key0 = (uint32_t)(s->prm.seed & 0xFFFFFFFFu);
+    a.key1 = (uint32_t)(s->prm.seed >> 32);
+    a.frame = (uint32_t)f->frame_index;
+    a.stream_word = bpfa::kTagAcq | ((uint32_t)f->stream << 8);
+    const float* w = targeted && ss->wvalid && ss->wshape == f->shape ? ss->weights : nullptr;
+    st = bpfa::problem_acquire(h, a, pol.kind, w);
+  } else {
+    st = bpfa::problem_upload_frame(h, f->img, f->mask);
+  }
   if (st != BPFA_OK) return st;
   st = bpfa::problem_import_dict(h, ss->blob, f->t0, (uint32_t)f->stream);
   if (st != BPFA_OK) return st;
-  st = run_body(s, sl, f->learn ? 1 : 0);
+  st = run_body(s, sl, f->learn ? 1 : 0, targeted ? pol.var_samples : 0);
   if (st == BPFA_OK) st = bpfa::problem_export_dict(h, ss->pending);
+  if (st == BPFA_OK && targeted) {
+    // the frame's variance steers the stream's next frame once the frame is good
+    const size_t px = (size_t)f->pixels;
+    if (ss->wcap < px) {
+      (void)hipStreamSynchronize(hs);
+      (void)hipFree(ss->weights);
+      (void)hipFree(ss->wpending);
+      ss->weights = ss->wpending = nullptr;
+      ss->wcap = 0;
+      ss->wvalid = false;
+      if (hipMalloc((void**)&ss->weights, 4 * px) != hipSuccess ||
+          hipMalloc((void**)&ss->wpending, 4 * px) != hipSuccess)
+        st = BPFA_ENOMEM;
+      else
+        ss->wcap = px;
+    }
+    if (st == BPFA_OK &&
+        hipMemcpyAsync(ss->wpending, bpfa::problem_variance(h), 4 * px, hipMemcpyDeviceToDevice, hs) !=
+            hipSuccess)
+      st = BPFA_EDEVICE;
+  }
+  if (st == BPFA_OK && f->mask_out &&
+      hipMemcpyAsync(f->mask_out, bpfa::problem_mask(h), (size_t)f->pixels, hipMemcpyDeviceToHost, hs) !=
+          hipSuccess)
+    st = BPFA_EDEVICE;
   if (st != BPFA_OK) {
-    (void)hipStreamSynchronize(bpfa::problem_stream(h));   // the frame's buffers stay valid until then
+    (void)hipStreamSynchronize(hs);   // the frame's buffers stay valid until then
     return st;
   }
   // synchronises the slot's stream; reports a refused frame or a numeric
@@ -218,6 +276,11 @@ void worker_loop(bpfa_server* s, Slot* sl) {
     const bool learned = f->learn;
     if (st == BPFA_OK) {
       std::swap(ss->blob, ss->pending);   // the frame's state becomes the stream's
+      if (ss->pol.kind == BPFA_ACQ_TARGETED) {
+        std::swap(ss->weights, ss->wpending);
+        ss->wshape = f->shape;
+        ss->wvalid = true;
+      }
       ss->t = f->t0 + s->prm.sc_iters + (learned ? 1 : 0);
     }
     ss->busy = false;
@@ -232,8 +295,9 @@ void worker_loop(bpfa_server* s, Slot* sl) {
 
 void destroy_slot(Slot* sl) {
   if (sl->worker.joinable()) sl->worker.join();
-  for (auto& ex : sl->exec)
-    if (ex) (void)hipGraphExecDestroy(ex);
+  for (auto& row : sl->exec)
+    for (auto& ex : row)
+      if (ex) (void)hipGraphExecDestroy(ex);
   if (sl->h) bpfa_destroy(sl->h);
   delete sl;
 }
@@ -482,11 +546,11 @@ bpfa_status bpfa_server_set_dictionary(bpfa_server_t s, int32_t stream, bpfa_t s
   return (bpfa_status)st;
 }
 
-bpfa_status bpfa_server_submit(bpfa_server_t s, int32_t stream, const int64_t* shape,
-                               const float* image, const uint8_t* mask, float* out,
-                               uint64_t* ticket) {
-  if (!s || !shape || !image || !mask || !out || stream < 0 || stream >= s->prm.n_streams)
-    return BPFA_EINVAL;
+namespace {
+
+// Queue a frame: mask NULL for a scene (the stream's policy draws it).
+bpfa_status queue_frame(bpfa_server_t s, int32_t stream, const int64_t* shape, const float* image,
+                        const uint8_t* mask, float* out, uint8_t* mask_out, uint64_t* ticket) {
   const Clock::time_point arrival = Clock::now();
   std::vector<int64_t> shp(shape, shape + s->prm.ndim);
   bpfa_params fp = frame_params(s->prm, shp);
@@ -498,15 +562,22 @@ bpfa_status bpfa_server_submit(bpfa_server_t s, int32_t stream, const int64_t* s
   f->shape = shp;
   f->pixels = frame_pixels(s->prm.ndim, shape);
   f->out = out;
+  f->scene = mask == nullptr;
+  f->mask_out = mask_out;
   if (hipHostMalloc((void**)&f->img, 4 * (size_t)f->pixels, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&f->mask, (size_t)f->pixels, hipHostMallocDefault) != hipSuccess) {
+      (mask && hipHostMalloc((void**)&f->mask, (size_t)f->pixels, hipHostMallocDefault) != hipSuccess)) {
     (void)hipHostFree(f->img);
     delete f;
     return BPFA_ENOMEM;
   }
   std::memcpy(f->img, image, 4 * (size_t)f->pixels);
-  std::memcpy(f->mask, mask, (size_t)f->pixels);
+  if (mask) std::memcpy(f->mask, mask, (size_t)f->pixels);
   std::lock_guard<std::mutex> lk(s->mu);
+  if (f->scene && s->streams[stream].pol.kind == BPFA_ACQ_CALLER) {
+    (void)hipHostFree(f->img);
+    delete f;
+    return BPFA_EINVAL;
+  }
   f->submit_t = arrival;
   f->ticket = s->next_ticket++;
   if (ticket) *ticket = f->ticket;
@@ -515,6 +586,88 @@ bpfa_status bpfa_server_submit(bpfa_server_t s, int32_t stream, const int64_t* s
   ++s->queued;
   s->cv_disp.notify_all();
   return BPFA_OK;
+}
+
+bool policy_ok(const bpfa_acq_policy* p, int sc_iters) {
+  if (!p) return false;
+  if (p->kind < BPFA_ACQ_CALLER || p->kind > BPFA_ACQ_TARGETED) return false;
+  if (p->kind == BPFA_ACQ_CALLER) return true;
+  if (!(p->fraction > 0.0 && p->fraction <= 1.0)) return false;
+  if (p->kind == BPFA_ACQ_TARGETED &&
+      (!(p->targeted_share >= 0.0 && p->targeted_share <= 1.0) || p->var_samples < 2 ||
+       p->var_samples > sc_iters + 1))
+    return false;
+  return true;
+}
+
+}  // namespace
+
+bpfa_status bpfa_server_submit(bpfa_server_t s, int32_t stream, const int64_t* shape,
+                               const float* image, const uint8_t* mask, float* out,
+                               uint64_t* ticket) {
+  if (!s || !shape || !image || !mask || !out || stream < 0 || stream >= s->prm.n_streams)
+    return BPFA_EINVAL;
+  return queue_frame(s, stream, shape, image, mask, out, nullptr, ticket);
+}
+
+bpfa_status bpfa_server_submit_scene(bpfa_server_t s, int32_t stream, const int64_t* shape,
+                                     const float* scene, float* out, uint8_t* mask_out,
+                                     uint64_t* ticket) {
+  if (!s || !shape || !scene || !out || stream < 0 || stream >= s->prm.n_streams)
+    return BPFA_EINVAL;
+  return queue_frame(s, stream, shape, scene, nullptr, out, mask_out, ticket);
+}
+
+bpfa_status bpfa_server_set_policy(bpfa_server_t s, int32_t stream, const bpfa_acq_policy* policy) {
+  if (!s || stream < 0 || stream >= s->prm.n_streams || !policy_ok(policy, s->prm.sc_iters))
+    return BPFA_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  StreamState& ss = s->streams[stream];
+  s->cv_done.wait(lk, [&] { return !ss.busy && ss.fifo.empty(); });
+  ss.pol = *policy;
+  ss.wvalid = false;
+  return BPFA_OK;
+}
+
+bpfa_status bpfa_acquire_mask(const bpfa_acq_policy* policy, int32_t ndim, const int64_t* shape,
+                              const float* weights, uint64_t seed, int32_t stream, int64_t frame,
+                              uint8_t* mask, bpfa_mem mem, int32_t device) {
+  if (!policy || policy->kind == BPFA_ACQ_CALLER || !policy_ok(policy, 1 << 20) || !shape || !mask ||
+      ndim < 1 || ndim > 4 || stream < 0 || stream >= (1 << 24) || frame < 0)
+    return BPFA_EINVAL;
+  int64_t M = 1;
+  for (int d = 0; d < ndim; ++d) {
+    if (shape[d] < 1) return BPFA_EINVAL;
+    M *= shape[d];
+  }
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  if (hipSetDevice(device) != hipSuccess) return BPFA_EDEVICE;
+  bpfa::AcqArgs a{};
+  a.M = M;
+  a.rho = policy->fraction;
+  a.share = policy->targeted_share;
+  a.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
+  a.key1 = (uint32_t)(seed >> 32);
+  a.frame = (uint32_t)frame;
+  a.stream_word = bpfa::kTagAcq | ((uint32_t)stream << 8);
+  char* tmp = nullptr;
+  const size_t wbytes = weights && policy->kind == BPFA_ACQ_TARGETED ? 4 * (size_t)M : 0;
+  const size_t need = 16 + wbytes + (mem == BPFA_HOST ? (size_t)M : 0);
+  hipError_t e = hipMalloc((void**)&tmp, need);
+  const float* w = wbytes ? weights : nullptr;
+  uint8_t* m = mask;
+  if (e == hipSuccess && wbytes && mem == BPFA_HOST) {
+    e = hipMemcpy(tmp + 16, weights, wbytes, hipMemcpyHostToDevice);
+    w = (const float*)(tmp + 16);
+  }
+  if (mem == BPFA_HOST) m = (uint8_t*)(tmp + 16 + wbytes);
+  if (e == hipSuccess) e = bpfa::launch_acquire(a, policy->kind, ndim, shape, w, (double*)tmp, m, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess && mem == BPFA_HOST) e = hipMemcpy(mask, m, (size_t)M, hipMemcpyDeviceToHost);
+  if (tmp) (void)hipFree(tmp);
+  if (prev >= 0) (void)hipSetDevice(prev);
+  return e == hipSuccess ? BPFA_OK : BPFA_EDEVICE;
 }
 
 bpfa_status bpfa_server_poll(bpfa_server_t s, bpfa_serve_result* results, int32_t max, int32_t* n) {
@@ -582,6 +735,8 @@ void bpfa_server_destroy(bpfa_server_t s) {
     }
     if (ss.blob) (void)hipFree(ss.blob);
     if (ss.pending) (void)hipFree(ss.pending);
+    if (ss.weights) (void)hipFree(ss.weights);
+    if (ss.wpending) (void)hipFree(ss.wpending);
   }
   delete s;
 }

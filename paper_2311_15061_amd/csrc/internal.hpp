@@ -240,6 +240,18 @@ hipError_t launch_mean_add(long long n, const float* x, double* sum, double* sum
 hipError_t launch_mean_get(long long n, const double* sum, double count, float* out, hipStream_t st);
 hipError_t launch_variance_get(long long n, const double* sum, const double* sum2, double count,
                                float* out, hipStream_t st);
+// Acquisition masks (policies of bpfa_serve.h): kinds and the Philox
+// counter words of one mask (seed, frame index, stream word).
+enum { kAcqUniform = 1, kAcqLineHop = 2, kAcqTargeted = 3 };
+struct AcqArgs {
+  long long M;            // pixels
+  double rho, share;      // expected acquired fraction; targeted share
+  uint32_t key0, key1, frame, stream_word;
+};
+// mask[0 .. M) for the policy `kind` (targeted: weights may be NULL, then
+// the uniform rule; wsum is one binary64 of device scratch)
+hipError_t launch_acquire(const AcqArgs& a, int kind, int ndim, const int64_t* shape,
+                          const float* weights, double* wsum, uint8_t* mask, hipStream_t st);
 hipError_t launch_recon(const Geom& g, const Buffers& b, int cur, int Npad, float* out, bool bf16,
                         hipStream_t st);
 hipError_t launch_recon_patches_mfma(const Geom& g, const Buffers& b, int cur, hipStream_t st);
@@ -275,14 +287,23 @@ int problem_dims(bpfa_problem* h, int* K, int* P);
 // and mask from pinned host memory (no synchronisation; the buffers must
 // stay valid until the stream has copied them).  body: patch index (codes
 // cleared), sc_iters sparse-coding iterations, a dictionary iteration if
-// `learn`, the reconstruction into the workspace -- launches only, with no
-// pointer that changes between frames, so the body can be captured into a
-// graph and replayed for any frame of the handle's shape.  result:
+// `learn`, the reconstruction into the workspace, and with var_samples >= 2
+// the per-pixel posterior variance of the last var_samples samples (their
+// reconstructions' binary64 moments, as bpfa_mean_accumulate keeps them) --
+// launches only, with no pointer that changes between frames, so the body
+// can be captured into a graph and replayed for any frame of the handle's
+// shape.  result:
 // the reconstruction to host `out`, then a synchronisation that reports a
 // refused frame (ESHAPE) or a failed draw (ENUMERIC).
 int problem_upload_frame(bpfa_problem* h, const float* image, const uint8_t* mask);
-int problem_frame_body(bpfa_problem* h, int sc_iters, int learn);
+int problem_frame_body(bpfa_problem* h, int sc_iters, int learn, int var_samples);
 int problem_frame_result(bpfa_problem* h, float* out);
 hipStream_t problem_stream(bpfa_problem* h);
+// the frame's image only (its mask drawn on the device by problem_acquire)
+int problem_upload_image(bpfa_problem* h, const float* image);
+// the frame's mask from an acquisition policy (a.M is set from the handle)
+int problem_acquire(bpfa_problem* h, const AcqArgs& a, int kind, const float* weights);
+const float* problem_variance(bpfa_problem* h);   // device, the last served frame's variance
+const uint8_t* problem_mask(bpfa_problem* h);     // device, the frame's mask
 int problem_set_id(bpfa_problem* h, uint32_t problem_id);
 }  // namespace bpfa

@@ -17,7 +17,8 @@
 namespace bpfa {
 
 enum : uint32_t {
-  kTagZS = 1, kTagDict = 2, kTagPiA = 3, kTagPiB = 4, kTagGS = 5, kTagGE = 6, kTagInit = 7
+  kTagZS = 1, kTagDict = 2, kTagPiA = 3, kTagPiB = 4, kTagGS = 5, kTagGE = 6, kTagInit = 7,
+  kTagAcq = 8   // acquisition masks of a served stream
 };
 
 struct Block4 { uint32_t w0, w1, w2, w3; };

@@ -37,8 +37,24 @@ class ServeStats(ctypes.Structure):
                 ("graph_frames", ctypes.c_int64), ("graph_captures", ctypes.c_int64)]
 
 
+class AcqPolicy(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("var_samples", ctypes.c_int32),
+                ("fraction", ctypes.c_double), ("targeted_share", ctypes.c_double)]
+
+
+ACQ_CALLER, ACQ_UNIFORM, ACQ_LINE_HOP, ACQ_TARGETED = 0, 1, 2, 3
+_ACQ_KINDS = {"caller": ACQ_CALLER, "uniform": ACQ_UNIFORM, "line_hop": ACQ_LINE_HOP,
+              "targeted": ACQ_TARGETED}
+
+
+def make_policy(kind, fraction=0.1, targeted_share=0.5, var_samples=2):
+    return AcqPolicy(kind=_ACQ_KINDS.get(kind, kind), var_samples=int(var_samples),
+                     fraction=float(fraction), targeted_share=float(targeted_share))
+
+
 EXPORTED = ["bpfa_server_params_default", "bpfa_server_create", "bpfa_server_set_dictionary",
-            "bpfa_server_submit", "bpfa_server_poll", "bpfa_server_drain", "bpfa_server_stats",
+            "bpfa_server_submit", "bpfa_server_submit_scene", "bpfa_server_set_policy",
+            "bpfa_acquire_mask", "bpfa_server_poll", "bpfa_server_drain", "bpfa_server_stats",
             "bpfa_server_destroy"]
 
 _P = ctypes.POINTER
@@ -49,6 +65,14 @@ _sig = {
     "bpfa_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_int64),
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                           _P(ctypes.c_uint64)]),
+    "bpfa_server_submit_scene": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_int64),
+                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                _P(ctypes.c_uint64)]),
+    "bpfa_server_set_policy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _P(AcqPolicy)]),
+    "bpfa_acquire_mask": (ctypes.c_int, [_P(AcqPolicy), ctypes.c_int32, _P(ctypes.c_int64),
+                                         ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32,
+                                         ctypes.c_int64, ctypes.c_void_p, ctypes.c_int,
+                                         ctypes.c_int32]),
     "bpfa_server_poll": (ctypes.c_int, [ctypes.c_void_p, _P(ServeResult), ctypes.c_int32,
                                         _P(ctypes.c_int32)]),
     "bpfa_server_drain": (ctypes.c_int, [ctypes.c_void_p]),
@@ -89,6 +113,7 @@ class Server:
         _check(lib.bpfa_server_create(ctypes.byref(p), ctypes.byref(h)))
         self._h = h
         self._pending = {}      # ticket -> output array (kept alive until completion)
+        self._masks = {}        # ticket -> drawn mask of a scene frame
 
     def close(self):
         if getattr(self, "_h", None):
@@ -123,6 +148,27 @@ class Server:
         self._pending[t.value] = out
         return t.value, out
 
+    def set_policy(self, stream, kind, fraction=0.1, targeted_share=0.5, var_samples=2):
+        """Acquisition policy of a stream: "uniform", "line_hop", "targeted" or "caller"."""
+        pol = make_policy(kind, fraction, targeted_share, var_samples)
+        _check(lib.bpfa_server_set_policy(self._h, int(stream), ctypes.byref(pol)))
+
+    def submit_scene(self, stream, scene):
+        """Queue a scene: the stream's policy chooses the acquired pixels.  Returns
+        (ticket, out, mask); both arrays are filled when the ticket is polled."""
+        scene = np.ascontiguousarray(scene, np.float32)
+        if scene.ndim != self.params.ndim:
+            raise ValueError("the scene must have the server's dimension")
+        out = np.empty(scene.shape, np.float32)
+        mask = np.empty(scene.shape, np.uint8)
+        shape = (ctypes.c_int64 * scene.ndim)(*scene.shape)
+        t = ctypes.c_uint64()
+        _check(lib.bpfa_server_submit_scene(self._h, int(stream), shape, scene.ctypes.data,
+                                            out.ctypes.data, mask.ctypes.data, ctypes.byref(t)))
+        self._pending[t.value] = out
+        self._masks[t.value] = mask
+        return t.value, out, mask
+
     def poll(self, max_results=1024):
         buf = (ServeResult * max_results)()
         n = ctypes.c_int32()
@@ -131,6 +177,7 @@ class Server:
         for i in range(n.value):
             r = {name: getattr(buf[i], name) for name, _ in ServeResult._fields_}
             r["out"] = self._pending.pop(r["ticket"], None)
+            r["mask"] = self._masks.pop(r["ticket"], None)
             res.append(r)
         return res
 
@@ -141,3 +188,18 @@ class Server:
         s = ServeStats()
         _check(lib.bpfa_server_stats(self._h, ctypes.byref(s)))
         return {name: getattr(s, name) for name, _ in ServeStats._fields_}
+
+
+def acquire_mask(kind, shape, seed, stream, frame, fraction=0.1, targeted_share=0.5, weights=None,
+                 device=0):
+    """The mask a policy gives frame `frame` of stream `stream` (the server's rule,
+    computed on the GPU); weights: the targeted policy's variance (host array)."""
+    pol = make_policy(kind, fraction, targeted_share, 2)
+    shape = tuple(int(x) for x in shape)
+    mask = np.empty(shape, np.uint8)
+    w = None if weights is None else np.ascontiguousarray(weights, np.float32)
+    shp = (ctypes.c_int64 * len(shape))(*shape)
+    _check(lib.bpfa_acquire_mask(ctypes.byref(pol), len(shape), shp,
+                                 None if w is None else w.ctypes.data, int(seed), int(stream),
+                                 int(frame), mask.ctypes.data, _b.HOST, int(device)))
+    return mask

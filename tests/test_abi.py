@@ -51,6 +51,7 @@ def test_struct_layouts_match_c(bpfa, tmp_path):
                    ' offsetof(bpfa_state_view, mem), sizeof(bpfa_stats), offsetof(bpfa_stats, n_sweeps),'
                    ' sizeof(bpfa_server_params), offsetof(bpfa_server_params, device),'
                    ' sizeof(bpfa_serve_result), sizeof(bpfa_serve_stats));'
+                   'printf("%zu %zu\\n", sizeof(bpfa_acq_policy), offsetof(bpfa_acq_policy, targeted_share));'
                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
@@ -60,7 +61,8 @@ def test_struct_layouts_match_c(bpfa, tmp_path):
     want = [ctypes.sizeof(bpfa.Params), bpfa.Params.stream.offset, ctypes.sizeof(bpfa.StateView),
             bpfa.StateView.mem.offset, ctypes.sizeof(bpfa.Stats), bpfa.Stats.n_sweeps.offset,
             ctypes.sizeof(serve.ServerParams), serve.ServerParams.device.offset,
-            ctypes.sizeof(serve.ServeResult), ctypes.sizeof(serve.ServeStats)]
+            ctypes.sizeof(serve.ServeResult), ctypes.sizeof(serve.ServeStats),
+            ctypes.sizeof(serve.AcqPolicy), serve.AcqPolicy.targeted_share.offset]
     assert got == want
 
 

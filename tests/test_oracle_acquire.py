@@ -36,7 +36,7 @@ def test_uniform_neighbours_are_independent():
 
 def test_line_hop_hops_are_uniform_on_one_to_hmax():
     rho = 0.2
-    hmax = max(1, int(round(2.0 / rho)) - 1)     # 9
+    hmax = max(1, int(np.floor(2.0 / rho + 0.5)) - 1)     # 9
     starts, hops = [], []
     for f in range(6):
         m = acquire.line_hop_mask(SHAPE, rho, SEED, 2, f)
