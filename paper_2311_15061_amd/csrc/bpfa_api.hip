@@ -115,13 +115,21 @@ bpfa_status make_geom(const bpfa_params* p, Geom* g) {
 DictPlan make_dict_plan(const Geom& g) {
   DictPlan pl;
   const int K = g.K;
+  // accumulators per block: 128 KiB, leaving room for large visit chunks; but
+  // when the whole triangle fits beside the smallest chunk (one visit per
+  // thread), one row group: every block then walks each visit's pairs once
+  // instead of once per group
+  const long long whole = (long long)K * (K + 1) / 2 + K;
+  const long long room1 =
+      ((long long)kLdsBytes - (long long)(K + 1) * 4 - (long long)kWave * 8 - (long long)kDictBlock * 10) / 8;
+  const long long budget = whole <= room1 ? whole : kDictLdsEntries;
   int rg = 0;
   pl.row0[0] = 0;
   pl.ent0[0] = 0;
   long long len = 0;
   for (int k = 0; k < K; ++k) {
     const long long add = (K - k) + 1;
-    if (len + add > kDictLdsEntries && len > 0) {
+    if (len + add > budget && len > 0) {
       ++rg;
       pl.row0[rg] = k;
       pl.ent0[rg] = (long long)k * K - (long long)k * (k - 1) / 2;
