@@ -247,11 +247,13 @@ def isolated_latency(frames=20, precision="fp32"):
     return out
 
 
-def time_to_solution(epochs=2, reps=3):
+def time_to_solution(epochs=2, reps=3, batches=(16,)):
     """Context for the paper's one published timing (Time-to-solution section:
     a greyscale 1024 x 1024 image, a dictionary of 64 atoms of 10 x 10 patches
-    trained for two complete epochs, about 4 s on an RTX 3060).  Reading: an
-    epoch is one Gibbs iteration over every patch (full batch); the frame is the
+    trained for two complete epochs, about 4 s on an RTX 3060), in both
+    readings of an epoch: one full-batch Gibbs iteration over every patch, and
+    a pass of mini-batch steps over a partition into B batches (patch i in
+    batch i mod B, each step's statistics scaled by N / n_b).  The frame is the
     1024 x 1024 synthetic lattice with K = 64.  Timed like a user's call, from
     host buffers to the reconstruction in host memory, workspace allocation and
     the patch index included; median of `reps` runs after one warm-up run."""
@@ -264,20 +266,29 @@ def time_to_solution(epochs=2, reps=3):
     y, m, _ = synth.make_frame(wl)
     y = np.ascontiguousarray(y, np.float32)
     m = np.ascontiguousarray(m, np.uint8)
-    times = []
-    for r in range(reps + 1):
-        t0 = time.perf_counter()
-        prob = bpfa.Problem(y, m, wl.patch, wl.stride, K=wl.K, seed=wl.method_seed)
-        prob.iterate(epochs, bpfa.LEARN_DICT)
-        xh = prob.reconstruct()
-        prob.close()
-        if r:
-            times.append(time.perf_counter() - t0)
-    assert np.all(np.isfinite(xh))
-    return {"workload": "1024x1024 lattice, 10x10 patches stride 1, K=64, %d epochs" % epochs,
-            "reading": "epoch = one Gibbs iteration over all patches (full batch)",
-            "seconds": statistics.median(times), "runs": reps,
-            "paper_seconds": 4.0, "paper_hardware": "NVIDIA RTX 3060 (context only)"}
+
+    def timed(run):
+        times = []
+        for r in range(reps + 1):
+            t0 = time.perf_counter()
+            prob = bpfa.Problem(y, m, wl.patch, wl.stride, K=wl.K, seed=wl.method_seed)
+            run(prob)
+            xh = prob.reconstruct()
+            prob.close()
+            if r:
+                times.append(time.perf_counter() - t0)
+        assert np.all(np.isfinite(xh))
+        return statistics.median(times)
+
+    out = {"workload": "1024x1024 lattice, 10x10 patches stride 1, K=64, %d epochs" % epochs,
+           "reading": "epoch = one Gibbs iteration over all patches (full batch)",
+           "seconds": timed(lambda p: p.iterate(epochs, bpfa.LEARN_DICT)), "runs": reps,
+           "paper_seconds": 4.0, "paper_hardware": "NVIDIA RTX 3060 (context only)"}
+    for B in batches:
+        out["minibatch_%d_seconds" % B] = timed(lambda p: p.epochs(epochs, B))
+        out["minibatch_%d_reading" % B] = ("epoch = %d mini-batch steps over patch i in batch i mod %d"
+                                           % (B, B))
+    return out
 
 
 def multichannel_run(iters=10):
@@ -357,6 +368,13 @@ def main():
     ap.add_argument("--no-tts", action="store_true", help="skip the paper's time-to-solution context run")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the multi-channel and targeted-selection runs")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only the serving leg (binary32 form): print its JSON and exit")
+    ap.add_argument("--saturate-frames", type=int, default=48,
+                    help="frames of the serving leg's saturation burst")
+    ap.add_argument("--timed-only", action="store_true",
+                    help="only the timed frames (for profiler runs): no roofline work count, "
+                         "precision-form, posterior-mean, quality or extra legs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES three times (the "
                          "reference kernel that scales the HBM byte counters) and exit")
@@ -384,6 +402,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": 4 * n, "copies": 3}), flush=True)
+        return
+    if args.serving_only:
+        print(json.dumps(serving_run(duration_s=args.serving_seconds,
+                                     saturate_frames=args.saturate_frames)), flush=True)
         return
     wl = synth.workload(args.workload)
     iters = args.iters or wl.iters
@@ -450,6 +472,12 @@ def main():
         "phase_ms_per_frame_dict_stats": st["ms_dict_stats"] / args.steps,
     }
     stats_ms = st["ms_dict_stats"] / max(st["n_sweeps"], 1)
+    if args.timed_only:
+        res["kernels"] = {"sweep_kernel": {"ms_per_launch": sweep_ms},
+                          "dict_stats_kernel": {"ms_per_launch": stats_ms}}
+        prob.close()
+        print(json.dumps(res), flush=True)
+        return
     terms = frame_stats_terms(prob, y_d, m_d, iters)
     lds_achieved = terms / (stats_ms * 1e-3)
     kernels = {
@@ -516,9 +544,11 @@ def main():
     if not args.no_serving:
         # both reconstruction forms under the same arrival sequence; the
         # faster binary32 form is the server's default and the headline p99
-        sv = serving_run(duration_s=args.serving_seconds, precision="fp32")
+        sv = serving_run(duration_s=args.serving_seconds, precision="fp32",
+                         saturate_frames=args.saturate_frames)
         res["serving"] = sv
-        res["serving_bf16"] = serving_run(duration_s=args.serving_seconds, precision="bf16")
+        res["serving_bf16"] = serving_run(duration_s=args.serving_seconds, precision="bf16",
+                                          saturate_frames=args.saturate_frames)
         res["p99_frame_latency_ms_512"] = sv.get("p99_ms_512")
         res["serving_isolated_latency"] = isolated_latency()
     if not args.no_tts:

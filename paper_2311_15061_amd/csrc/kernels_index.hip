@@ -378,8 +378,8 @@ __global__ void init_dict_kernel(Geom g, float* __restrict__ D, uint32_t key0, u
 // gives a patch with |Obs| in class c = [lo_c, hi_c] lanes_c lanes, and cuts
 // each (batch, class) run of slots into wavefronts of 64 / lanes_c slots
 // (the last one shorter).  A wavefront's register count J covers its last,
-// largest slot: J = max(4, |Obs| rounded up to even) for one lane per patch,
-// 12 or 16 for two lanes, 16 otherwise.
+// largest slot: J = max(4, |Obs| rounded up to even) for one lane per patch;
+// for a group of L lanes 12 or 16 (L J >= |Obs|), and 10 too for 4 lanes.
 
 __device__ __constant__ int kClassLo[kLaneClasses] = {0, 17, 33, 65, 129};
 __device__ __constant__ int kClassHi[kLaneClasses] = {16, 32, 64, 128, 256};
@@ -485,9 +485,11 @@ __global__ __launch_bounds__(256) void plan_waves_kernel(int E, const FramePlan*
   const int slot = plan->cls_s0[lo] + (w - plan->cls_w0[lo]) * per;
   const int ns = min(per, plan->cls_s1[lo] - slot);
   const int clast = count[perm[slot + ns - 1]];
+  // rows per lane: the smallest compiled body that holds the wave's largest patch
   int J = 16;
   if (lanes == 1) J = max(4, (clast + 1) & ~1);
-  else if (lanes == 2 && clast <= 24) J = 12;
+  else if (lanes == 4 && clast <= 40) J = 10;
+  else if (clast <= 12 * lanes) J = 12;
   waves[w] = make_int4(slot, ns, lanes, J);
 }
 

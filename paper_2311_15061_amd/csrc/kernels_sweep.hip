@@ -341,9 +341,19 @@ __device__ __forceinline__ void sweep_group(const SweepArgs& a, const int4* __re
       if (J <= 12) BPFA_BODY(12, 2);
       else BPFA_BODY(16, 2);
       break;
-    case 4: BPFA_BODY(16, 4); break;
-    case 8: BPFA_BODY(16, 8); break;
-    default: BPFA_BODY(16, 16); break;
+    case 4:
+      if (J <= 10) BPFA_BODY(10, 4);
+      else if (J <= 12) BPFA_BODY(12, 4);
+      else BPFA_BODY(16, 4);
+      break;
+    case 8:
+      if (J <= 12) BPFA_BODY(12, 8);
+      else BPFA_BODY(16, 8);
+      break;
+    default:
+      if (J <= 12) BPFA_BODY(12, 16);
+      else BPFA_BODY(16, 16);
+      break;
   }
 #undef BPFA_BODY
 }
