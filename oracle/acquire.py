@@ -12,7 +12,7 @@ probability p computed in binary64.
 
 * uniform:  every pixel q independently with p = rho (counter (q, 0, f)).
 * line hop: each line along the last axis is visited from a random start by
-  random hops: with hmax = max(1, round(2 / rho) - 1), the first acquired
+  random hops: with hmax = max(1, floor(2 / rho + 1/2) - 1), the first acquired
   pixel of line r is floor(u_0 hmax) and hop j >= 1 moves floor(u_j hmax) + 1
   pixels on (u_j from counter (r, j, f)); the mean hop is (hmax + 1) / 2,
   about 1 / rho.
@@ -43,7 +43,7 @@ def line_hop_mask(shape, rho, seed, stream, frame):
     shape = tuple(int(s) for s in shape)
     L = shape[-1]
     lines = int(np.prod(shape[:-1])) if len(shape) > 1 else 1
-    hmax = max(1, int(round(2.0 / rho)) - 1)
+    hmax = max(1, int(np.floor(2.0 / rho + 0.5)) - 1)
     m = np.zeros((lines, L), np.uint8)
     for r in range(lines):
         pos = int(np.floor(_uniforms(seed, stream, [r], [0], frame)[0] * hmax))
