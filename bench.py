@@ -353,6 +353,25 @@ def targeted_run(burn_in=10, samples=5, more=10):
     return out
 
 
+def recon_forms(prob, wl, torch, np):
+    """The reconstruction's contraction in both precision forms on the handle's
+    current state: ms per reconstruction (10 timed after one untimed) and the
+    outputs."""
+    rec_ms, outs = {}, {}
+    for prec in ("fp32", "bf16"):
+        prob.set_precision(prec)
+        o = torch.empty(wl.shape, dtype=torch.float32, device="cuda")
+        prob.reconstruct(o)
+        prob.set_timing(True)
+        for _ in range(10):
+            prob.reconstruct(o)
+        rec_ms[prec] = prob.stats()["ms_recon"] / 10
+        prob.set_timing(False)
+        outs[prec] = o.cpu().numpy().astype(np.float64)
+    prob.set_precision("fp32")
+    return rec_ms, outs
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -373,8 +392,9 @@ def main():
     ap.add_argument("--saturate-frames", type=int, default=48,
                     help="frames of the serving leg's saturation burst")
     ap.add_argument("--timed-only", action="store_true",
-                    help="only the timed frames (for profiler runs): no roofline work count, "
-                         "precision-form, posterior-mean, quality or extra legs")
+                    help="only the timed frames and the reconstruction in both precision forms "
+                         "(for profiler runs): no roofline work count, posterior-mean, quality or "
+                         "extra legs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES three times (the "
                          "reference kernel that scales the HBM byte counters) and exit")
@@ -475,6 +495,7 @@ def main():
     if args.timed_only:
         res["kernels"] = {"sweep_kernel": {"ms_per_launch": sweep_ms},
                           "dict_stats_kernel": {"ms_per_launch": stats_ms}}
+        res["reconstruct_ms"], _ = recon_forms(prob, wl, torch, np)
         prob.close()
         print(json.dumps(res), flush=True)
         return
@@ -498,21 +519,7 @@ def main():
     dominant = max(kernels, key=lambda k: kernels[k]["ms_per_frame"])
     res["roofline"] = dict(kernel=dominant, **kernels[dominant])
     res["kernels"] = kernels
-    # the reconstruction's contraction in both precision forms, on the final state
-    rec_ms = {}
-    outs = {}
-    for prec in ("fp32", "bf16"):
-        prob.set_precision(prec)
-        o = torch.empty(wl.shape, dtype=torch.float32, device="cuda")
-        prob.reconstruct(o)
-        prob.set_timing(True)
-        for _ in range(10):
-            prob.reconstruct(o)
-        rec_ms[prec] = prob.stats()["ms_recon"] / 10
-        prob.set_timing(False)
-        outs[prec] = o.cpu().numpy().astype(np.float64)
-    prob.set_precision("fp32")
-    res["reconstruct_ms"] = rec_ms
+    res["reconstruct_ms"], outs = recon_forms(prob, wl, torch, np)
     # posterior mean over the last half of a frame's iterations (after burn-in)
     prob.reset_state()
     prob.set_frame(y_d, m_d, reset_codes=True)

@@ -21,8 +21,9 @@
 //    kernel covers every |Obs|, so the long patches run beside the bulk in
 //    the same launch instead of trailing it;
 //  * the lanes of one patch form an aligned group; their partial dot
-//    products are summed by a butterfly, so every lane of the group holds
-//    the same sums (addition is commutative at every level), draws the same
+//    products are summed by a butterfly of DPP lane permutations (VALU
+//    operand modifiers, not LDS-crossbar shuffles), so every lane of the
+//    group holds the same sums (addition is commutative at every level), draws the same
 //    numbers from the patch's Philox counters and takes the same decisions;
 //    only the group's first lane writes the patch's outputs;
 //  * 8 wavefronts per block share one LDS copy of the dictionary tile; the
@@ -69,13 +70,27 @@ __device__ __forceinline__ void load_tile(const SweepArgs& a, float* lds, int k0
   for (int kk = threadIdx.x; kk < a.KS; kk += kSweepBlock) lds[a.P * a.KS + kk] = 0.f;
 }
 
-// sum over the LPP lanes of an aligned group, the same value in every lane
+// value of the partner lane under a data-parallel-primitive permutation (a
+// VALU operand modifier: no trip through the LDS crossbar)
+template <int CTRL>
+__device__ __forceinline__ float dpp_partner(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+constexpr int kDppQuadXor1 = 0xB1;     // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadXor2 = 0x4E;     // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7 - i within 8 lanes
+constexpr int kDppMirror = 0x140;      // lane i <-> 15 - i within 16 lanes
+
+// sum over the LPP lanes of an aligned group, the same value in every lane: a
+// butterfly in which each stage pairs every lane with one of the other half
+// of its group (after the previous stages all lanes of a half hold the same
+// sum), and a + b = b + a, so the group's lanes agree bit for bit
 template <int LPP>
 __device__ __forceinline__ float group_sum(float v) {
-  if constexpr (LPP >= 2) v += __shfl_xor(v, 1);
-  if constexpr (LPP >= 4) v += __shfl_xor(v, 2);
-  if constexpr (LPP >= 8) v += __shfl_xor(v, 4);
-  if constexpr (LPP >= 16) v += __shfl_xor(v, 8);
+  if constexpr (LPP >= 2) v += dpp_partner<kDppQuadXor1>(v);
+  if constexpr (LPP >= 4) v += dpp_partner<kDppQuadXor2>(v);
+  if constexpr (LPP >= 8) v += dpp_partner<kDppHalfMirror>(v);
+  if constexpr (LPP >= 16) v += dpp_partner<kDppMirror>(v);
   return v;
 }
 
