@@ -121,7 +121,8 @@ DictPlan make_dict_plan(const Geom& g) {
   // instead of once per group
   const long long whole = (long long)K * (K + 1) / 2 + K;
   const long long room1 =
-      ((long long)kLdsBytes - (long long)(K + 1) * 4 - (long long)kWave * 8 - (long long)kDictBlock * 10) / 8;
+      ((long long)kLdsBytes - (long long)(K + 1) * 4 - (long long)dict_sink_entries(K) * 8 -
+       (long long)kDictBlock * 10) / 8;
   const long long budget = whole <= room1 ? whole : kDictLdsEntries;
   int rg = 0;
   pl.row0[0] = 0;
@@ -147,7 +148,7 @@ DictPlan make_dict_plan(const Geom& g) {
   long long rec_max = 0;
   for (int r = 0; r < pl.RG; ++r)
     rec_max = std::max(rec_max, (pl.ent0[r + 1] - pl.ent0[r]) + (long long)(pl.row0[r + 1] - pl.row0[r]));
-  const long long room = (long long)kLdsBytes - (rec_max + kWave) * 8 - (long long)(K + 1) * 4;
+  const long long room = (long long)kLdsBytes - (rec_max + dict_sink_entries(K)) * 8 - (long long)(K + 1) * 4;
   pl.chunk_visits = (int)std::max<long long>(
       kDictBlock, std::min<long long>(kDictBlock * kDictVpt, room / 10 / kDictBlock * kDictBlock));
   // chunk slots per (p, row group): the frame plan uses the first few of them,

@@ -157,8 +157,13 @@ struct DictPlan {
 };
 
 // bytes of LDS of the statistics kernel
+// statistics LDS: accumulators | sink region | K + 1 bins | chunk visit records.
+// The sink region holds one slot per lane and K spare slots: a term that
+// belongs to no accumulator of the block adds into (lane slot + column).
+__host__ __device__ inline int dict_sink_entries(int K) { return kWave + K; }
 inline size_t dict_stats_lds(int K, long long rec_stride, int chunk_visits) {
-  return (size_t)(rec_stride + kWave) * 8 + (size_t)(K + 1) * 4 + (size_t)chunk_visits * 10;
+  return (size_t)(rec_stride + dict_sink_entries(K)) * 8 + (size_t)(K + 1) * 4 +
+         (size_t)chunk_visits * 10;
 }
 
 // Sweep LDS: tile (P + 1) x KS floats | [wave][K] z counts (bytes) | per-wave

@@ -85,41 +85,130 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
-// Pair accumulation of one visit.  Branch-free: an entry that does not
-// contribute (past the patch's n_a, or outside the block's row group) adds an
-// exact zero to the lane's own sink entry, so no lane toggles the exec mask
-// and the scalar unit (one per CU) stays out of the inner loop.
+// Pair accumulation of one visit, in straight-line code.  Byte offsets into
+// the block's LDS: the group's triangle rows, its B entries, then the sink
+// region (one slot per lane followed by K spare slots).  A term whose row lies
+// outside the group (or past the patch's n_a) goes to sink + 8 column, inside
+// the sink region; a column past n_a is replaced by a column the row holds
+// (the lane's last staged atom, or the row's own diagonal) with a zero
+// weight.  Row offsets pass through an empty asm so that the compiler keeps
+// one select per row instead of turning the choice into exec-mask branches
+// around every term (branches put the CU's one scalar unit back in the loop).
 struct StatsRow {
-  long long* acc;
-  long long* sink;
-  int r0, r1;
-  long long e0;
-  int E, K;
+  char* lds;
+  unsigned sink;          // this lane's sink slot
+  int r0, r1, e0, tw, E;  // group rows, its first triangle entry, 2K - 1, its entry count
   double sc, ysb;
-  // accumulator offset of row k: entry (k, j), j >= k, is at row_off(k) + j
-  __device__ __forceinline__ int row_off(int k) const { return (int)(tri_off(k, K) - e0) - k; }
+  __device__ __forceinline__ bool in(int k) const { return k >= r0 && k < r1; }
+  // entry (k, j) of row k, j >= k, sits at row_byte(k) + 8 j:
+  // tri_off(k, K) - k = k (2K - 1 - k) / 2 (an integer)
+  __device__ __forceinline__ unsigned row_byte(int k) const {
+    return 8u * (unsigned)((int)(__umul24((unsigned)k, (unsigned)(tw - k)) >> 1) - e0);
+  }
+  __device__ __forceinline__ unsigned b_byte(int k) const { return 8u * (unsigned)(E + k - r0); }
+  __device__ __forceinline__ unsigned row_or_sink(bool in_group, int k) const {
+    unsigned o = in_group ? row_byte(k) : sink;
+    asm volatile("" : "+v"(o));
+    return o;
+  }
+  __device__ __forceinline__ unsigned b_or_sink(bool in_group, int k) const {
+    unsigned o = in_group ? b_byte(k) : sink;
+    asm volatile("" : "+v"(o));
+    return o;
+  }
+  __device__ __forceinline__ void add(unsigned off, double x) const {
+    atomicAdd(reinterpret_cast<unsigned long long*>(lds + off), to_fixed(x));
+  }
 };
+
+// A register stage of up to kStatsCap list entries: atoms (-1 past the
+// patch's n_a), weights (0 there) and column offsets (8 x atom; past n_a the
+// last valid atom's, a column every staged row holds since lists ascend).
+struct Stage {
+  int kk[kStatsCap];
+  unsigned col[kStatsCap];
+  double ww[kStatsCap];
+};
+
+__device__ __forceinline__ void stage_from(Stage& s, const int2 (&raw)[kStatsCap], int nv) {
+  unsigned last = 0;
+#pragma unroll
+  for (int a = 0; a < kStatsCap; ++a) {
+    const bool in = a < nv;
+    s.kk[a] = in ? raw[a].x : -1;
+    s.ww[a] = in ? (double)__int_as_float(raw[a].y) : 0.0;
+    last = in ? 8u * (unsigned)raw[a].x : last;
+    s.col[a] = last;
+  }
+}
 
 // SKIP: with three or more row groups a row no lane of the wave holds in
 // this block's group (it adds only to the sinks) is skipped whole by a
 // uniform branch; with fewer groups the test costs more than it saves
 template <int NB, bool SKIP>
-__device__ __forceinline__ void stats_pairs(const StatsRow& sr, const int (&kk)[kStatsCap],
-                                            const double (&ww)[kStatsCap]) {
+__device__ __forceinline__ void stats_pairs(const StatsRow& sr, const Stage& s) {
 #pragma unroll
   for (int a = 0; a < NB; ++a) {
-    const bool ina = kk[a] >= sr.r0 && kk[a] < sr.r1;   // kk = -1 past n_a
+    const bool ina = sr.in(s.kk[a]);   // kk = -1 past n_a
     if (SKIP && __builtin_amdgcn_ballot_w64(ina) == 0) continue;
-    const double wa = ina ? ww[a] : 0.0;
-    atomicAdd((unsigned long long*)(ina ? sr.acc + sr.E + (kk[a] - sr.r0) : sr.sink),
-              to_fixed(wa * sr.ysb));
-    const double was = wa * sr.sc;
-    const int row = sr.row_off(ina ? kk[a] : 0);
+    sr.add(sr.b_or_sink(ina, s.kk[a]), s.ww[a] * sr.ysb);
+    const unsigned rb = sr.row_or_sink(ina, s.kk[a]);
+    const double was = s.ww[a] * sr.sc;
 #pragma unroll
-    for (int b = a; b < NB; ++b) {
-      long long* pc = (ina && kk[b] >= 0) ? sr.acc + (row + kk[b]) : sr.sink;
-      atomicAdd((unsigned long long*)pc, to_fixed(was * ww[b]));
-    }
+    for (int b = a; b < NB; ++b) sr.add(rb + s.col[b], was * s.ww[b]);
+  }
+}
+
+template <bool SKIP>
+__device__ __forceinline__ void stats_stage(const StatsRow& sr, const Stage& s, int bound) {
+  switch ((min(bound, kStatsCap) + 1) >> 1) {
+    case 1: stats_pairs<2, SKIP>(sr, s); break;
+    case 2: stats_pairs<4, SKIP>(sr, s); break;
+    case 3: stats_pairs<6, SKIP>(sr, s); break;
+    case 4: stats_pairs<8, SKIP>(sr, s); break;
+    case 5: stats_pairs<10, SKIP>(sr, s); break;
+    case 6: stats_pairs<12, SKIP>(sr, s); break;
+    case 7: stats_pairs<14, SKIP>(sr, s); break;
+    case 8: stats_pairs<16, SKIP>(sr, s); break;
+    default: break;
+  }
+}
+
+// pairs of the staged rows with list entry b read from memory (b past the
+// stage; a lane whose list ends before b adds zeros at its last staged column)
+__device__ __forceinline__ void stats_stage_with(const StatsRow& sr, const Stage& s,
+                                                 const unsigned (&rb)[kStatsCap],
+                                                 const double (&wsc)[kStatsCap], bool inb, int2 eb) {
+  const double wb = inb ? (double)__int_as_float(eb.y) : 0.0;
+  const unsigned cb = inb ? 8u * (unsigned)eb.x : s.col[kStatsCap - 1];
+#pragma unroll
+  for (int a = 0; a < kStatsCap; ++a) sr.add(rb[a] + cb, wsc[a] * wb);
+}
+
+__device__ __forceinline__ void stage_rows(const StatsRow& sr, const Stage& s,
+                                           unsigned (&rb)[kStatsCap], double (&wsc)[kStatsCap]) {
+#pragma unroll
+  for (int a = 0; a < kStatsCap; ++a) {
+    rb[a] = sr.row_or_sink(sr.in(s.kk[a]), s.kk[a]);
+    wsc[a] = s.ww[a] * sr.sc;
+  }
+}
+
+// entries b = from .. wmax - 1 read from memory: each one's B entry and its
+// pairs (a, b) with the entries a = from .. b, also read from memory (the
+// rare tails past the register stages); L is the patch's list row
+__device__ __forceinline__ void stats_tail(const StatsRow& sr, const int2* L, int na, int K,
+                                           int from, int b, bool inb, int2 eb) {
+  const double wb = inb ? (double)__int_as_float(eb.y) : 0.0;
+  sr.add(sr.b_or_sink(inb && sr.in(eb.x), eb.x), wb * sr.ysb);
+  for (int a = from; a <= b; ++a) {
+    int2 ea = make_int2(-1, 0);
+    if (a < na) ea = L[a];
+    const bool ina = a < na && sr.in(ea.x);
+    const unsigned rb = sr.row_or_sink(ina, ea.x);
+    // a column past n_a: the row's own diagonal, with a zero weight
+    const unsigned cb = inb ? 8u * (unsigned)eb.x : 8u * (unsigned)max(ea.x, 0);
+    sr.add(rb + cb, (double)__int_as_float(ea.y) * sr.sc * wb);
   }
 }
 
@@ -190,7 +279,7 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
   const int E = (int)(pl.ent0[rg + 1] - e0);
   const int rec = E + (r1 - r0);
   const int K = g.K;
-  int* bins = reinterpret_cast<int*>(acc + pl.rec_stride + kWave); // K + 1 counts, then starts
+  int* bins = reinterpret_cast<int*>(acc + pl.rec_stride + dict_sink_entries(K)); // K + 1 counts, then starts
   int* v_pat = bins + (K + 1);
   float* v_y = reinterpret_cast<float*>(v_pat + pl.chunk_visits);
   uint16_t* v_na = reinterpret_cast<uint16_t*>(v_y + pl.chunk_visits);
@@ -198,6 +287,7 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
   for (int e = tid; e < rec; e += kDictBlock) acc[e] = 0;
 
   const double sc = scal->scale_c, sb = scal->scale_b;
+  const unsigned sink = (unsigned)((pl.rec_stride + lane) * 8);   // this lane's sink slot
   const int32_t* vs = vpatch + (size_t)p * g.Mtot;
   double x2 = 0.0;
 
@@ -295,116 +385,55 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
     clear(q[kStatsAhead]);
     if (vb + kStatsAhead * kDictBlock < nvis) fetch(vb + kStatsAhead * kDictBlock, q[kStatsAhead]);
     const int pid = q[0].pid, na = q[0].na, wmax = q[0].wmax;
-    const double y = q[0].y;
-    const int2 (&raw)[kStatsCap] = q[0].raw;
     const int2* L = list + (size_t)pid * K;
-    int kk[kStatsCap];
-    double ww[kStatsCap];
-#pragma unroll
-    for (int a = 0; a < kStatsCap; ++a) {
-      const bool in = a < na;
-      kk[a] = in ? raw[a].x : -1;
-      ww[a] = in ? (double)__int_as_float(raw[a].y) : 0.0;
-    }
-    const double ysb = y * sb;
-    long long* const sink = acc + pl.rec_stride + lane;
-    const StatsRow sr{acc, sink, r0, r1, e0, E, K, sc, ysb};
-    switch ((min(wmax, kStatsCap) + 1) >> 1) {
-      case 1: stats_pairs<2, SKIP>(sr, kk, ww); break;
-      case 2: stats_pairs<4, SKIP>(sr, kk, ww); break;
-      case 3: stats_pairs<6, SKIP>(sr, kk, ww); break;
-      case 4: stats_pairs<8, SKIP>(sr, kk, ww); break;
-      case 5: stats_pairs<10, SKIP>(sr, kk, ww); break;
-      case 6: stats_pairs<12, SKIP>(sr, kk, ww); break;
-      case 7: stats_pairs<14, SKIP>(sr, kk, ww); break;
-      case 8: stats_pairs<16, SKIP>(sr, kk, ww); break;
-      default: break;
-    }
-    if (wmax > kStatsCap + kStatsCap / 2) {
-      // lists longer than the register stage.  (1) every later entry b, one
-      // at a time, with the first-stage entries a < kStatsCap
-      for (int b = kStatsCap; b < wmax; ++b) {
-        int2 eb = make_int2(-1, 0);
-        if (b < na) eb = L[b];
-        const bool inb = b < na;
-        const double wb = inb ? (double)__int_as_float(eb.y) : 0.0;
-#pragma unroll
-        for (int a = 0; a < kStatsCap; ++a) {
-          const bool ok = inb && kk[a] >= r0 && kk[a] < r1;
-          long long* pc = ok ? acc + (sr.row_off(kk[a]) + eb.x) : sink;
-          atomicAdd((unsigned long long*)pc, to_fixed(ok ? ww[a] * sc * wb : 0.0));
+    const StatsRow sr{reinterpret_cast<char*>(acc), sink, r0, r1, (int)e0, 2 * K - 1, E, sc,
+                      q[0].y * sb};
+    Stage s;
+    stage_from(s, q[0].raw, min(na, kStatsCap));
+    stats_stage<SKIP>(sr, s, wmax);
+    if (wmax > kStatsCap) {
+      unsigned rb[kStatsCap];
+      double wsc[kStatsCap];
+      stage_rows(sr, s, rb, wsc);
+      if (wmax > kStatsCap + kStatsCap / 2) {
+        // lists longer than the register stage.  (1) every later entry b, one
+        // at a time, with the staged entries
+        for (int b = kStatsCap; b < wmax; ++b) {
+          int2 eb = make_int2(-1, 0);
+          if (b < na) eb = L[b];
+          stats_stage_with(sr, s, rb, wsc, b < na, eb);
         }
-      }
-      // (2) entries kStatsCap .. 2 kStatsCap - 1 replace the first stage in
-      // registers (loaded together; the bound is the wave's): their B
-      // entries and the pairs among them, by the same bodies
-      const int n2 = min(wmax, 2 * kStatsCap) - kStatsCap;
+        // (2) entries kStatsCap .. 2 kStatsCap - 1 replace the stage in
+        // registers (loaded together; the bound is the wave's): their B
+        // entries and the pairs among them, by the same bodies
+        const int n2 = min(wmax, 2 * kStatsCap) - kStatsCap;
+        int2 raw2[kStatsCap];
 #pragma unroll
-      for (int u = 0; u < kStatsCap; ++u) {
-        int2 e = make_int2(-1, 0);
-        if (u < n2) e = L[min(kStatsCap + u, K - 1)];
-        const bool in = kStatsCap + u < na;
-        kk[u] = in ? e.x : -1;
-        ww[u] = in ? (double)__int_as_float(e.y) : 0.0;
-      }
-      switch ((n2 + 1) >> 1) {
-        case 1: stats_pairs<2, SKIP>(sr, kk, ww); break;
-        case 2: stats_pairs<4, SKIP>(sr, kk, ww); break;
-        case 3: stats_pairs<6, SKIP>(sr, kk, ww); break;
-        case 4: stats_pairs<8, SKIP>(sr, kk, ww); break;
-        case 5: stats_pairs<10, SKIP>(sr, kk, ww); break;
-        case 6: stats_pairs<12, SKIP>(sr, kk, ww); break;
-        case 7: stats_pairs<14, SKIP>(sr, kk, ww); break;
-        default: stats_pairs<16, SKIP>(sr, kk, ww); break;
-      }
-      // (3) entries past both stages (rare): B entries, pairs with the second
-      // stage, and pairs among themselves from memory
-      for (int b = 2 * kStatsCap; b < wmax; ++b) {
-        int2 eb = make_int2(-1, 0);
-        if (b < na) eb = L[b];
-        const bool inb = b < na;
-        const double wb = inb ? (double)__int_as_float(eb.y) : 0.0;
-        const bool inbr = inb && eb.x >= r0 && eb.x < r1;
-        atomicAdd((unsigned long long*)(inbr ? acc + E + (eb.x - r0) : sink),
-                  to_fixed((inbr ? wb : 0.0) * ysb));
-#pragma unroll
-        for (int a = 0; a < kStatsCap; ++a) {
-          const bool ok = inb && kk[a] >= r0 && kk[a] < r1;
-          long long* pc = ok ? acc + (sr.row_off(kk[a]) + eb.x) : sink;
-          atomicAdd((unsigned long long*)pc, to_fixed(ok ? ww[a] * sc * wb : 0.0));
+        for (int u = 0; u < kStatsCap; ++u) {
+          raw2[u] = make_int2(-1, 0);
+          if (u < n2) raw2[u] = L[min(kStatsCap + u, K - 1)];
         }
-        for (int a = 2 * kStatsCap; a <= b; ++a) {
-          int2 ea = make_int2(-1, 0);
-          if (a < na) ea = L[a];
-          const bool ok = inb && a < na && ea.x >= r0 && ea.x < r1;
-          long long* pc = ok ? acc + (sr.row_off(ea.x) + eb.x) : sink;
-          atomicAdd((unsigned long long*)pc,
-                    to_fixed(ok ? (double)__int_as_float(ea.y) * sc * wb : 0.0));
+        stage_from(s, raw2, min(max(na - kStatsCap, 0), kStatsCap));
+        stats_stage<SKIP>(sr, s, n2);
+        // (3) entries past both stages (rare): pairs with the second stage,
+        // then B entries and pairs among themselves from memory
+        if (wmax > 2 * kStatsCap) {
+          stage_rows(sr, s, rb, wsc);
+          for (int b = 2 * kStatsCap; b < wmax; ++b) {
+            int2 eb = make_int2(-1, 0);
+            if (b < na) eb = L[b];
+            stats_stage_with(sr, s, rb, wsc, b < na, eb);
+            stats_tail(sr, L, na, K, 2 * kStatsCap, b, b < na, eb);
+          }
         }
-      }
-    } else {
-      // entries beyond the register stage (rare): pairs (a, b), a <= b, b >= kStatsCap
-      for (int b = kStatsCap; b < wmax; ++b) {
-        int2 eb = make_int2(-1, 0);
-        if (b < na) eb = L[b];
-        const bool inb = b < na;
-        const double wb = inb ? (double)__int_as_float(eb.y) : 0.0;
-        const bool inbr = inb && eb.x >= r0 && eb.x < r1;
-        atomicAdd((unsigned long long*)(inbr ? acc + E + (eb.x - r0) : sink),
-                  to_fixed((inbr ? wb : 0.0) * ysb));
-  #pragma unroll
-        for (int a = 0; a < kStatsCap; ++a) {
-          const bool ok = inb && kk[a] >= r0 && kk[a] < r1;
-          long long* pc = ok ? acc + (sr.row_off(kk[a]) + eb.x) : sink;
-          atomicAdd((unsigned long long*)pc, to_fixed(ok ? ww[a] * sc * wb : 0.0));
-        }
-        for (int a = kStatsCap; a <= b; ++a) {
-          int2 ea = make_int2(-1, 0);
-          if (a < na) ea = L[a];
-          const bool ok = inb && a < na && ea.x >= r0 && ea.x < r1;
-          long long* pc = ok ? acc + (sr.row_off(ea.x) + eb.x) : sink;
-          atomicAdd((unsigned long long*)pc,
-                    to_fixed(ok ? (double)__int_as_float(ea.y) * sc * wb : 0.0));
+      } else {
+        // entries beyond the register stage (rare): pairs with the stage,
+        // B entries and pairs among themselves from memory
+        for (int b = kStatsCap; b < wmax; ++b) {
+          int2 eb = make_int2(-1, 0);
+          if (b < na) eb = L[b];
+          stats_stage_with(sr, s, rb, wsc, b < na, eb);
+          stats_tail(sr, L, na, K, kStatsCap, b, b < na, eb);
         }
       }
     }
