@@ -392,48 +392,39 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
     stage_from(s, q[0].raw, min(na, kStatsCap));
     stats_stage<SKIP>(sr, s, wmax);
     if (wmax > kStatsCap) {
+      // lists longer than the register stage (the wave's bound past
+      // kStatsCap).  (1) every later entry, one at a time with the next in
+      // flight, paired with the staged entries; (2) entries kStatsCap ..
+      // 2 kStatsCap - 1, loaded together, replace the stage in registers:
+      // their B entries and the pairs among them, by the same bodies (holding
+      // them in registers through (1) as well would spill); (3) entries past
+      // both stages (rare): pairs with the second stage, then B entries and
+      // pairs among themselves from memory
       unsigned rb[kStatsCap];
       double wsc[kStatsCap];
       stage_rows(sr, s, rb, wsc);
-      if (wmax > kStatsCap + kStatsCap / 2) {
-        // lists longer than the register stage.  (1) every later entry b, one
-        // at a time, with the staged entries
-        for (int b = kStatsCap; b < wmax; ++b) {
-          int2 eb = make_int2(-1, 0);
-          if (b < na) eb = L[b];
-          stats_stage_with(sr, s, rb, wsc, b < na, eb);
-        }
-        // (2) entries kStatsCap .. 2 kStatsCap - 1 replace the stage in
-        // registers (loaded together; the bound is the wave's): their B
-        // entries and the pairs among them, by the same bodies
-        const int n2 = min(wmax, 2 * kStatsCap) - kStatsCap;
-        int2 raw2[kStatsCap];
+      const int n2 = min(wmax, 2 * kStatsCap) - kStatsCap;
+      int2 eb = L[kStatsCap];
+      for (int b = kStatsCap; b < wmax; ++b) {
+        const int2 cur = eb;
+        if (b + 1 < wmax) eb = L[min(b + 1, K - 1)];
+        stats_stage_with(sr, s, rb, wsc, b < na, cur);
+      }
+      int2 raw2[kStatsCap];
 #pragma unroll
-        for (int u = 0; u < kStatsCap; ++u) {
-          raw2[u] = make_int2(-1, 0);
-          if (u < n2) raw2[u] = L[min(kStatsCap + u, K - 1)];
-        }
-        stage_from(s, raw2, min(max(na - kStatsCap, 0), kStatsCap));
-        stats_stage<SKIP>(sr, s, n2);
-        // (3) entries past both stages (rare): pairs with the second stage,
-        // then B entries and pairs among themselves from memory
-        if (wmax > 2 * kStatsCap) {
-          stage_rows(sr, s, rb, wsc);
-          for (int b = 2 * kStatsCap; b < wmax; ++b) {
-            int2 eb = make_int2(-1, 0);
-            if (b < na) eb = L[b];
-            stats_stage_with(sr, s, rb, wsc, b < na, eb);
-            stats_tail(sr, L, na, K, 2 * kStatsCap, b, b < na, eb);
-          }
-        }
-      } else {
-        // entries beyond the register stage (rare): pairs with the stage,
-        // B entries and pairs among themselves from memory
-        for (int b = kStatsCap; b < wmax; ++b) {
+      for (int u = 0; u < kStatsCap; ++u) {
+        raw2[u] = make_int2(-1, 0);
+        if (u < n2) raw2[u] = L[min(kStatsCap + u, K - 1)];
+      }
+      stage_from(s, raw2, min(max(na - kStatsCap, 0), kStatsCap));
+      stats_stage<SKIP>(sr, s, n2);
+      if (wmax > 2 * kStatsCap) {
+        stage_rows(sr, s, rb, wsc);
+        for (int b = 2 * kStatsCap; b < wmax; ++b) {
           int2 eb = make_int2(-1, 0);
           if (b < na) eb = L[b];
           stats_stage_with(sr, s, rb, wsc, b < na, eb);
-          stats_tail(sr, L, na, K, kStatsCap, b, b < na, eb);
+          stats_tail(sr, L, na, K, 2 * kStatsCap, b, b < na, eb);
         }
       }
     }
