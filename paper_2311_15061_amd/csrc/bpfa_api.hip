@@ -64,7 +64,7 @@ struct Layout {
   DictPlan plan;
   // byte offsets
   size_t image, mask, poff, pcoord, obs_bits, obs_count, perm, inv_perm, obs_idx, obs_val, sweep_waves, fplan, sort_hist, sort_bin,
-      omega, omega_c, omega_blk, vpatch, omega_y, D, list0, list1, nact0, nact1, Ck, ell, scal, nk, sw_cnt, sw_part, dpart,
+      omega, omega_c, omega_blk, vpatch, omega_y, D, list0, list1, nact0, nact1, Ck, ell, scal, nk, sw_cnt, sw_part, goff, dpart,
       dx2, Cfull, Bvec, diag, x2p, sumr2_p, Y, recon, mean, mean2, var, wsum, total;
 };
 
@@ -122,7 +122,7 @@ DictPlan make_dict_plan(const Geom& g) {
   const long long whole = (long long)K * (K + 1) / 2 + K;
   const long long room1 =
       ((long long)kLdsBytes - (long long)(K + 1) * 4 - (long long)dict_sink_entries(K) * 8 -
-       (long long)kDictBlock * 10) / 8;
+       (long long)kDictBlock * kDictVisitBytes) / 8;
   const long long budget = whole <= room1 ? whole : kDictLdsEntries;
   int rg = 0;
   pl.row0[0] = 0;
@@ -150,7 +150,7 @@ DictPlan make_dict_plan(const Geom& g) {
     rec_max = std::max(rec_max, (pl.ent0[r + 1] - pl.ent0[r]) + (long long)(pl.row0[r + 1] - pl.row0[r]));
   const long long room = (long long)kLdsBytes - (rec_max + dict_sink_entries(K)) * 8 - (long long)(K + 1) * 4;
   pl.chunk_visits = (int)std::max<long long>(
-      kDictBlock, std::min<long long>(kDictBlock * kDictVpt, room / 10 / kDictBlock * kDictBlock));
+      kDictBlock, std::min<long long>(kDictBlock * kDictVpt, room / kDictVisitBytes / kDictBlock * kDictBlock));
   // chunk slots per (p, row group): the frame plan uses the first few of them,
   // chosen on the device from the frame's observed pixels
   const long long mt = g.Mtot;
@@ -226,6 +226,7 @@ Layout make_layout(const Geom& g) {
   L.nk = take(8 * K);
   L.sw_cnt = take(4 * K);
   L.sw_part = take(sizeof(SweepPart) * (size_t)((L.wave_cap + kSweepWaves - 1) / kSweepWaves));
+  L.goff = take(2 * N * (size_t)(L.plan.RG - 1));
   L.dpart = take(8 * (size_t)P * L.plan.RG * L.plan.chunks * rec_stride);
   L.dx2 = take(8 * P * L.plan.chunks);
   L.Cfull = take(8 * P * K * K);
@@ -766,6 +767,7 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
   b.nk = (long long*)(w + L.nk);
   b.sw_cnt = (int32_t*)(w + L.sw_cnt);
   b.sw_part = (SweepPart*)(w + L.sw_part);
+  b.goff = (uint16_t*)(w + L.goff);
   b.dpart = (long long*)(w + L.dpart);
   b.dx2 = (double*)(w + L.dx2);
   b.Cfull = (double*)(w + L.Cfull);

@@ -133,6 +133,8 @@ struct Buffers {
   SweepPart* sw_part = nullptr;  // sweep blocks
   int32_t* vpatch = nullptr;     // [p][Mtot]: patch that shows observed pixel v at offset p, or -1
   float* omega_y = nullptr;      // Mtot: value of observed pixel v
+  uint16_t* goff = nullptr;      // N x (row groups - 1): list entries of patch i below each later
+                                 // statistics row group's first row
   long long* dpart = nullptr;    // dictionary statistics partials
   double* dx2 = nullptr;         // P x chunks: sum of y^2 over visits
   double* Cfull = nullptr;       // P x K x K
@@ -161,9 +163,12 @@ struct DictPlan {
 // The sink region holds one slot per lane and K spare slots: a term that
 // belongs to no accumulator of the block adds into (lane slot + column).
 __host__ __device__ inline int dict_sink_entries(int K) { return kWave + K; }
+// a chunk visit record: patch (int32), observed value (float), the list's
+// length from the block's row group on and its offset there (uint16 each)
+constexpr int kDictVisitBytes = 12;
 inline size_t dict_stats_lds(int K, long long rec_stride, int chunk_visits) {
   return (size_t)(rec_stride + dict_sink_entries(K)) * 8 + (size_t)(K + 1) * 4 +
-         (size_t)chunk_visits * 10;
+         (size_t)chunk_visits * kDictVisitBytes;
 }
 
 // Sweep LDS: tile (P + 1) x KS floats | [wave][K] z counts (bytes) | per-wave

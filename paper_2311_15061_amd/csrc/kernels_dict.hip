@@ -13,10 +13,11 @@
 //
 // dict_stats_kernel: one block per (p, row group of the K x K triangle,
 //   chunk of observed pixels).  The visits of the chunk (observed pixel q,
-//   the patch whose origin is q - b(p)) are first grouped by the patch's
-//   number of active atoms n_a in LDS, so a wavefront's lanes share a pair
-//   loop bound; then a lane stages a patch's active entries in registers and
-//   adds its outer product into LDS.  Sums are 64-bit fixed point: the
+//   the patch whose origin is q - b(p)) are first grouped by the length of
+//   the patch's active list from the block's row group on (a later group
+//   starts at the offset list_groups_kernel found) in LDS, so a wavefront's
+//   lanes share a pair loop bound; then a lane stages those entries in
+//   registers and adds their outer product into LDS.  Sums are 64-bit fixed point: the
 //   binary64 product of two binary32 weights is exact, it is scaled by a power
 //   of two and rounded to an integer by adding 1.5 * 2^52 (exact for
 //   |x| < 2^51); integer adds are associative, so the statistics do not
@@ -37,10 +38,11 @@ namespace bpfa {
 constexpr int kStatsCap = 16;   // active entries of a patch held in registers
 constexpr int kStatsAhead = 1;  // statistics iterations whose list rows are in flight
 
-// a visit of the statistics pass: patch, its n_a and observed value, the
-// wave's bound on n_a, and the first kStatsCap list entries
+// a visit of the statistics pass: patch, its list's length from the block's
+// row group on and the offset where that part starts, the observed value, the
+// wave's bound on the length, and the first kStatsCap entries of that part
 struct VisitRow {
-  int pid, na, wmax;
+  int pid, na, off, wmax;
   double y;
   int2 raw[kStatsCap];
 };
@@ -197,7 +199,7 @@ __device__ __forceinline__ void stage_rows(const StatsRow& sr, const Stage& s,
 // entries b = from .. wmax - 1 read from memory: each one's B entry and its
 // pairs (a, b) with the entries a = from .. b, also read from memory (the
 // rare tails past the register stages); L is the patch's list row
-__device__ __forceinline__ void stats_tail(const StatsRow& sr, const int2* L, int na, int K,
+__device__ __forceinline__ void stats_tail(const StatsRow& sr, const int2* L, int na,
                                            int from, int b, bool inb, int2 eb) {
   const double wb = inb ? (double)__int_as_float(eb.y) : 0.0;
   sr.add(sr.b_or_sink(inb && sr.in(eb.x), eb.x), wb * sr.ysb);
@@ -248,7 +250,8 @@ template <bool SKIP>
 __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
     Geom g, DictPlanDev pl, const FramePlan* __restrict__ fplan, const int32_t* __restrict__ vpatch,
     const float* __restrict__ omega_y, const int2* __restrict__ list,
-    const int32_t* __restrict__ nact, const DevScalars* __restrict__ scal,
+    const int32_t* __restrict__ nact, const uint16_t* __restrict__ goff,
+    const DevScalars* __restrict__ scal,
     long long* __restrict__ dpart, double* __restrict__ dx2, int n_batches, int batch) {
   extern __shared__ long long acc[];
   __shared__ double s_x2[kDictBlock / kWave];
@@ -283,6 +286,7 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
   int* v_pat = bins + (K + 1);
   float* v_y = reinterpret_cast<float*>(v_pat + pl.chunk_visits);
   uint16_t* v_na = reinterpret_cast<uint16_t*>(v_y + pl.chunk_visits);
+  uint16_t* v_off = v_na + pl.chunk_visits;
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
   for (int e = tid; e < rec; e += kDictBlock) acc[e] = 0;
 
@@ -298,7 +302,7 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
   __syncthreads();
 
   // pass 1: this thread's visits (at most kDictVpt) in registers; rank within its n_a bin
-  int r_pat[kDictVpt], r_na[kDictVpt], r_rank[kDictVpt];
+  int r_pat[kDictVpt], r_na[kDictVpt], r_off[kDictVpt], r_rank[kDictVpt];
   float r_y[kDictVpt];
 #pragma unroll
   for (int u = 0; u < kDictVpt; ++u) {
@@ -313,7 +317,12 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
     }
   }
 #pragma unroll
-  for (int u = 0; u < kDictVpt; ++u) r_na[u] = r_pat[u] >= 0 ? nact[r_pat[u]] : 0;
+  for (int u = 0; u < kDictVpt; ++u) {
+    // a later row group skips the list's entries below its first row (lists
+    // ascend, and a pair (j, k), j <= k, belongs to row j's group)
+    r_off[u] = rg > 0 && r_pat[u] >= 0 ? goff[(size_t)r_pat[u] * (pl.RG - 1) + (rg - 1)] : 0;
+    r_na[u] = r_pat[u] >= 0 ? nact[r_pat[u]] - r_off[u] : 0;
+  }
 #pragma unroll
   for (int u = 0; u < kDictVpt; ++u) {
     r_rank[u] = 0;
@@ -347,6 +356,7 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
       v_pat[pos] = r_pat[u];
       v_y[pos] = r_y[u];
       v_na[pos] = (uint16_t)r_na[u];
+      v_off[pos] = (uint16_t)r_off[u];
     }
   __syncthreads();
   const int nvis = s_total;
@@ -358,19 +368,20 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
     const bool on = vi < nvis;
     f.pid = on ? v_pat[vi] : 0;
     f.na = on ? (int)v_na[vi] : 0;
+    f.off = on ? (int)v_off[vi] : 0;
     f.y = on ? (double)v_y[vi] : 0.0;
     f.wmax = __builtin_amdgcn_readfirstlane(wave_max_i(f.na));
-    const int2* L = list + (size_t)f.pid * K;
+    const int2* L = list + (size_t)f.pid * K + f.off;
     // the first entries up to the wave's bound, loads issued together (a
     // clamped index stays inside the patch's list row)
 #pragma unroll
     for (int a = 0; a < kStatsCap; ++a) {
       f.raw[a] = make_int2(-1, 0);
-      if (a < f.wmax) f.raw[a] = L[min(a, K - 1)];
+      if (a < f.wmax) f.raw[a] = L[min(a, K - 1 - f.off)];
     }
   };
   auto clear = [&](VisitRow& f) {
-    f.pid = f.na = f.wmax = 0;
+    f.pid = f.na = f.off = f.wmax = 0;
     f.y = 0.0;
 #pragma unroll
     for (int a = 0; a < kStatsCap; ++a) f.raw[a] = make_int2(-1, 0);
@@ -385,7 +396,8 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
     clear(q[kStatsAhead]);
     if (vb + kStatsAhead * kDictBlock < nvis) fetch(vb + kStatsAhead * kDictBlock, q[kStatsAhead]);
     const int pid = q[0].pid, na = q[0].na, wmax = q[0].wmax;
-    const int2* L = list + (size_t)pid * K;
+    const int2* L = list + (size_t)pid * K + q[0].off;
+    const int lim = K - 1 - q[0].off;   // last index inside the patch's list row
     const StatsRow sr{reinterpret_cast<char*>(acc), sink, r0, r1, (int)e0, 2 * K - 1, E, sc,
                       q[0].y * sb};
     Stage s;
@@ -404,17 +416,17 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
       double wsc[kStatsCap];
       stage_rows(sr, s, rb, wsc);
       const int n2 = min(wmax, 2 * kStatsCap) - kStatsCap;
-      int2 eb = L[kStatsCap];
+      int2 eb = L[min(kStatsCap, lim)];
       for (int b = kStatsCap; b < wmax; ++b) {
         const int2 cur = eb;
-        if (b + 1 < wmax) eb = L[min(b + 1, K - 1)];
+        if (b + 1 < wmax) eb = L[min(b + 1, lim)];
         stats_stage_with(sr, s, rb, wsc, b < na, cur);
       }
       int2 raw2[kStatsCap];
 #pragma unroll
       for (int u = 0; u < kStatsCap; ++u) {
         raw2[u] = make_int2(-1, 0);
-        if (u < n2) raw2[u] = L[min(kStatsCap + u, K - 1)];
+        if (u < n2) raw2[u] = L[min(kStatsCap + u, lim)];
       }
       stage_from(s, raw2, min(max(na - kStatsCap, 0), kStatsCap));
       stats_stage<SKIP>(sr, s, n2);
@@ -424,7 +436,7 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
           int2 eb = make_int2(-1, 0);
           if (b < na) eb = L[b];
           stats_stage_with(sr, s, rb, wsc, b < na, eb);
-          stats_tail(sr, L, na, K, 2 * kStatsCap, b, b < na, eb);
+          stats_tail(sr, L, na, 2 * kStatsCap, b, b < na, eb);
         }
       }
     }
@@ -746,9 +758,34 @@ static DictPlanDev to_dev(const Geom& g, const DictPlan& plan) {
   return d;
 }
 
+// With several row groups: per patch, the number of its list entries below
+// each later group's first row (lists ascend), so a block of that group
+// starts the patch's pairs there.  One thread per patch (of the step's batch).
+__global__ __launch_bounds__(256) void list_groups_kernel(int N, int K, DictPlanDev pl,
+                                                          const int2* __restrict__ list,
+                                                          const int32_t* __restrict__ nact,
+                                                          uint16_t* __restrict__ goff, int n_batches,
+                                                          int batch) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N || (n_batches > 1 && i % n_batches != batch)) return;
+  const int na = nact[i];
+  const int2* L = list + (size_t)i * K;
+  int e = 0;
+  for (int r = 1; r < pl.RG; ++r) {
+    while (e < na && L[e].x < pl.row0[r]) ++e;
+    goff[(size_t)i * (pl.RG - 1) + (r - 1)] = (uint16_t)e;
+  }
+}
+
 hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& plan, int grid_chunks,
                              int cur, int n_batches, int batch, hipStream_t st) {
   const DictPlanDev d = to_dev(g, plan);
+  if (plan.RG > 1) {
+    list_groups_kernel<<<(g.N + 255) / 256, 256, 0, st>>>(g.N, g.K, d, b.list[cur], b.nact[cur],
+                                                          b.goff, n_batches, batch);
+    const hipError_t e0 = hipGetLastError();
+    if (e0 != hipSuccess) return e0;
+  }
   // blocks for grid_chunks chunk slots per (p, row group): the frame's count
   // when the host knows it, else all of them (blocks of slots the frame
   // leaves empty return at once)
@@ -762,11 +799,11 @@ hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& pl
   if (e != hipSuccess) return e;
   if (skip)
     dict_stats_kernel<true><<<blocks, kDictBlock, lds, st>>>(
-        g, d, b.plan, b.vpatch, b.omega_y, b.list[cur], b.nact[cur], b.scal, b.dpart, b.dx2,
+        g, d, b.plan, b.vpatch, b.omega_y, b.list[cur], b.nact[cur], b.goff, b.scal, b.dpart, b.dx2,
         n_batches, batch);
   else
     dict_stats_kernel<false><<<blocks, kDictBlock, lds, st>>>(
-        g, d, b.plan, b.vpatch, b.omega_y, b.list[cur], b.nact[cur], b.scal, b.dpart, b.dx2,
+        g, d, b.plan, b.vpatch, b.omega_y, b.list[cur], b.nact[cur], b.goff, b.scal, b.dpart, b.dx2,
         n_batches, batch);
   return hipGetLastError();
 }
