@@ -115,15 +115,22 @@ bpfa_status make_geom(const bpfa_params* p, Geom* g) {
 DictPlan make_dict_plan(const Geom& g) {
   DictPlan pl;
   const int K = g.K;
-  // accumulators per block: 128 KiB, leaving room for large visit chunks; but
-  // when the whole triangle fits beside the smallest chunk (one visit per
-  // thread), one row group: every block then walks each visit's pairs once
-  // instead of once per group
+  // One row group when the whole triangle fits beside the smallest chunk
+  // (one visit per thread): every visit's bookkeeping and list gather then
+  // happens once.  Otherwise the groups leave room for chunks of
+  // kDictChunkTarget visits: a block buckets its chunk's visits by list
+  // length and its wavefronts take consecutive runs of 64, so in a small
+  // chunk they get very different pair counts and wait for the longest at
+  // the chunk's barrier (a later group walks only the lists' tails, see
+  // list_groups_kernel, so more groups add little pair work).
   const long long whole = (long long)K * (K + 1) / 2 + K;
-  const long long room1 =
-      ((long long)kLdsBytes - (long long)(K + 1) * 4 - (long long)dict_sink_entries(K) * 8 -
-       (long long)kDictBlock * kDictVisitBytes) / 8;
-  const long long budget = whole <= room1 ? whole : kDictLdsEntries;
+  const long long fixed = (long long)(K + 1) * 4 + (long long)dict_sink_entries(K) * 8;
+  const long long room1 = ((long long)kLdsBytes - fixed - (long long)kDictBlock * kDictVisitBytes) / 8;
+  const long long budget =
+      whole <= room1 ? whole
+                     : std::max<long long>((long long)K + 1,
+                                           ((long long)kLdsBytes - fixed -
+                                            (long long)kDictChunkTarget * kDictVisitBytes) / 8);
   int rg = 0;
   pl.row0[0] = 0;
   pl.ent0[0] = 0;
@@ -529,6 +536,8 @@ bpfa_status run_step(bpfa_t h, int learn, int batch) {
     const int s0 = h->batch_slot0[batch];
     HIPCHK(launch_list_copy(g, b, 1 - h->cur, s0, h->batch_slot0[batch + 1] - s0, h->st));
   }
+  // with several statistics row groups: where each list enters each group
+  if (learn) HIPCHK(launch_list_groups(g, b, L.plan, h->cur, nbat, bsel, h->st));
   if (h->timing && (r = record(h, &ev[2])) != BPFA_OK) return r;
   if (learn)
     HIPCHK(launch_dict_stats(g, b, L.plan, h->plan_known ? h->dict_chunks : L.plan.chunks, h->cur, nbat,

@@ -19,7 +19,7 @@ constexpr int kDictBlock = 768;
 constexpr int kDictVpt = 8;       // visits per thread of one statistics chunk, held in registers
 constexpr int kChainLdsMaxK = 128;  // largest K whose binary64 C_p (K x K) the chain stages in LDS
 constexpr int kLdsBytes = 160 * 1024 - 1024;   // per block, leaving room for static arrays
-constexpr int kDictLdsEntries = 16384; // int64 accumulators per statistics block (128 KiB)
+constexpr int kDictChunkTarget = 4608; // visits per statistics chunk the row-group size leaves room for
 constexpr int kSortBlock = 256;        // patches per block of the slot sort
 constexpr int kMaxBatches = 256;       // mini-batches of the epoch schedule, at most
 
@@ -148,7 +148,7 @@ struct Buffers {
 // Plan of the dictionary-statistics pass: row groups of the K x K triangle
 // that fit the LDS accumulator, and patch-visit chunks per (p, row group).
 struct DictPlan {
-  int RG = 1;                  // row groups
+  int RG = 1;                  // row groups (at most 46: K <= 1024, and a group holds >= 11.8k entries)
   int row0[65];                // row group r covers atoms [row0[r], row0[r+1])
   long long ent0[65];          // triangle entry offset of row0[r]
   int chunks = 1;
@@ -222,6 +222,8 @@ hipError_t launch_sweep_reduce(const Geom& g, const Buffers& b, const int* range
 // (chunk count, chunk size and mapping from the frame plan; plan.chunks and
 // plan.chunk_visits give the launch's maximum; the grid covers grid_chunks
 // chunk slots, at least the frame's)
+hipError_t launch_list_groups(const Geom& g, const Buffers& b, const DictPlan& plan, int cur,
+                              int n_batches, int batch, hipStream_t st);
 hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& plan, int grid_chunks,
                              int cur, int n_batches, int batch, hipStream_t st);
 hipError_t launch_dict_reduce(const Geom& g, const Buffers& b, const DictPlan& plan,

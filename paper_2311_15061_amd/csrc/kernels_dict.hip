@@ -144,9 +144,11 @@ __device__ __forceinline__ void stage_from(Stage& s, const int2 (&raw)[kStatsCap
   }
 }
 
-// SKIP: with three or more row groups a row no lane of the wave holds in
-// this block's group (it adds only to the sinks) is skipped whole by a
-// uniform branch; with fewer groups the test costs more than it saves
+// SKIP: with several row groups a row no lane of the wave holds in this
+// block's group (it adds only to the sinks) is skipped whole by a uniform
+// branch; a lane's rows in the group are a prefix of its staged entries, so
+// this bounds the rows by the wave's longest prefix.  With one group every
+// staged row is in it and the test is left out.
 template <int NB, bool SKIP>
 __device__ __forceinline__ void stats_pairs(const StatsRow& sr, const Stage& s) {
 #pragma unroll
@@ -760,7 +762,9 @@ static DictPlanDev to_dev(const Geom& g, const DictPlan& plan) {
 
 // With several row groups: per patch, the number of its list entries below
 // each later group's first row (lists ascend), so a block of that group
-// starts the patch's pairs there.  One thread per patch (of the step's batch).
+// starts the patch's pairs there.  One thread per patch (of the step's
+// batch); the first entries are loaded together, a longer list continues
+// from memory only while its entries stay below the boundary.
 __global__ __launch_bounds__(256) void list_groups_kernel(int N, int K, DictPlanDev pl,
                                                           const int2* __restrict__ list,
                                                           const int32_t* __restrict__ nact,
@@ -770,29 +774,38 @@ __global__ __launch_bounds__(256) void list_groups_kernel(int N, int K, DictPlan
   if (i >= N || (n_batches > 1 && i % n_batches != batch)) return;
   const int na = nact[i];
   const int2* L = list + (size_t)i * K;
-  int e = 0;
+  int x[kStatsCap];
+#pragma unroll
+  for (int a = 0; a < kStatsCap; ++a) x[a] = a < na ? L[a].x : K;
   for (int r = 1; r < pl.RG; ++r) {
-    while (e < na && L[e].x < pl.row0[r]) ++e;
+    const int lo = pl.row0[r];
+    int e = 0;
+#pragma unroll
+    for (int a = 0; a < kStatsCap; ++a) e += x[a] < lo ? 1 : 0;
+    if (e == kStatsCap)
+      while (e < na && L[e].x < lo) ++e;
     goff[(size_t)i * (pl.RG - 1) + (r - 1)] = (uint16_t)e;
   }
+}
+
+hipError_t launch_list_groups(const Geom& g, const Buffers& b, const DictPlan& plan, int cur,
+                              int n_batches, int batch, hipStream_t st) {
+  if (plan.RG <= 1) return hipSuccess;
+  list_groups_kernel<<<(g.N + 255) / 256, 256, 0, st>>>(g.N, g.K, to_dev(g, plan), b.list[cur],
+                                                        b.nact[cur], b.goff, n_batches, batch);
+  return hipGetLastError();
 }
 
 hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& plan, int grid_chunks,
                              int cur, int n_batches, int batch, hipStream_t st) {
   const DictPlanDev d = to_dev(g, plan);
-  if (plan.RG > 1) {
-    list_groups_kernel<<<(g.N + 255) / 256, 256, 0, st>>>(g.N, g.K, d, b.list[cur], b.nact[cur],
-                                                          b.goff, n_batches, batch);
-    const hipError_t e0 = hipGetLastError();
-    if (e0 != hipSuccess) return e0;
-  }
   // blocks for grid_chunks chunk slots per (p, row group): the frame's count
   // when the host knows it, else all of them (blocks of slots the frame
   // leaves empty return at once)
   const int blocks = g.P * plan.RG * std::max(1, std::min(grid_chunks, plan.chunks));
   // the LDS holds visit records for the largest chunk the plan allows
   const size_t lds = dict_stats_lds(g.K, d.rec_stride, plan.chunk_visits);
-  const bool skip = plan.RG >= 3;
+  const bool skip = plan.RG >= 2;
   hipError_t e = hipFuncSetAttribute(
       skip ? (const void*)dict_stats_kernel<true> : (const void*)dict_stats_kernel<false>,
       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
