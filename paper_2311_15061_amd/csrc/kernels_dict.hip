@@ -36,7 +36,6 @@
 namespace bpfa {
 
 constexpr int kStatsCap = 16;   // active entries of a patch held in registers
-constexpr int kStatsAhead = 1;  // statistics iterations whose list rows are in flight
 
 // a visit of the statistics pass: patch, its list's length from the block's
 // row group on and the offset where that part starts, the observed value, the
@@ -257,7 +256,7 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
     long long* __restrict__ dpart, double* __restrict__ dx2, int n_batches, int batch) {
   extern __shared__ long long acc[];
   __shared__ double s_x2[kDictBlock / kWave];
-  __shared__ int s_total;
+  __shared__ int s_total, s_next;
   // this frame's chunking: cc chunks of cvf observed pixels (the launch has
   // room for pl.chunks chunks of pl.chunk_visits)
   const int nom = scal->n_omega;
@@ -347,7 +346,10 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
       if (b <= K) bins[b] = run + incl - x;
       run += __shfl(incl, kWave - 1);
     }
-    if (lane == 0) s_total = run;
+    if (lane == 0) {
+      s_total = run;
+      s_next = kDictBlock / kWave;   // pass 3's first unclaimed run
+    }
   }
   __syncthreads();
   // pass 2: place the visits, grouped by n_a
@@ -362,12 +364,15 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
     }
   __syncthreads();
   const int nvis = s_total;
-  // pass 3: outer products into the accumulators
-  // each iteration's list rows are fetched kStatsAhead iterations ahead, so
-  // the gather latency overlaps the accumulation of the visits before it
-  auto fetch = [&](int vb, VisitRow& f) {
-    const int vi = vb + tid;
-    const bool on = vi < nvis;
+  // pass 3: outer products into the accumulators.  The visits, sorted by
+  // list length, form runs of 64 (one per wavefront step) claimed from the
+  // longest down: wavefront w takes run w, then the next unclaimed one, so
+  // the wavefronts finish the chunk nearly together (longest runs first).
+  // A run's list rows are fetched while the run before it accumulates.
+  const int nruns = (nvis + kWave - 1) / kWave;
+  auto fetch = [&](int run, VisitRow& f) {
+    const int vi = nvis - kWave * (run + 1) + lane;
+    const bool on = vi >= 0;
     f.pid = on ? v_pat[vi] : 0;
     f.na = on ? (int)v_na[vi] : 0;
     f.off = on ? (int)v_off[vi] : 0;
@@ -388,15 +393,16 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
 #pragma unroll
     for (int a = 0; a < kStatsCap; ++a) f.raw[a] = make_int2(-1, 0);
   };
-  VisitRow q[kStatsAhead + 1];
-#pragma unroll
-  for (int d = 0; d < kStatsAhead; ++d) {
-    clear(q[d]);
-    if (d * kDictBlock < nvis) fetch(d * kDictBlock, q[d]);
-  }
-  for (int vb = 0; vb < nvis; vb += kDictBlock) {
-    clear(q[kStatsAhead]);
-    if (vb + kStatsAhead * kDictBlock < nvis) fetch(vb + kStatsAhead * kDictBlock, q[kStatsAhead]);
+  VisitRow q[2];
+  int run = tid / kWave;
+  clear(q[0]);
+  if (run < nruns) fetch(run, q[0]);
+  while (run < nruns) {
+    int nxt = 0;
+    if (lane == 0) nxt = atomicAdd(&s_next, 1);
+    nxt = __builtin_amdgcn_readfirstlane(nxt);
+    clear(q[1]);
+    if (nxt < nruns) fetch(nxt, q[1]);
     const int pid = q[0].pid, na = q[0].na, wmax = q[0].wmax;
     const int2* L = list + (size_t)pid * K + q[0].off;
     const int lim = K - 1 - q[0].off;   // last index inside the patch's list row
@@ -442,8 +448,8 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
         }
       }
     }
-#pragma unroll
-    for (int d = 0; d < kStatsAhead; ++d) q[d] = q[d + 1];
+    q[0] = q[1];
+    run = nxt;
   }
   __syncthreads();   // the visit records are rewritten by the next chunk
   }
