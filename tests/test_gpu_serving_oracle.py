@@ -51,11 +51,9 @@ def stream_frames():
     return out
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
-def test_stream_matches_oracle_in_follow_mode(precision):
-    frames = stream_frames()
-    print("server stream %d: %d frames, %s" % (STREAM, len(frames), precision), flush=True)
-    srv = serve.Server(patch=PATCH, K=K, n_streams=3, sc_iters=SC_ITERS, dict_every=DICT_EVERY,
+def _run_stream(frames, patch, K, sc_iters, dict_every, precision, label):
+    print("server stream %d: %d frames, %s (%s)" % (STREAM, len(frames), precision, label), flush=True)
+    srv = serve.Server(patch=patch, K=K, n_streams=3, sc_iters=sc_iters, dict_every=dict_every,
                        max_slots=2, seed=SEED, precision=precision)
     tickets = [srv.submit(STREAM, y, m)[0] for y, m in frames]
     srv.drain()
@@ -63,27 +61,27 @@ def test_stream_matches_oracle_in_follow_mode(precision):
     srv.close()
 
     prm = ob.Params(K=K, seed=SEED, problem_id=STREAM)
-    st = ob.init_state(prm, 1, int(np.prod(PATCH)))
+    st = ob.init_state(prm, 1, int(np.prod(patch)))
     tol_x = FP32_TOL if precision == "fp32" else 1e-4
     worst = {}
     for f, (y, m) in enumerate(frames):
         r = res[tickets[f]]
         assert r["status"] == bpfa.OK and r["frame_index"] == f
-        learn_frame = (f + 1) % DICT_EVERY == 0
+        learn_frame = (f + 1) % dict_every == 0
         assert r["learned"] == int(learn_frame)
-        X, Mk = patches.extract(y.astype(np.float64), m, PATCH, (1, 1))
+        X, Mk = patches.extract(y.astype(np.float64), m, patch, (1, 1))
         N = X.shape[0]
         st = ob.State(D=st.D, W=np.zeros((N, K)), Z=np.zeros((N, K), bool), ell=st.ell,
                       gamma_s=st.gamma_s, gamma_eps=st.gamma_eps, t=st.t)
         # the first frame starts from the handle's own prior draw (the stream's
         # first dictionary is that draw, made on the device), later ones from
         # the state the previous frame's handle ended with
-        prob = bpfa.Problem(y, m, PATCH, K=K, seed=SEED, problem_id=STREAM)
+        prob = bpfa.Problem(y, m, patch, K=K, seed=SEED, problem_id=STREAM)
         prob.set_precision(precision)
         if f > 0:
             prob.set_state(D=gs["D"], logit_pi=gs["logit_pi"], gamma_s=gs["gamma_s"],
                            gamma_eps=gs["gamma_eps"], t=gs["t"])
-        for learn in [False] * SC_ITERS + ([True] if learn_frame else []):
+        for learn in [False] * sc_iters + ([True] if learn_frame else []):
             prob.iterate(1, bpfa.LEARN_DICT if learn else bpfa.SPARSE_CODE_ONLY)
             gs = prob.get_state()
             st, rep = ob.iterate(prm, X, Mk, st, learn_dict=learn, follow_z=gs["Z"])
@@ -94,7 +92,27 @@ def test_stream_matches_oracle_in_follow_mode(precision):
         xh = prob.reconstruct()
         prob.close()
         assert np.array_equal(r["out"], xh), "served frame %d differs from the handle's" % f
-        ex = assert_close(xh, ob.reconstruct(st, y.shape, PATCH, (1, 1)), tol_x,
+        ex = assert_close(xh, ob.reconstruct(st, y.shape, patch, (1, 1)), tol_x,
                           "frame %d reconstruction" % f)
         worst["recon"] = max(worst.get("recon", 0.0), ex)
-    record("serving stream, 4 frames 34-52 px, K=24, %s" % precision, **worst)
+    record("%s, %s" % (label, precision), **worst)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_stream_matches_oracle_in_follow_mode(precision):
+    _run_stream(stream_frames(), PATCH, K, SC_ITERS, DICT_EVERY, precision,
+                "serving stream, 4 frames 34-52 px, K=24")
+
+
+def test_stream_at_serving_size_matches_oracle():
+    """The serving leg's own configuration: 256 x 256 frames, 10 x 10 patches,
+    K = 128 (the smallest of its frame sizes; the oracle takes ~1 s per
+    iteration there), two frames at 10% and 20% sampling, three sparse-coding
+    iterations each and a dictionary iteration on the second."""
+    rng = np.random.Generator(np.random.PCG64(909))
+    wl = synth.workload("stem512")
+    frames = []
+    for rho in (0.1, 0.2):
+        y, m, _ = synth.make_frame(wl, data_seed=int(rng.integers(1 << 30)), shape=(256, 256), rho=rho)
+        frames.append((y.astype(np.float32), m))
+    _run_stream(frames, (10, 10), 128, 3, 2, "fp32", "serving stream, 2 frames 256 x 256, K=128")
