@@ -516,6 +516,14 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// The standard normal of the draw of d_jp: Box-Muller on the DICT Philox
+// block (p, j, t); `stream` carries the tag and the problem id.
+__device__ __forceinline__ double chain_normal(int p, int j, uint32_t t, uint32_t stream,
+                                               uint32_t key0, uint32_t key1) {
+  const Block4 rb = philox10((uint32_t)p, (uint32_t)j, t, stream, key0, key1);
+  return sqrt(-2.0 * log(u01d(rb.w0))) * cos(2.0 * M_PI * u01d(rb.w1));
+}
+
 // One wavefront per position p.  Lane l owns components j = l + 64 m of d
 // and of u = C_p d.  With g_k = gamma_eps / lam_k and the constant
 // t_k = g_k (B_k + C_kk d_k) + n_k / sqrt(lam_k) (d_k not yet redrawn),
@@ -526,13 +534,14 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 // scale: the data statistics enter the conditional multiplied by it (a
 // mini-batch step's N / n_b), i.e. gamma_eps scale in place of gamma_eps in
 // lam and g; the residual sum of squares stays the batch's own.
+// u0, nrm: u = C_p d and the normals n_j when the caller has them at hand.
 template <int KPL, int PF>
 __device__ __forceinline__ void chain_run(const Geom& g, int p, int lane, const double* C,
                                           const double* Bp, const double* diagp, double x2,
                                           DevScalars* scal, float* __restrict__ D,
                                           double* __restrict__ sumr2_p, double scale,
                                           uint32_t key0, uint32_t key1, uint32_t stream,
-                                          const double* u0 = nullptr) {
+                                          const double* u0 = nullptr, const double* nrm = nullptr) {
   static_assert(kWave % PF == 0, "a ring slot keeps its row across register groups");
   const int K = g.K, P = g.P;
   const uint32_t t = (uint32_t)scal->t;
@@ -545,8 +554,7 @@ __device__ __forceinline__ void chain_run(const Geom& g, int p, int lane, const 
     const int j = lane + kWave * m;
     dreg[m] = ureg[m] = greg[m] = treg[m] = breg[m] = 0.0;
     if (j < K) {
-      const Block4 rb = philox10((uint32_t)p, (uint32_t)j, t, stream, key0, key1);
-      const double n = sqrt(-2.0 * log(u01d(rb.w0))) * cos(2.0 * M_PI * u01d(rb.w1));
+      const double n = nrm ? nrm[j] : chain_normal(p, j, t, stream, key0, key1);
       const double cjj = diagp[j];
       const double lam = (double)P + ge * cjj;
       breg[m] = Bp[j];
@@ -695,26 +703,30 @@ __global__ __launch_bounds__(1024) void dict_chain_lds_kernel(
     double* __restrict__ sumr2_p, double scale, uint32_t key0, uint32_t key1, uint32_t stream) {
   extern __shared__ double Cs[];                 // K x K, then the u partials
   __shared__ double s_B[kChainLdsMaxK], s_diag[kChainLdsMaxK], s_d[kChainLdsMaxK],
-      s_u[kChainLdsMaxK];
+      s_u[kChainLdsMaxK], s_n[kChainLdsMaxK];
   const int p = blockIdx.x, K = g.K, P = g.P, tid = threadIdx.x;
   const int E = K * (K + 1) / 2;
   const double* T = Ctri + (size_t)p * E;
-  // the symmetric expansion, 16 loads per thread in flight before their
-  // stores (a load-store loop waits out one memory latency per element)
-  constexpr int kExp = 16;
-  for (int base = 0; base < K * K; base += 1024 * kExp) {
+  // the symmetric expansion: thread (row k0 + R u, column j) with R = 1024 / K
+  // rows per step (one division per thread, 32-bit offsets: K <= 128), all
+  // of a thread's loads in flight before their stores (a load-store loop
+  // waits out one memory latency per element)
+  constexpr int kExp = 16;   // rows per thread: K / (1024 / K) <= 16 for K <= 128
+  {
+    const int R = 1024 / K, j = tid % K, k0 = tid / K;
     double v[kExp];
 #pragma unroll
     for (int u = 0; u < kExp; ++u) {
-      const int idx = min(base + tid + 1024 * u, K * K - 1);   // clamped: stays in the triangle
-      const int k = idx / K, j = idx - k * K;
+      const int k = min(k0 + R * u, K - 1);        // clamped: stays in the triangle
       const int a = min(k, j), b = max(k, j);
-      v[u] = T[tri_off(a, K) + (b - a)];
+      v[u] = T[(a * (2 * K - a + 1) >> 1) + (b - a)];
     }
+    if (k0 < R) {
 #pragma unroll
-    for (int u = 0; u < kExp; ++u) {
-      const int idx = base + tid + 1024 * u;
-      if (idx < K * K) Cs[idx] = v[u];
+      for (int u = 0; u < kExp; ++u) {
+        const int k = k0 + R * u;
+        if (k < K) Cs[k * K + j] = v[u];
+      }
     }
   }
   for (int k = tid; k < K; k += 1024) {
@@ -723,6 +735,11 @@ __global__ __launch_bounds__(1024) void dict_chain_lds_kernel(
   }
   __syncthreads();
   for (int k = tid; k < K; k += 1024) s_diag[k] = Cs[k * K + k];
+  // the chain's normals, drawn by the wavefronts after the first while the
+  // block forms u (the chain itself runs on the first)
+  if (tid >= kWave && tid - kWave < K)
+    s_n[tid - kWave] = chain_normal(p, tid - kWave, (uint32_t)scal->t,
+                                    (stream & 0xFFu) | (scal->problem_id << 8), key0, key1);
   // u_j = sum_k C[k][j] d_k: slice s of the k range per thread group
   double* up = Cs + (size_t)K * K;               // [slices][K]
   const int slices = 1024 / K, per = (K + slices - 1) / slices;
@@ -743,7 +760,7 @@ __global__ __launch_bounds__(1024) void dict_chain_lds_kernel(
     // 8 row loads in flight: the LDS counter holds at most 15 outstanding,
     // so a deeper ring makes every step wait for all of them
     chain_run<KPL, 8 / KPL>(g, p, tid, Cs, s_B, s_diag, x2p[p], scal, D, sumr2_p, scale, key0, key1,
-                            stream, s_u);
+                            stream, s_u, s_n);
 }
 
 static DictPlanDev to_dev(const Geom& g, const DictPlan& plan) {
