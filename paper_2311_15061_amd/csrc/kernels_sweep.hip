@@ -354,11 +354,11 @@ __device__ __forceinline__ void sweep_group(const SweepArgs& a, const int4* __re
       break;
     case 2:
       if (J <= 12) BPFA_BODY(12, 2);
-      else BPFA_BODY(16, 2);
+      else if (J <= 16) BPFA_BODY(16, 2);
+      else BPFA_BODY(20, 2);
       break;
     case 4:
-      if (J <= 10) BPFA_BODY(10, 4);
-      else if (J <= 12) BPFA_BODY(12, 4);
+      if (J <= 12) BPFA_BODY(12, 4);
       else BPFA_BODY(16, 4);
       break;
     case 8:
