@@ -206,7 +206,7 @@ hipError_t launch_init_dict(const Geom& g, const Buffers& b, uint32_t key0, uint
 hipError_t launch_sweep(const int4* waves, const int* range, int blocks, bool strided, size_t lds,
                         const SweepArgs& a, hipStream_t st);
 // lanes per patch of the sweep for a patch with c observed pixels
-inline int sweep_lanes(int c) { return c <= 16 ? 1 : c <= 40 ? 2 : c <= 64 ? 4 : c <= 128 ? 8 : 16; }
+inline int sweep_lanes(int c) { return c <= 16 ? 1 : c <= 48 ? 2 : c <= 64 ? 4 : c <= 128 ? 8 : 16; }
 // wavefronts the sweep table can need for N slots: at least 4 slots per wave
 // except the last wave of each (batch, lanes per slot) run
 inline long long sweep_wave_capacity(long long N) { return (N + 3) / 4 + 8LL * kMaxBatches + 16; }

@@ -381,8 +381,8 @@ __global__ void init_dict_kernel(Geom g, float* __restrict__ D, uint32_t key0, u
 // largest slot: J = max(4, |Obs| rounded up to even) for one lane per patch;
 // for a group of L lanes 12 or 16 (L J >= |Obs|), and 10 too for 4 lanes.
 
-__device__ __constant__ int kClassLo[kLaneClasses] = {0, 17, 41, 65, 129};
-__device__ __constant__ int kClassHi[kLaneClasses] = {16, 40, 64, 128, 256};
+__device__ __constant__ int kClassLo[kLaneClasses] = {0, 17, 49, 65, 129};
+__device__ __constant__ int kClassHi[kLaneClasses] = {16, 48, 64, 128, 256};
 __device__ __constant__ int kClassLanes[kLaneClasses] = {1, 2, 4, 8, 16};
 
 struct PlanArgs {
@@ -488,7 +488,7 @@ __global__ __launch_bounds__(256) void plan_waves_kernel(int E, const FramePlan*
   // rows per lane: the smallest compiled body that holds the wave's largest patch
   int J = 16;
   if (lanes == 1) J = max(4, (clast + 1) & ~1);
-  else if (lanes == 2 && clast > 32) J = 20;
+  else if (lanes == 2 && clast > 32) J = clast <= 40 ? 20 : 24;
   else if (clast <= 12 * lanes) J = 12;
   waves[w] = make_int4(slot, ns, lanes, J);
 }

@@ -122,7 +122,12 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslo
   const int K = a.K;
 
   lds_f* const L = (lds_f*)lds;
-  lds_f* col[J];     // column p_j of the tile (p_j = P: the zero row)
+  // column p_j of the tile (p_j = P: the zero row) for each of the lane's
+  // rows: a pointer per row, or for the longest bodies two 16-bit float offsets
+  // per register (the tile is below 64 K floats), unpacked at each use
+  constexpr bool kPacked = J > 20;
+  lds_f* colp[kPacked ? 1 : J];
+  uint32_t colk[kPacked ? (J + 1) / 2 : 1];
   float r[J];        // residual on this lane's observed pixels
 #pragma unroll
   for (int jj = 0; jj < J; ++jj) {
@@ -133,9 +138,19 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslo
       p = a.obs_idx[(size_t)j * npad + s];
       x = a.obs_val[(size_t)j * npad + s];
     }
-    col[jj] = L + p * a.KS;
+    if constexpr (kPacked) {
+      const uint32_t o = (uint32_t)(p * a.KS);
+      if (jj & 1) colk[jj >> 1] |= o << 16;
+      else colk[jj >> 1] = o;
+    } else {
+      colp[jj] = L + p * a.KS;
+    }
     r[jj] = x;
   }
+  auto col = [&](int jj) -> lds_f* {
+    if constexpr (kPacked) return L + ((jj & 1) ? (colk[jj >> 1] >> 16) : (colk[jj >> 1] & 0xFFFFu));
+    else return colp[jj];
+  };
   uint8_t* const cnt_w = cnt_lds + wid * K;
   const float* __restrict__ Ck = a.Ck;
 
@@ -163,7 +178,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslo
           const float w = __int_as_float(eb[u].y);
           const int ko = eb[u].x - k0;
 #pragma unroll
-          for (int j = 0; j < J; ++j) r[j] = fmaf(-col[j][ko], w, r[j]);
+          for (int j = 0; j < J; ++j) r[j] = fmaf(-col(j)[ko], w, r[j]);
           used = u + 1;
         }
       }
@@ -229,6 +244,12 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslo
       // induction register plus a copy
       int ko = k - k0;
       asm volatile("" : "+s"(ko));
+      // packed column offsets are unpacked at each use, not once for the
+      // whole loop (that would hold J registers again)
+      if constexpr (kPacked) {
+#pragma unroll
+        for (int i = 0; i < (J + 1) / 2; ++i) asm volatile("" : "+v"(colk[i]));
+      }
       // old weights of the pair; the next two entries are fetched now and
       // first needed by the next pair
       const bool c0 = e0.x == k;
@@ -246,7 +267,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslo
       float dl0 = 0.f, dl1 = 0.f, rh0 = 0.f, rh1 = 0.f, g01 = 0.f;
 #pragma unroll
       for (int j = 0; j < J; ++j) {
-        const float x0 = col[j][ko], x1 = col[j][ko + 1];
+        const float x0 = col(j)[ko], x1 = col(j)[ko + 1];
         dl0 = fmaf(x0, x0, dl0);
         dl1 = fmaf(x1, x1, dl1);
         rh0 = fmaf(x0, r[j], rh0);
@@ -271,7 +292,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& a, int blk, int nslo
       if (dw0 != 0.f || dw1 != 0.f) {
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-          const float x0 = col[j][ko], x1 = col[j][ko + 1];
+          const float x0 = col(j)[ko], x1 = col(j)[ko + 1];
           r[j] = fmaf(-x1, dw1, fmaf(-x0, dw0, r[j]));
         }
       }
@@ -355,7 +376,8 @@ __device__ __forceinline__ void sweep_group(const SweepArgs& a, const int4* __re
     case 2:
       if (J <= 12) BPFA_BODY(12, 2);
       else if (J <= 16) BPFA_BODY(16, 2);
-      else BPFA_BODY(20, 2);
+      else if (J <= 20) BPFA_BODY(20, 2);
+      else BPFA_BODY(24, 2);
       break;
     case 4:
       if (J <= 12) BPFA_BODY(12, 4);

@@ -155,7 +155,8 @@ def test_sparse_code_only_parity():
     ((10, 9, 6, 5), (3, 3, 2, 2), (1, 1, 2, 1), 12, 0.3),  # 4-D patches spanning two frames
     ((24, 22, 3), (6, 6, 3), (1, 1, 1), 16, 0.3),  # full-depth patches (B_2 = M_2, e.g. RGB)
     ((20, 20, 3), (5, 5, 1), (1, 1, 1), 16, 0.3),  # one single-channel dictionary across layers
-    ((26, 26), (12, 12), (1, 1), 16, 0.35),       # |Obs| ~ 50: 4 lanes per patch
+    ((26, 26), (12, 12), (1, 1), 16, 0.35),       # |Obs| ~ 50: 2 (20 and 24 rows) and 4 lanes per patch
+    ((30, 30), (12, 12), (1, 1), 18, 0.28),       # |Obs| ~ 40: 2 lanes per patch, 16-, 20- and 24-row bodies
     ((22, 22), (12, 12), (1, 1), 12, 0.65),       # |Obs| ~ 94: 8 lanes per patch
     ((28, 28), (12, 12), (1, 1), 20, 0.2),        # |Obs| spread over 1, 2 and 4 lanes per patch
     ((20, 20), (12, 12), (1, 1), 8, 0.95),        # |Obs| ~ 137: 16 lanes per patch
