@@ -115,22 +115,18 @@ bpfa_status make_geom(const bpfa_params* p, Geom* g) {
 DictPlan make_dict_plan(const Geom& g) {
   DictPlan pl;
   const int K = g.K;
-  // One row group when the whole triangle fits beside the smallest chunk
-  // (one visit per thread): every visit's bookkeeping and list gather then
-  // happens once.  Otherwise the groups leave room for chunks of
-  // kDictChunkTarget visits: a block buckets its chunk's visits by list
-  // length and its wavefronts take consecutive runs of 64, so in a small
-  // chunk they get very different pair counts and wait for the longest at
-  // the chunk's barrier (a later group walks only the lists' tails, see
-  // list_groups_kernel, so more groups add little pair work).
+  // Row groups leave room for chunks of kDictChunkTarget visits (one group
+  // when the whole triangle fits beside such a chunk).  A block buckets its
+  // chunk's visits by list length and its wavefronts claim runs of 64, so in
+  // a small chunk they get very different pair counts and wait for the
+  // longest at the chunk's barrier; several row groups cost each visit its
+  // bookkeeping and gather once per group, but a later group walks only the
+  // lists' tails (list_groups_kernel), so they add little pair work.
   const long long whole = (long long)K * (K + 1) / 2 + K;
   const long long fixed = (long long)(K + 1) * 4 + (long long)dict_sink_entries(K) * 8;
-  const long long room1 = ((long long)kLdsBytes - fixed - (long long)kDictBlock * kDictVisitBytes) / 8;
-  const long long budget =
-      whole <= room1 ? whole
-                     : std::max<long long>((long long)K + 1,
-                                           ((long long)kLdsBytes - fixed -
-                                            (long long)kDictChunkTarget * kDictVisitBytes) / 8);
+  const long long group_room =
+      ((long long)kLdsBytes - fixed - (long long)kDictChunkTarget * kDictVisitBytes) / 8;
+  const long long budget = whole <= group_room ? whole : std::max<long long>((long long)K + 1, group_room);
   int rg = 0;
   pl.row0[0] = 0;
   pl.ent0[0] = 0;
