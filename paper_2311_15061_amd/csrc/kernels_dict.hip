@@ -22,8 +22,9 @@
 //   of two and rounded to an integer by adding 1.5 * 2^52 (exact for
 //   |x| < 2^51); integer adds are associative, so the statistics do not
 //   depend on scheduling.
-// dict_reduce_kernel: sums the chunk partials, one block per (p, row k),
-//   into the symmetric binary64 C_p, B_p and the diagonal.
+// dict_reduce_kernel: sums the chunk partials, one block per (p, 32 x 32
+//   tile of the upper triangle), into the symmetric binary64 C_p, B_p and
+//   the diagonal.
 // dict_chain_kernel: one wavefront per p runs the chain with rows of C_p
 //   prefetched ahead of use, keeping u = C_p d current instead of reducing a
 //   dot product per step, draws d_kp with the Philox DICT stream, and forms
@@ -468,35 +469,64 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
   }
 }
 
-// one block per (p, row k): C_p[k][j] = C_p[j][k] for j >= k, B_p[k], diag, X2_p
+// One block per (p, 32 x 32 tile of the upper triangle of C_p): entry (k, j),
+// j >= k, is the sum of the chunk partials of row k's group; the block writes
+// the tile's rows and, through LDS, its transpose below the diagonal, both in
+// whole rows (a write of C_p[j][k] per entry strides by K); the diagonal
+// tiles also write diag and B_p, the first one X2_p.
+constexpr int kRedTile = 32;
 __global__ __launch_bounds__(256) void dict_reduce_kernel(
     Geom g, DictPlanDev pl, const FramePlan* __restrict__ fplan, const long long* __restrict__ dpart,
     const double* __restrict__ dx2, const DevScalars* __restrict__ scal, double* __restrict__ Cfull,
     double* __restrict__ Bvec, double* __restrict__ diag, double* __restrict__ x2p) {
+  __shared__ double tile[kRedTile][kRedTile + 1];
   const int K = g.K;
+  const int nt = (K + kRedTile - 1) / kRedTile, ntri = nt * (nt + 1) / 2;
+  const int p = blockIdx.x / ntri;
+  int t = blockIdx.x - p * ntri, ti = 0;
+  while (t >= nt - ti) {   // tile (ti, tj), ti <= tj, rows of the upper triangle in order
+    t -= nt - ti;
+    ++ti;
+  }
+  const int tj = ti + t;
   const int cc = fplan->dict_chunks;
-  const int p = blockIdx.x / K, k = blockIdx.x % K;
-  int rg = 0;
-  while (rg + 1 < pl.RG && pl.row0[rg + 1] <= k) ++rg;
-  const long long e0 = pl.ent0[rg];
-  const int E = (int)(pl.ent0[rg + 1] - e0);
-  const long long* rec = dpart + (size_t)(p * pl.RG + rg) * pl.chunks * pl.rec_stride;
-  const long long ek = tri_off(k, K) - e0 - k;
   const double inv_c = 1.0 / scal->scale_c;
   double* C = Cfull + (size_t)p * K * K;
-  for (int j = k + threadIdx.x; j < K; j += blockDim.x) {
-    long long sum = 0;
-    for (int c = 0; c < cc; ++c) sum += rec[(size_t)c * pl.rec_stride + ek + j];
-    const double v = (double)sum * inv_c;
-    C[(size_t)k * K + j] = v;
-    C[(size_t)j * K + k] = v;
-    if (j == k) diag[(size_t)p * K + k] = v;
+  const int tx = threadIdx.x % kRedTile, ty = threadIdx.x / kRedTile;
+  const int j = tj * kRedTile + tx;
+  for (int r = ty; r < kRedTile; r += 256 / kRedTile) {
+    const int k = ti * kRedTile + r;
+    double v = 0.0;
+    if (k < K && j < K && j >= k) {
+      int rg = 0;
+      while (rg + 1 < pl.RG && pl.row0[rg + 1] <= k) ++rg;
+      const long long* rec = dpart + (size_t)(p * pl.RG + rg) * pl.chunks * pl.rec_stride;
+      const long long ek = tri_off(k, K) - pl.ent0[rg] - k;
+      long long sum = 0;
+      for (int c = 0; c < cc; ++c) sum += rec[(size_t)c * pl.rec_stride + ek + j];
+      v = (double)sum * inv_c;
+      C[(size_t)k * K + j] = v;
+      if (j == k) diag[(size_t)p * K + k] = v;
+    }
+    tile[r][tx] = v;
   }
-  if (threadIdx.x == 0) {
-    long long sum = 0;
-    for (int c = 0; c < cc; ++c) sum += rec[(size_t)c * pl.rec_stride + E + (k - pl.row0[rg])];
-    Bvec[(size_t)p * K + k] = (double)sum / scal->scale_b;
-    if (k == 0) {
+  __syncthreads();
+  for (int r = ty; r < kRedTile; r += 256 / kRedTile) {
+    const int jr = tj * kRedTile + r, kc = ti * kRedTile + tx;
+    if (jr < K && kc < jr) C[(size_t)jr * K + kc] = tile[tx][r];
+  }
+  if (ti == tj && threadIdx.x < kRedTile) {
+    const int k = ti * kRedTile + threadIdx.x;
+    if (k < K) {
+      int rg = 0;
+      while (rg + 1 < pl.RG && pl.row0[rg + 1] <= k) ++rg;
+      const long long* rec = dpart + (size_t)(p * pl.RG + rg) * pl.chunks * pl.rec_stride;
+      const int E = (int)(pl.ent0[rg + 1] - pl.ent0[rg]);
+      long long sum = 0;
+      for (int c = 0; c < cc; ++c) sum += rec[(size_t)c * pl.rec_stride + E + (k - pl.row0[rg])];
+      Bvec[(size_t)p * K + k] = (double)sum / scal->scale_b;
+    }
+    if (ti == 0 && threadIdx.x == 0) {
       double x2 = 0.0;
       for (int c = 0; c < cc; ++c) x2 += dx2[p * pl.chunks + c];
       x2p[p] = x2;
@@ -847,7 +877,8 @@ hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& pl
 hipError_t launch_dict_reduce(const Geom& g, const Buffers& b, const DictPlan& plan,
                               hipStream_t st) {
   const DictPlanDev d = to_dev(g, plan);
-  dict_reduce_kernel<<<g.P * g.K, 256, 0, st>>>(g, d, b.plan, b.dpart, b.dx2, b.scal, b.Cfull,
+  const int nt = (g.K + kRedTile - 1) / kRedTile;
+  dict_reduce_kernel<<<g.P * (nt * (nt + 1) / 2), 256, 0, st>>>(g, d, b.plan, b.dpart, b.dx2, b.scal, b.Cfull,
                                                 b.Bvec, b.diag, b.x2p);
   return hipGetLastError();
 }
