@@ -379,7 +379,9 @@ __global__ void init_dict_kernel(Geom g, float* __restrict__ D, uint32_t key0, u
 // each (batch, class) run of slots into wavefronts of 64 / lanes_c slots
 // (the last one shorter).  A wavefront's register count J covers its last,
 // largest slot: J = max(4, |Obs| rounded up to even) for one lane per patch;
-// for a group of L lanes 12 or 16 (L J >= |Obs|), and 10 too for 4 lanes.
+// for a group of L lanes 12 or 16 (L J >= |Obs|), and 20 or 24 too for two
+// lanes (patches with 33-48 observed pixels: fewer lanes per patch repeat the
+// pair's draws and decisions fewer times).
 
 __device__ __constant__ int kClassLo[kLaneClasses] = {0, 17, 49, 65, 129};
 __device__ __constant__ int kClassHi[kLaneClasses] = {16, 48, 64, 128, 256};
