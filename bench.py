@@ -444,8 +444,14 @@ def main():
         prob.iterate(iters, bpfa.LEARN_DICT)
         prob.reconstruct(out_d)
 
-    for _ in range(args.warmup):
+    # the first frame on fresh caches and allocations, timed on its own (warm-up)
+    first_ms = None
+    for w in range(args.warmup):
+        t_w = time.perf_counter()
         step()
+        if w == 0:
+            prob.sync()
+            first_ms = 1e3 * (time.perf_counter() - t_w)
     prob.sync()
     prob.set_timing(True)
     torch.cuda.synchronize()
@@ -456,6 +462,15 @@ def main():
     elapsed = time.perf_counter() - t0
     st = prob.stats()
     prob.set_timing(False)
+    # after the timed region: the spread of single frames, each run alone
+    # (synchronised) and timed on the host
+    frame_ms = []
+    for _ in range(args.steps):
+        t_f = time.perf_counter()
+        step()
+        prob.sync()
+        frame_ms.append(1e3 * (time.perf_counter() - t_f))
+    frame_ms.sort()
 
     ms_step = 1e3 * elapsed / args.steps
     updates = float(N) * K * iters
@@ -483,6 +498,9 @@ def main():
                    "stride": list(wl.stride), "K": K, "patches": N, "sampled_fraction": wl.rho,
                    "gibbs_iters_per_frame": iters, "parallelism": "single GPU"},
         "frames_per_s": args.steps / elapsed,
+        "frame_ms_alone": {"median": frame_ms[len(frame_ms) // 2], "min": frame_ms[0],
+                           "max": frame_ms[-1], "frames": len(frame_ms),
+                           "first_frame_cold": first_ms},
         "phase_ms_per_frame": {
             "index": st["ms_index"] / args.steps, "sweep": st["ms_sweep"] / args.steps,
             "dictionary": st["ms_dict"] / args.steps, "scalars": st["ms_scalars"] / args.steps,
