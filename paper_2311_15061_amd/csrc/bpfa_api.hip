@@ -123,23 +123,37 @@ DictPlan make_dict_plan(const Geom& g) {
   // bookkeeping and gather once per group, but a later group walks only the
   // lists' tails (list_groups_kernel), so they add little pair work.
   const long long whole = (long long)K * (K + 1) / 2 + K;
-  const long long fixed = (long long)(K + 1) * 4 + (long long)dict_sink_entries(K) * 8;
-  const long long group_room =
-      ((long long)kLdsBytes - fixed - (long long)kDictChunkTarget * kDictVisitBytes) / 8;
-  const long long budget = whole <= group_room ? whole : std::max<long long>((long long)K + 1, group_room);
+  // the groups are found for a room that leaves space for the diagonal / B
+  // copies of `reserve` rows; the copies then take the largest group's rows,
+  // and the grouping is redone with that reserve until it fits (twice at most
+  // for the sizes the library takes)
+  const int copies = dict_copies(K);
   int rg = 0;
-  pl.row0[0] = 0;
-  pl.ent0[0] = 0;
-  long long len = 0;
-  for (int k = 0; k < K; ++k) {
-    const long long add = (K - k) + 1;
-    if (len + add > budget && len > 0) {
-      ++rg;
-      pl.row0[rg] = k;
-      pl.ent0[rg] = (long long)k * K - (long long)k * (k - 1) / 2;
-      len = 0;
+  for (int reserve = 0;;) {
+    const long long fixed = (long long)(K + 1) * 4 + (long long)dict_sink_entries(K) * 8 +
+                            (long long)copies * 2 * reserve * 8;
+    const long long group_room =
+        ((long long)kLdsBytes - fixed - (long long)kDictChunkTarget * kDictVisitBytes) / 8;
+    const long long budget = whole <= group_room ? whole : std::max<long long>((long long)K + 1, group_room);
+    rg = 0;
+    pl.row0[0] = 0;
+    pl.ent0[0] = 0;
+    long long len = 0;
+    int rows = 0, rows_max = 0;
+    for (int k = 0; k < K; ++k) {
+      const long long add = (K - k) + 1;
+      if (len + add > budget && len > 0) {
+        ++rg;
+        pl.row0[rg] = k;
+        pl.ent0[rg] = (long long)k * K - (long long)k * (k - 1) / 2;
+        len = 0;
+        rows = 0;
+      }
+      len += add;
+      rows_max = std::max(rows_max, ++rows);
     }
-    len += add;
+    if (rows_max <= reserve || reserve >= K) break;
+    reserve = std::max(rows_max, reserve + 1);
   }
   pl.RG = rg + 1;
   pl.row0[pl.RG] = K;
@@ -151,7 +165,12 @@ DictPlan make_dict_plan(const Geom& g) {
   long long rec_max = 0;
   for (int r = 0; r < pl.RG; ++r)
     rec_max = std::max(rec_max, (pl.ent0[r + 1] - pl.ent0[r]) + (long long)(pl.row0[r + 1] - pl.row0[r]));
-  const long long room = (long long)kLdsBytes - (rec_max + dict_sink_entries(K)) * 8 - (long long)(K + 1) * 4;
+  pl.copies = dict_copies(K);
+  pl.copy_rows = 0;
+  for (int r = 0; r < pl.RG; ++r) pl.copy_rows = std::max(pl.copy_rows, pl.row0[r + 1] - pl.row0[r]);
+  const long long room = (long long)kLdsBytes -
+                         (rec_max + dict_sink_entries(K) + (long long)pl.copies * 2 * pl.copy_rows) * 8 -
+                         (long long)(K + 1) * 4;
   pl.chunk_visits = (int)std::max<long long>(
       kDictBlock, std::min<long long>(kDictBlock * kDictVpt, room / kDictVisitBytes / kDictBlock * kDictBlock));
   // chunk slots per (p, row group): the frame plan uses the first few of them,
@@ -745,7 +764,8 @@ bpfa_status bpfa_create(const bpfa_params* params, void* workspace, size_t ws_by
     const int sweep_per_cu = (int)std::max(1LL, std::min(2LL, lds_cu / (long long)L.sweep_lds));
     h->sweep_grid = (int)std::min<long long>((L.wave_cap + kSweepWaves - 1) / kSweepWaves,
                                              (long long)h->n_cu * sweep_per_cu);
-    const size_t dlds = dict_stats_lds(g.K, L.rec_stride, L.plan.chunk_visits);
+    const size_t dlds = dict_stats_lds(g.K, L.rec_stride, L.plan.copies * 2 * L.plan.copy_rows,
+                                       L.plan.chunk_visits);
     h->dict_slots = h->n_cu * (int)std::max(1LL, lds_cu / (long long)dlds);
   }
   if (workspace) {

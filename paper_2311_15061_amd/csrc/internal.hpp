@@ -148,26 +148,34 @@ struct Buffers {
 // Plan of the dictionary-statistics pass: row groups of the K x K triangle
 // that fit the LDS accumulator, and patch-visit chunks per (p, row group).
 struct DictPlan {
-  int RG = 1;                  // row groups (at most 46: K <= 1024, and a group holds >= 11.8k entries)
+  int RG = 1;                  // row groups (at most 48: K <= 1024, and a group holds >= 11.5k entries)
   int row0[65];                // row group r covers atoms [row0[r], row0[r+1])
   long long ent0[65];          // triangle entry offset of row0[r]
   int chunks = 1;
   int chunk_visits = 0;        // observed pixels per chunk (LDS visit records)
+  int copies = 1;              // copies of a group's diagonal and B accumulators (lane groups)
+  int copy_rows = 0;           // rows of the largest row group (each copy holds 2 x copy_rows)
   int xcd = 0;                 // chunks is a multiple of 8: map each chunk's blocks to one XCD
   long long rec_len_total = 0; // sum over row groups of (entries + rows)
   long long tri_entries = 0;   // K (K + 1) / 2
 };
 
 // bytes of LDS of the statistics kernel
-// statistics LDS: accumulators | sink region | K + 1 bins | chunk visit records.
-// The sink region holds one slot per lane and K spare slots: a term that
-// belongs to no accumulator of the block adds into (lane slot + column).
+// statistics LDS: accumulators | sink region | diagonal / B copies | K + 1
+// bins | chunk visit records.  The sink region holds one slot per lane and K
+// spare slots: a term that belongs to no accumulator of the block adds into
+// (lane slot + column).
 __host__ __device__ inline int dict_sink_entries(int K) { return kWave + K; }
+// lane groups with their own copy of the diagonal and B accumulators: a few
+// atoms are active in a third to a half of all patches, so the lanes of one
+// instruction meet on their diagonal and B entries (the LDS serialises
+// atomics to one address); K > 256 keeps one copy (its groups have few rows)
+__host__ __device__ inline int dict_copies(int K) { return K <= 256 ? 4 : 1; }
 // a chunk visit record: patch (int32), observed value (float), the list's
 // length from the block's row group on and its offset there (uint16 each)
 constexpr int kDictVisitBytes = 12;
-inline size_t dict_stats_lds(int K, long long rec_stride, int chunk_visits) {
-  return (size_t)(rec_stride + dict_sink_entries(K)) * 8 + (size_t)(K + 1) * 4 +
+inline size_t dict_stats_lds(int K, long long rec_stride, int copy_entries, int chunk_visits) {
+  return (size_t)(rec_stride + dict_sink_entries(K) + copy_entries) * 8 + (size_t)(K + 1) * 4 +
          (size_t)chunk_visits * kDictVisitBytes;
 }
 

@@ -52,7 +52,7 @@ struct VisitRow {
 // largest chunk (the LDS layout).  A frame uses the first dict_chunks slots of
 // dict_cv visits each (frame plan).
 struct DictPlanDev {
-  int RG, chunks, K, chunk_visits, xcd;
+  int RG, chunks, K, chunk_visits, xcd, copies, copy_rows;
   int row0[65];
   long long ent0[65];
   long long rec_stride;
@@ -99,7 +99,9 @@ __device__ __forceinline__ int wave_max_i(int v) {
 struct StatsRow {
   char* lds;
   unsigned sink;          // this lane's sink slot
+  unsigned copy;          // this lane's copy of the group's diagonal, then B, accumulators
   int r0, r1, e0, tw, E;  // group rows, its first triangle entry, 2K - 1, its entry count
+  int R;                  // rows per copy
   double sc, ysb;
   __device__ __forceinline__ bool in(int k) const { return k >= r0 && k < r1; }
   // entry (k, j) of row k, j >= k, sits at row_byte(k) + 8 j:
@@ -115,6 +117,17 @@ struct StatsRow {
   }
   __device__ __forceinline__ unsigned b_or_sink(bool in_group, int k) const {
     unsigned o = in_group ? b_byte(k) : sink;
+    asm volatile("" : "+v"(o));
+    return o;
+  }
+  // the lane group's copies of entry (k, k) and of B_p[k]
+  __device__ __forceinline__ unsigned diag_copy_or_sink(bool in_group, int k) const {
+    unsigned o = in_group ? copy + 8u * (unsigned)(k - r0) : sink;
+    asm volatile("" : "+v"(o));
+    return o;
+  }
+  __device__ __forceinline__ unsigned b_copy_or_sink(bool in_group, int k) const {
+    unsigned o = in_group ? copy + 8u * (unsigned)(R + k - r0) : sink;
     asm volatile("" : "+v"(o));
     return o;
   }
@@ -155,11 +168,14 @@ __device__ __forceinline__ void stats_pairs(const StatsRow& sr, const Stage& s) 
   for (int a = 0; a < NB; ++a) {
     const bool ina = sr.in(s.kk[a]);   // kk = -1 past n_a
     if (SKIP && __builtin_amdgcn_ballot_w64(ina) == 0) continue;
-    sr.add(sr.b_or_sink(ina, s.kk[a]), s.ww[a] * sr.ysb);
-    const unsigned rb = sr.row_or_sink(ina, s.kk[a]);
+    // B_p[k] and the diagonal (k, k) go to the lane group's copies; the
+    // pairs (k, j), j > k, to the shared rows
+    sr.add(sr.b_copy_or_sink(ina, s.kk[a]), s.ww[a] * sr.ysb);
     const double was = s.ww[a] * sr.sc;
+    sr.add(sr.diag_copy_or_sink(ina, s.kk[a]), was * s.ww[a]);
+    const unsigned rb = sr.row_or_sink(ina, s.kk[a]);
 #pragma unroll
-    for (int b = a; b < NB; ++b) sr.add(rb + s.col[b], was * s.ww[b]);
+    for (int b = a + 1; b < NB; ++b) sr.add(rb + s.col[b], was * s.ww[b]);
   }
 }
 
@@ -284,16 +300,22 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
   const int E = (int)(pl.ent0[rg + 1] - e0);
   const int rec = E + (r1 - r0);
   const int K = g.K;
-  int* bins = reinterpret_cast<int*>(acc + pl.rec_stride + dict_sink_entries(K)); // K + 1 counts, then starts
+  // copies of the group's diagonal and B accumulators, one per lane group
+  long long* cpy = acc + pl.rec_stride + dict_sink_entries(K);
+  const int ncopy = pl.copies * 2 * pl.copy_rows;
+  int* bins = reinterpret_cast<int*>(cpy + ncopy);   // K + 1 counts, then starts
   int* v_pat = bins + (K + 1);
   float* v_y = reinterpret_cast<float*>(v_pat + pl.chunk_visits);
   uint16_t* v_na = reinterpret_cast<uint16_t*>(v_y + pl.chunk_visits);
   uint16_t* v_off = v_na + pl.chunk_visits;
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
   for (int e = tid; e < rec; e += kDictBlock) acc[e] = 0;
+  for (int e = tid; e < ncopy; e += kDictBlock) cpy[e] = 0;
 
   const double sc = scal->scale_c, sb = scal->scale_b;
   const unsigned sink = (unsigned)((pl.rec_stride + lane) * 8);   // this lane's sink slot
+  const unsigned copy = (unsigned)((pl.rec_stride + dict_sink_entries(K) +
+                                    (long long)(lane / (kWave / pl.copies)) * 2 * pl.copy_rows) * 8);
   const int32_t* vs = vpatch + (size_t)p * g.Mtot;
   double x2 = 0.0;
 
@@ -407,8 +429,8 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
     const int pid = q[0].pid, na = q[0].na, wmax = q[0].wmax;
     const int2* L = list + (size_t)pid * K + q[0].off;
     const int lim = K - 1 - q[0].off;   // last index inside the patch's list row
-    const StatsRow sr{reinterpret_cast<char*>(acc), sink, r0, r1, (int)e0, 2 * K - 1, E, sc,
-                      q[0].y * sb};
+    const StatsRow sr{reinterpret_cast<char*>(acc), sink, copy, r0, r1, (int)e0, 2 * K - 1, E,
+                      pl.copy_rows, sc, q[0].y * sb};
     Stage s;
     stage_from(s, q[0].raw, min(na, kStatsCap));
     stats_stage<SKIP>(sr, s, wmax);
@@ -453,6 +475,18 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
     run = nxt;
   }
   __syncthreads();   // the visit records are rewritten by the next chunk
+  }
+  __syncthreads();
+  // the copies into the group's diagonal and B entries (each thread its rows)
+  for (int i = tid; i < r1 - r0; i += kDictBlock) {
+    long long dsum = 0, bsum = 0;
+    for (int cpi = 0; cpi < pl.copies; ++cpi) {
+      dsum += cpy[(size_t)cpi * 2 * pl.copy_rows + i];
+      bsum += cpy[(size_t)cpi * 2 * pl.copy_rows + pl.copy_rows + i];
+    }
+    const int k = r0 + i;
+    acc[(int)(tri_off(k, K) - e0)] += dsum;   // entry (k, k)
+    acc[E + i] += bsum;
   }
   __syncthreads();
   long long* out = dpart + (size_t)(prg * pl.chunks + c) * pl.rec_stride;
@@ -800,6 +834,8 @@ static DictPlanDev to_dev(const Geom& g, const DictPlan& plan) {
   d.chunk_visits = plan.chunk_visits;
   d.xcd = plan.xcd;
   d.K = g.K;
+  d.copies = plan.copies;
+  d.copy_rows = plan.copy_rows;
   long long stride = 0;
   for (int r = 0; r <= plan.RG; ++r) {
     d.row0[r] = plan.row0[r];
@@ -857,7 +893,7 @@ hipError_t launch_dict_stats(const Geom& g, const Buffers& b, const DictPlan& pl
   // leaves empty return at once)
   const int blocks = g.P * plan.RG * std::max(1, std::min(grid_chunks, plan.chunks));
   // the LDS holds visit records for the largest chunk the plan allows
-  const size_t lds = dict_stats_lds(g.K, d.rec_stride, plan.chunk_visits);
+  const size_t lds = dict_stats_lds(g.K, d.rec_stride, plan.copies * 2 * plan.copy_rows, plan.chunk_visits);
   const bool skip = plan.RG >= 2;
   hipError_t e = hipFuncSetAttribute(
       skip ? (const void*)dict_stats_kernel<true> : (const void*)dict_stats_kernel<false>,
