@@ -151,6 +151,8 @@ def test_sparse_code_only_parity():
 @pytest.mark.parametrize("shape,patch,stride,K,rho", [
     ((40, 36), (6, 5), (1, 1), 21, 0.2),          # ragged grid, odd K
     ((30, 30), (10, 10), (1, 1), 200, 0.15),      # several LDS tiles, two statistics row groups
+    ((28, 28), (10, 10), (1, 1), 160, 0.2),       # the smallest K with two statistics row groups
+    ((26, 26), (8, 8), (1, 1), 257, 0.2),         # one diagonal / B copy (K > 256), three row groups
     ((20, 18, 8), (4, 4, 2), (1, 1, 2), 24, 0.25),  # 3-D video patches with a time stride
     ((10, 9, 6, 5), (3, 3, 2, 2), (1, 1, 2, 1), 12, 0.3),  # 4-D patches spanning two frames
     ((24, 22, 3), (6, 6, 3), (1, 1, 1), 16, 0.3),  # full-depth patches (B_2 = M_2, e.g. RGB)
