@@ -258,7 +258,13 @@ bpfa_status bpfa_set_state_noalloc(bpfa_t h, const bpfa_state_view* view);
 /* Per-iteration statistics (synchronises). */
 bpfa_status bpfa_get_stats(bpfa_t h, bpfa_stats* stats);
 
-/* Turn per-phase HIP-event timing on (1) or off (0); resets the totals. */
+/* Turn per-phase HIP-event timing on (1) or off (0); resets the totals.
+ * Timing records six events per iteration on the handle's stream (created
+ * without a system-scope fence: they are read only after the stream is
+ * synchronised) and two per frame load and reconstruction; turning it on
+ * creates a pool of 3072 events for them, which the handle keeps and reuses.
+ * The durations are read at bpfa_get_stats (and, to bound the events held,
+ * at a frame's end once more than 2048 iterations are pending).  Synchronises. */
 bpfa_status bpfa_set_timing(bpfa_t h, int on);
 
 /* Wait for the handle's stream; ENUMERIC if a draw failed since the last check. */
