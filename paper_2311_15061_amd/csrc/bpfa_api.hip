@@ -161,7 +161,7 @@ DictPlan make_dict_plan(const Geom& g) {
   pl.tri_entries = pl.ent0[pl.RG];
   pl.rec_len_total = pl.tri_entries + K;
   // chunk of observed pixels per block: as many visit records as the LDS
-  // left over by the largest row group holds (a multiple of the block size)
+  // left over by the largest row group holds (a multiple of the wavefront)
   long long rec_max = 0;
   for (int r = 0; r < pl.RG; ++r)
     rec_max = std::max(rec_max, (pl.ent0[r + 1] - pl.ent0[r]) + (long long)(pl.row0[r + 1] - pl.row0[r]));
@@ -172,7 +172,7 @@ DictPlan make_dict_plan(const Geom& g) {
                          (rec_max + dict_sink_entries(K) + (long long)pl.copies * 2 * pl.copy_rows) * 8 -
                          (long long)(K + 1) * 4;
   pl.chunk_visits = (int)std::max<long long>(
-      kDictBlock, std::min<long long>(kDictBlock * kDictVpt, room / kDictVisitBytes / kDictBlock * kDictBlock));
+      kDictBlock, std::min<long long>(kDictBlock * kDictVpt, room / kDictVisitBytes / kWave * kWave));
   // chunk slots per (p, row group): the frame plan uses the first few of them,
   // chosen on the device from the frame's observed pixels
   const long long mt = g.Mtot;

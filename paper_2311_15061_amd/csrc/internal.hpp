@@ -15,8 +15,8 @@ constexpr int kSweepWaves = kSweepBlock / 64;
 constexpr int kSweepWavesPerSimd = 4;
 constexpr int kSlotAlign = 256;
 constexpr int kLdsTileBytes = 64 * 1024;
-constexpr int kDictBlock = 768;
-constexpr int kDictVpt = 8;       // visits per thread of one statistics chunk, held in registers
+constexpr int kDictBlock = 1024;
+constexpr int kDictVpt = 6;       // visits per thread of one statistics chunk, held in registers
 constexpr int kChainLdsMaxK = 128;  // largest K whose binary64 C_p (K x K) the chain stages in LDS
 constexpr int kLdsBytes = 160 * 1024 - 1024;   // per block, leaving room for static arrays
 constexpr int kDictChunkTarget = 4608; // visits per statistics chunk the row-group size leaves room for

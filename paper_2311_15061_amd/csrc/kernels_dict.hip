@@ -136,13 +136,16 @@ struct StatsRow {
   }
 };
 
-// A register stage of up to kStatsCap list entries: atoms (-1 past the
-// patch's n_a), weights (0 there) and column offsets (8 x atom; past n_a the
-// last valid atom's, a column every staged row holds since lists ascend).
+// A register stage of up to kStatsCap list entries: weights (0 past the
+// patch's n_a) and column offsets (8 x atom; past n_a the last valid atom's, a
+// column every staged row holds since lists ascend).  A row is live when its
+// weight is non-zero: a listed entry whose weight is exactly zero adds only
+// zeros, so sending its terms to the sink leaves every sum unchanged.
 struct Stage {
-  int kk[kStatsCap];
   unsigned col[kStatsCap];
   double ww[kStatsCap];
+  __device__ __forceinline__ int atom(int a) const { return (int)(col[a] >> 3); }
+  __device__ __forceinline__ bool live(int a) const { return ww[a] != 0.0; }
 };
 
 __device__ __forceinline__ void stage_from(Stage& s, const int2 (&raw)[kStatsCap], int nv) {
@@ -150,7 +153,6 @@ __device__ __forceinline__ void stage_from(Stage& s, const int2 (&raw)[kStatsCap
 #pragma unroll
   for (int a = 0; a < kStatsCap; ++a) {
     const bool in = a < nv;
-    s.kk[a] = in ? raw[a].x : -1;
     s.ww[a] = in ? (double)__int_as_float(raw[a].y) : 0.0;
     last = in ? 8u * (unsigned)raw[a].x : last;
     s.col[a] = last;
@@ -166,14 +168,15 @@ template <int NB, bool SKIP>
 __device__ __forceinline__ void stats_pairs(const StatsRow& sr, const Stage& s) {
 #pragma unroll
   for (int a = 0; a < NB; ++a) {
-    const bool ina = sr.in(s.kk[a]);   // kk = -1 past n_a
+    const int k = s.atom(a);
+    const bool ina = s.live(a) && sr.in(k);
     if (SKIP && __builtin_amdgcn_ballot_w64(ina) == 0) continue;
     // B_p[k] and the diagonal (k, k) go to the lane group's copies; the
     // pairs (k, j), j > k, to the shared rows
-    sr.add(sr.b_copy_or_sink(ina, s.kk[a]), s.ww[a] * sr.ysb);
+    sr.add(sr.b_copy_or_sink(ina, k), s.ww[a] * sr.ysb);
     const double was = s.ww[a] * sr.sc;
-    sr.add(sr.diag_copy_or_sink(ina, s.kk[a]), was * s.ww[a]);
-    const unsigned rb = sr.row_or_sink(ina, s.kk[a]);
+    sr.add(sr.diag_copy_or_sink(ina, k), was * s.ww[a]);
+    const unsigned rb = sr.row_or_sink(ina, k);
 #pragma unroll
     for (int b = a + 1; b < NB; ++b) sr.add(rb + s.col[b], was * s.ww[b]);
   }
@@ -209,7 +212,8 @@ __device__ __forceinline__ void stage_rows(const StatsRow& sr, const Stage& s,
                                            unsigned (&rb)[kStatsCap], double (&wsc)[kStatsCap]) {
 #pragma unroll
   for (int a = 0; a < kStatsCap; ++a) {
-    rb[a] = sr.row_or_sink(sr.in(s.kk[a]), s.kk[a]);
+    const int k = s.atom(a);
+    rb[a] = sr.row_or_sink(s.live(a) && sr.in(k), k);
     wsc[a] = s.ww[a] * sr.sc;
   }
 }

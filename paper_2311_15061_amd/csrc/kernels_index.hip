@@ -444,7 +444,7 @@ __global__ __launch_bounds__(1024) void frame_plan_kernel(Geom g, PlanArgs pa,
     }
     const int per = (nom + best - 1) / best;
     plan->dict_chunks = best;
-    plan->dict_cv = min(pa.dict_cv_max, max(kDictBlock, (per + kDictBlock - 1) / kDictBlock * kDictBlock));
+    plan->dict_cv = min(pa.dict_cv_max, max(kWave, (per + kWave - 1) / kWave * kWave));
     plan->dict_xcd = best % 8 == 0 ? 1 : 0;
   }
   __syncthreads();
