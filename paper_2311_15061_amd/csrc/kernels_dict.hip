@@ -82,11 +82,6 @@ __device__ __forceinline__ int visit_patch(const Geom& g, const int4 qc, const i
   return ok ? pidx : -1;
 }
 
-__device__ __forceinline__ int wave_max_i(int v) {
-  for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-  return v;
-}
-
 // Pair accumulation of one visit, in straight-line code.  Byte offsets into
 // the block's LDS: the group's triangle rows, its B entries, then the sink
 // region (one slot per lane followed by K spare slots).  A term whose row lies
@@ -157,6 +152,13 @@ __device__ __forceinline__ void stage_from(Stage& s, const int2 (&raw)[kStatsCap
     last = in ? 8u * (unsigned)raw[a].x : last;
     s.col[a] = last;
   }
+}
+
+// Holds the stage's values where this is called: an empty asm that reads and
+// writes them, with a memory clobber so that no later load moves above it.
+__device__ __forceinline__ void pin_stage(Stage& s) {
+#pragma unroll
+  for (int a = 0; a < kStatsCap; ++a) asm volatile("" : "+v"(s.col[a]), "+v"(s.ww[a]) : : "memory");
 }
 
 // SKIP: with several row groups a row no lane of the wave holds in this
@@ -329,27 +331,35 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
   for (int e = tid; e <= K; e += kDictBlock) bins[e] = 0;
   __syncthreads();
 
-  // pass 1: this thread's visits (at most kDictVpt) in registers; rank within its n_a bin
+  // pass 1: this thread's visits (at most kDictVpt) in registers; rank within its n_a bin.
+  // Every load is issued (indices clamped into the chunk and the patch range)
+  // and the result selected afterwards, so the loads of all visits are in
+  // flight together instead of each behind a branch and its own wait.
   int r_pat[kDictVpt], r_na[kDictVpt], r_off[kDictVpt], r_rank[kDictVpt];
   float r_y[kDictVpt];
 #pragma unroll
   for (int u = 0; u < kDictVpt; ++u) {
     const int v = v0 + tid + u * kDictBlock;
-    r_pat[u] = -1;
-    r_y[u] = 0.f;
-    if (v < v1) {
-      r_pat[u] = vs[v];
-      r_y[u] = omega_y[v];
-      // a mini-batch step counts only the visits of its batch's patches
-      if (n_batches > 1 && r_pat[u] >= 0 && r_pat[u] % n_batches != batch) r_pat[u] = -1;
-    }
+    const int vc = min(v, v1 - 1);   // v0 < v1: an observed pixel of the chunk
+    const int pat = vs[vc];
+    r_y[u] = omega_y[vc];
+    r_pat[u] = v < v1 ? pat : -1;
+  }
+  // a mini-batch step counts only the visits of its batch's patches
+  if (n_batches > 1) {
+#pragma unroll
+    for (int u = 0; u < kDictVpt; ++u)
+      if (r_pat[u] >= 0 && r_pat[u] % n_batches != batch) r_pat[u] = -1;
   }
 #pragma unroll
   for (int u = 0; u < kDictVpt; ++u) {
     // a later row group skips the list's entries below its first row (lists
     // ascend, and a pair (j, k), j <= k, belongs to row j's group)
-    r_off[u] = rg > 0 && r_pat[u] >= 0 ? goff[(size_t)r_pat[u] * (pl.RG - 1) + (rg - 1)] : 0;
-    r_na[u] = r_pat[u] >= 0 ? nact[r_pat[u]] - r_off[u] : 0;
+    const int pc = max(r_pat[u], 0);
+    const int off = rg > 0 ? (int)goff[(size_t)pc * (pl.RG - 1) + (rg - 1)] : 0;
+    const int n = nact[pc];
+    r_off[u] = r_pat[u] >= 0 ? off : 0;
+    r_na[u] = r_pat[u] >= 0 ? n - off : 0;
   }
 #pragma unroll
   for (int u = 0; u < kDictVpt; ++u) {
@@ -397,21 +407,28 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
   // the wavefronts finish the chunk nearly together (longest runs first).
   // A run's list rows are fetched while the run before it accumulates.
   const int nruns = (nvis + kWave - 1) / kWave;
+  // A run's visit records (a lane past the visits reads record 0 and keeps
+  // zeros) and the first entries of each lane's list row, up to the run's
+  // bound (a clamped index stays inside the patch's list row).
   auto fetch = [&](int run, VisitRow& f) {
     const int vi = nvis - kWave * (run + 1) + lane;
     const bool on = vi >= 0;
-    f.pid = on ? v_pat[vi] : 0;
-    f.na = on ? (int)v_na[vi] : 0;
-    f.off = on ? (int)v_off[vi] : 0;
-    f.y = on ? (double)v_y[vi] : 0.0;
-    f.wmax = __builtin_amdgcn_readfirstlane(wave_max_i(f.na));
+    const int vc = max(vi, 0);
+    const int pid = v_pat[vc], na = (int)v_na[vc], off = (int)v_off[vc];
+    const float y = v_y[vc];
+    f.pid = on ? pid : 0;
+    f.na = on ? na : 0;
+    f.off = on ? off : 0;
+    f.y = on ? (double)y : 0.0;
+    // visits ascend by length, so the run's longest list is its last lane's
+    // (a run's last lane always holds a visit)
+    f.wmax = __builtin_amdgcn_readlane(f.na, kWave - 1);
     const int2* L = list + (size_t)f.pid * K + f.off;
-    // the first entries up to the wave's bound, loads issued together (a
-    // clamped index stays inside the patch's list row)
+    const int lim = K - 1 - f.off;
 #pragma unroll
     for (int a = 0; a < kStatsCap; ++a) {
       f.raw[a] = make_int2(-1, 0);
-      if (a < f.wmax) f.raw[a] = L[min(a, K - 1 - f.off)];
+      if (a < f.wmax) f.raw[a] = L[min(a, lim)];
     }
   };
   auto clear = [&](VisitRow& f) {
@@ -428,6 +445,12 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
     int nxt = 0;
     if (lane == 0) nxt = atomicAdd(&s_next, 1);
     nxt = __builtin_amdgcn_readfirstlane(nxt);
+    // Stage this run's entries first (its rows were loaded one run ago), then
+    // issue the next run's loads: their number depends on that run's bound,
+    // so a use of this run's rows after them would wait for all of them.
+    Stage s;
+    stage_from(s, q[0].raw, min(q[0].na, kStatsCap));
+    pin_stage(s);
     clear(q[1]);
     if (nxt < nruns) fetch(nxt, q[1]);
     const int pid = q[0].pid, na = q[0].na, wmax = q[0].wmax;
@@ -435,8 +458,6 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
     const int lim = K - 1 - q[0].off;   // last index inside the patch's list row
     const StatsRow sr{reinterpret_cast<char*>(acc), sink, copy, r0, r1, (int)e0, 2 * K - 1, E,
                       pl.copy_rows, sc, q[0].y * sb};
-    Stage s;
-    stage_from(s, q[0].raw, min(na, kStatsCap));
     stats_stage<SKIP>(sr, s, wmax);
     if (wmax > kStatsCap) {
       // lists longer than the register stage (the wave's bound past
