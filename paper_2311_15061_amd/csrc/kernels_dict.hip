@@ -186,15 +186,23 @@ __device__ __forceinline__ void stats_pairs(const StatsRow& sr, const Stage& s) 
 
 template <bool SKIP>
 __device__ __forceinline__ void stats_stage(const StatsRow& sr, const Stage& s, int bound) {
-  switch ((min(bound, kStatsCap) + 1) >> 1) {
-    case 1: stats_pairs<2, SKIP>(sr, s); break;
-    case 2: stats_pairs<4, SKIP>(sr, s); break;
-    case 3: stats_pairs<6, SKIP>(sr, s); break;
-    case 4: stats_pairs<8, SKIP>(sr, s); break;
-    case 5: stats_pairs<10, SKIP>(sr, s); break;
-    case 6: stats_pairs<12, SKIP>(sr, s); break;
-    case 7: stats_pairs<14, SKIP>(sr, s); break;
-    case 8: stats_pairs<16, SKIP>(sr, s); break;
+  switch (min(bound, kStatsCap)) {
+    case 1: stats_pairs<1, SKIP>(sr, s); break;
+    case 2: stats_pairs<2, SKIP>(sr, s); break;
+    case 3: stats_pairs<3, SKIP>(sr, s); break;
+    case 4: stats_pairs<4, SKIP>(sr, s); break;
+    case 5: stats_pairs<5, SKIP>(sr, s); break;
+    case 6: stats_pairs<6, SKIP>(sr, s); break;
+    case 7: stats_pairs<7, SKIP>(sr, s); break;
+    case 8: stats_pairs<8, SKIP>(sr, s); break;
+    case 9: stats_pairs<9, SKIP>(sr, s); break;
+    case 10: stats_pairs<10, SKIP>(sr, s); break;
+    case 11: stats_pairs<11, SKIP>(sr, s); break;
+    case 12: stats_pairs<12, SKIP>(sr, s); break;
+    case 13: stats_pairs<13, SKIP>(sr, s); break;
+    case 14: stats_pairs<14, SKIP>(sr, s); break;
+    case 15: stats_pairs<15, SKIP>(sr, s); break;
+    case 16: stats_pairs<16, SKIP>(sr, s); break;
     default: break;
   }
 }
