@@ -818,6 +818,10 @@ __global__ __launch_bounds__(1024) void dict_chain_lds_kernel(
       const int a = min(k, j), b = max(k, j);
       v[u] = T[(a * (2 * K - a + 1) >> 1) + (b - a)];
     }
+    // the values are needed here, so the loads are not sunk into the
+    // conditional stores below (one round trip each)
+#pragma unroll
+    for (int u = 0; u < kExp; ++u) asm volatile("" : "+v"(v[u]));
     if (k0 < R) {
 #pragma unroll
       for (int u = 0; u < kExp; ++u) {
