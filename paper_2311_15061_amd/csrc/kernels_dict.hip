@@ -703,7 +703,6 @@ __device__ __forceinline__ void chain_run(const Geom& g, int p, int lane, const 
 #pragma unroll
     for (int m = 0; m < KPL; ++m)
       ring[u][m] = C[(size_t)min(u, K - 1) * K + min(lane + kWave * m, K - 1)];
-  bool bad = false;
 #pragma unroll
   for (int m = 0; m < KPL; ++m) {
     const int kend = min(K, kWave * (m + 1));
@@ -713,13 +712,11 @@ __device__ __forceinline__ void chain_run(const Geom& g, int p, int lane, const 
         const int k = kb + u;
         if (k < kend) {
           const int kl = k - kWave * m;
-          const double uk = readlane_d(ureg[m], kl);
-          const double dk = readlane_d(dreg[m], kl);
-          const double gk = readlane_d(greg[m], kl);
-          const double tk = readlane_d(treg[m], kl);
-          const double dn = fma(-gk, uk, tk);
-          bad = bad || !isfinite(dn);
-          const double delta = dn - dk;
+          // every lane forms t - g u from its own registers; lane kl's value is
+          // the draw of d_k, and only its change is broadcast (one readlane
+          // on the step-to-step path instead of four and their moves)
+          const double dn = fma(-greg[m], ureg[m], treg[m]);
+          const double delta = readlane_d(dn - dreg[m], kl);
 #pragma unroll
           for (int mm = 0; mm < KPL; ++mm) ureg[mm] = fma(ring[u][mm], delta, ureg[mm]);
           if (lane == kl) dreg[m] = dn;
@@ -734,12 +731,15 @@ __device__ __forceinline__ void chain_run(const Geom& g, int p, int lane, const 
       }
     }
   }
-  // new atoms' column p; residual sum of squares X2 - 2 d.B + d.(C d)
+  // new atoms' column p; residual sum of squares X2 - 2 d.B + d.(C d).
+  // Every draw stays in dreg, so a non-finite draw is found here.
   double quad = 0.0, lin = 0.0;
+  bool bad = false;
 #pragma unroll
   for (int m = 0; m < KPL; ++m) {
     const int j = lane + kWave * m;
     if (j < K) {
+      bad = bad || !isfinite(dreg[m]);
       D[(size_t)j * P + p] = (float)dreg[m];
       quad = fma(ureg[m], dreg[m], quad);
       lin = fma(breg[m], dreg[m], lin);
@@ -747,9 +747,10 @@ __device__ __forceinline__ void chain_run(const Geom& g, int p, int lane, const 
   }
   quad = wave_sum_d(quad);
   lin = wave_sum_d(lin);
+  const bool any_bad = __builtin_amdgcn_ballot_w64(bad) != 0;
   if (lane == 0) {
     sumr2_p[p] = x2 - 2.0 * lin + quad;
-    if (bad) atomicOr(&scal->status, 1);
+    if (any_bad) atomicOr(&scal->status, 1);
   }
 }
 
