@@ -765,76 +765,77 @@ __global__ __launch_bounds__(kWave) void dict_chain_kernel(
                      diag + (size_t)p * K, x2p[p], scal, D, sumr2_p, scale, key0, key1, stream);
 }
 
-// K <= kChainLdsMaxK (one row group): the chunk partials are summed into the
-// packed upper triangle of C_p (binary64, coalesced), B_p and X2_p.
-__global__ __launch_bounds__(256) void dict_reduce_tri_kernel(
-    Geom g, DictPlanDev pl, const FramePlan* __restrict__ fplan, const long long* __restrict__ dpart,
-    const double* __restrict__ dx2, const DevScalars* __restrict__ scal, double* __restrict__ Ctri,
-    double* __restrict__ Bvec, double* __restrict__ x2p) {
-  const int K = g.K, E = K * (K + 1) / 2;
-  const int cc = fplan->dict_chunks;
-  const int per_p = (E + K + 255) / 256;
-  const int p = blockIdx.x / per_p;
-  const int e = (blockIdx.x % per_p) * 256 + threadIdx.x;
-  const long long* rec = dpart + (size_t)p * pl.chunks * pl.rec_stride;
-  if (e < E + K) {
-    long long sum = 0;
-    for (int c = 0; c < cc; ++c) sum += rec[(size_t)c * pl.rec_stride + e];
-    if (e < E) Ctri[(size_t)p * E + e] = (double)sum * (1.0 / scal->scale_c);
-    else Bvec[(size_t)p * K + (e - E)] = (double)sum / scal->scale_b;
-  }
-  if (e == 0) {
-    double x2 = 0.0;
-    for (int c = 0; c < cc; ++c) x2 += dx2[p * pl.chunks + c];
-    x2p[p] = x2;
-  }
-}
-
-// The chain with C_p staged in LDS.  One block per p expands the packed
-// triangle into the symmetric K x K matrix in LDS, forms u = C_p d (old d) with
+// The chain with C_p staged in LDS.  One block per p sums the chunk partials
+// of the packed triangle into the symmetric K x K matrix in LDS, forms u = C_p d (old d) with
 // all its threads (partial sums over 1024 / K slices of k, added in a fixed
 // order), then wavefront 0 runs the chain reading rows from LDS.
 template <int KPL>
 __global__ __launch_bounds__(1024) void dict_chain_lds_kernel(
-    Geom g, const double* __restrict__ Ctri, const double* __restrict__ Bvec,
-    const double* __restrict__ x2p, DevScalars* scal, float* __restrict__ D,
+    Geom g, DictPlanDev pl, const FramePlan* __restrict__ fplan, const long long* __restrict__ dpart,
+    const double* __restrict__ dx2, DevScalars* scal, float* __restrict__ D,
     double* __restrict__ sumr2_p, double scale, uint32_t key0, uint32_t key1, uint32_t stream) {
   extern __shared__ double Cs[];                 // K x K, then the u partials
   __shared__ double s_B[kChainLdsMaxK], s_diag[kChainLdsMaxK], s_d[kChainLdsMaxK],
       s_u[kChainLdsMaxK], s_n[kChainLdsMaxK];
+  __shared__ double s_x2;
   const int p = blockIdx.x, K = g.K, P = g.P, tid = threadIdx.x;
   const int E = K * (K + 1) / 2;
-  const double* T = Ctri + (size_t)p * E;
-  // the symmetric expansion: thread (row k0 + R u, column j) with R = 1024 / K
-  // rows per step (one division per thread, 32-bit offsets: K <= 128), all
-  // of a thread's loads in flight before their stores (a load-store loop
-  // waits out one memory latency per element)
-  constexpr int kExp = 16;   // rows per thread: K / (1024 / K) <= 16 for K <= 128
+  // The statistics of position p: its chunk partials (one row group: the
+  // packed upper triangle of C_p, then B_p) summed over the frame's chunks,
+  // each entry loaded once (coalesced, two chunks in flight), scaled as the
+  // fixed point was, and the triangle written into both halves of the
+  // symmetric matrix in LDS.
+  constexpr int kRedPT = 9;   // ceil((K (K + 1) / 2 + K) / 1024) for K <= 128
   {
-    const int R = 1024 / K, j = tid % K, k0 = tid / K;
-    double v[kExp];
+    const int cc = fplan->dict_chunks;
+    const long long* rec = dpart + (size_t)p * pl.chunks * pl.rec_stride;
+    long long v[kRedPT];
 #pragma unroll
-    for (int u = 0; u < kExp; ++u) {
-      const int k = min(k0 + R * u, K - 1);        // clamped: stays in the triangle
-      const int a = min(k, j), b = max(k, j);
-      v[u] = T[(a * (2 * K - a + 1) >> 1) + (b - a)];
+    for (int i = 0; i < kRedPT; ++i) v[i] = 0;
+    int c = 0;
+    for (; c + 1 < cc; c += 2) {
+      long long t0[kRedPT], t1[kRedPT];
+#pragma unroll
+      for (int i = 0; i < kRedPT; ++i) {
+        const int e = min(tid + 1024 * i, E + K - 1);
+        t0[i] = rec[(size_t)c * pl.rec_stride + e];
+        t1[i] = rec[(size_t)(c + 1) * pl.rec_stride + e];
+      }
+#pragma unroll
+      for (int i = 0; i < kRedPT; ++i) v[i] += t0[i] + t1[i];
     }
-    // the values are needed here, so the loads are not sunk into the
-    // conditional stores below (one round trip each)
+    if (c < cc) {
 #pragma unroll
-    for (int u = 0; u < kExp; ++u) asm volatile("" : "+v"(v[u]));
-    if (k0 < R) {
+      for (int i = 0; i < kRedPT; ++i)
+        v[i] += rec[(size_t)c * pl.rec_stride + min(tid + 1024 * i, E + K - 1)];
+    }
+    const double inv_c = 1.0 / scal->scale_c, sbs = scal->scale_b;
 #pragma unroll
-      for (int u = 0; u < kExp; ++u) {
-        const int k = k0 + R * u;
-        if (k < K) Cs[k * K + j] = v[u];
+    for (int i = 0; i < kRedPT; ++i) {
+      const int e = tid + 1024 * i;
+      if (e < E) {
+        // row a of entry e: rows a = K - 1, K - 2, ... hold 1, 2, ... entries
+        // from the end, so q = K - 1 - a is the triangular root of E - 1 - e
+        const int r = E - 1 - e;
+        int q = (int)((sqrtf(8.f * (float)r + 1.f) - 1.f) * 0.5f);
+        if (q * (q + 1) / 2 > r) --q;
+        if ((q + 1) * (q + 2) / 2 <= r) ++q;
+        const int a = K - 1 - q;
+        const int bcol = a + (e - (a * K - a * (a - 1) / 2));
+        const double x = (double)v[i] * inv_c;
+        Cs[a * K + bcol] = x;
+        Cs[bcol * K + a] = x;
+      } else if (e < E + K) {
+        s_B[e - E] = (double)v[i] / sbs;
       }
     }
+    if (tid == 0) {
+      double x2 = 0.0;
+      for (int cq = 0; cq < cc; ++cq) x2 += dx2[p * pl.chunks + cq];
+      s_x2 = x2;
+    }
   }
-  for (int k = tid; k < K; k += 1024) {
-    s_B[k] = Bvec[(size_t)p * K + k];
-    s_d[k] = (double)D[(size_t)k * P + p];
-  }
+  for (int k = tid; k < K; k += 1024) s_d[k] = (double)D[(size_t)k * P + p];
   __syncthreads();
   for (int k = tid; k < K; k += 1024) s_diag[k] = Cs[k * K + k];
   // the chain's normals, drawn by the wavefronts after the first while the
@@ -861,7 +862,7 @@ __global__ __launch_bounds__(1024) void dict_chain_lds_kernel(
   if (tid < kWave)
     // 8 row loads in flight: the LDS counter holds at most 15 outstanding,
     // so a deeper ring makes every step wait for all of them
-    chain_run<KPL, 8 / KPL>(g, p, tid, Cs, s_B, s_diag, x2p[p], scal, D, sumr2_p, scale, key0, key1,
+    chain_run<KPL, 8 / KPL>(g, p, tid, Cs, s_B, s_diag, s_x2, scal, D, sumr2_p, scale, key0, key1,
                             stream, s_u, s_n);
 }
 
@@ -982,25 +983,19 @@ hipError_t launch_dict_reduce_chain_lds(const Geom& g, const Buffers& b, const D
                                         uint32_t stream, hipStream_t st) {
   if (g.K > kChainLdsMaxK || plan.RG != 1) return hipErrorInvalidValue;
   const DictPlanDev d = to_dev(g, plan);
-  const int E = g.K * (g.K + 1) / 2;
-  const int per_p = (E + g.K + 255) / 256;
-  // the packed triangles go where the full matrices would (P x K x K >= P x E)
-  dict_reduce_tri_kernel<<<g.P * per_p, 256, 0, st>>>(g, d, b.plan, b.dpart, b.dx2, b.scal, b.Cfull,
-                                                       b.Bvec, b.x2p);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
   const size_t lds = dict_chain_lds_bytes(g.K);
   if (g.K <= kWave) {
     e = hipFuncSetAttribute((const void*)dict_chain_lds_kernel<1>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    dict_chain_lds_kernel<1><<<g.P, 1024, lds, st>>>(g, b.Cfull, b.Bvec, b.x2p, b.scal, b.D,
+    dict_chain_lds_kernel<1><<<g.P, 1024, lds, st>>>(g, d, b.plan, b.dpart, b.dx2, b.scal, b.D,
                                                      b.sumr2_p, scale, key0, key1, stream);
   } else {
     e = hipFuncSetAttribute((const void*)dict_chain_lds_kernel<2>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    dict_chain_lds_kernel<2><<<g.P, 1024, lds, st>>>(g, b.Cfull, b.Bvec, b.x2p, b.scal, b.D,
+    dict_chain_lds_kernel<2><<<g.P, 1024, lds, st>>>(g, d, b.plan, b.dpart, b.dx2, b.scal, b.D,
                                                      b.sumr2_p, scale, key0, key1, stream);
   }
   return hipGetLastError();
