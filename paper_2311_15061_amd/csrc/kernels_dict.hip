@@ -542,6 +542,24 @@ __global__ __launch_bounds__(kDictBlock) void dict_stats_kernel(
 // whole rows (a write of C_p[j][k] per entry strides by K); the diagonal
 // tiles also write diag and B_p, the first one X2_p.
 constexpr int kRedTile = 32;
+// the sum of n int64 values spaced `stride` apart, eight loads in flight (a
+// loop that adds each load before issuing the next waits out one memory
+// latency per value); integer adds are exact in any order
+__device__ __forceinline__ long long sum_strided(const long long* __restrict__ x, size_t stride,
+                                                 int n) {
+  long long s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int c = 0;
+  for (; c + 8 <= n; c += 8) {
+    long long t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = x[(size_t)(c + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += t[u];
+  }
+  for (; c < n; ++c) s[0] += x[(size_t)c * stride];
+  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
 __global__ __launch_bounds__(256) void dict_reduce_kernel(
     Geom g, DictPlanDev pl, const FramePlan* __restrict__ fplan, const long long* __restrict__ dpart,
     const double* __restrict__ dx2, const DevScalars* __restrict__ scal, double* __restrict__ Cfull,
@@ -569,8 +587,7 @@ __global__ __launch_bounds__(256) void dict_reduce_kernel(
       while (rg + 1 < pl.RG && pl.row0[rg + 1] <= k) ++rg;
       const long long* rec = dpart + (size_t)(p * pl.RG + rg) * pl.chunks * pl.rec_stride;
       const long long ek = tri_off(k, K) - pl.ent0[rg] - k;
-      long long sum = 0;
-      for (int c = 0; c < cc; ++c) sum += rec[(size_t)c * pl.rec_stride + ek + j];
+      const long long sum = sum_strided(rec + ek + j, (size_t)pl.rec_stride, cc);
       v = (double)sum * inv_c;
       C[(size_t)k * K + j] = v;
       if (j == k) diag[(size_t)p * K + k] = v;
@@ -589,8 +606,7 @@ __global__ __launch_bounds__(256) void dict_reduce_kernel(
       while (rg + 1 < pl.RG && pl.row0[rg + 1] <= k) ++rg;
       const long long* rec = dpart + (size_t)(p * pl.RG + rg) * pl.chunks * pl.rec_stride;
       const int E = (int)(pl.ent0[rg + 1] - pl.ent0[rg]);
-      long long sum = 0;
-      for (int c = 0; c < cc; ++c) sum += rec[(size_t)c * pl.rec_stride + E + (k - pl.row0[rg])];
+      const long long sum = sum_strided(rec + E + (k - pl.row0[rg]), (size_t)pl.rec_stride, cc);
       Bvec[(size_t)p * K + k] = (double)sum / scal->scale_b;
     }
     if (ti == 0 && threadIdx.x == 0) {
